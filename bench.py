@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: convolved TOD samples/s at lmax 512, kmax 100 on one MI355X.
+
+One step is the whole hot path on one batch of synthetic input already
+resident in HBM: map synthesis from (a_lm, b_lk) (ring sums by Wigner-d
+recursion, theta upsampling, phi synthesis) and the interpolation + k-sum at
+every pointing of a 1e7-sample synthetic scan.  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--precision f64maps_f32gather|fp64]
+
+Per-kernel durations come from HIP events the library records on its stream
+around each launch during the timed steps; the roofline object uses the
+dominant kernel.  The CPU baseline is the oracle (direct sum of Eq. 2) timed on
+a bounded random sample of the same pointings; its outputs also give the GPU
+result's error.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "conv TOD samples/s, lmax512 kmax100, mixed vs FP64 at 1e-6 rel err"
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}  # MI355X published peaks
+
+
+def ring_dvalues(L: int, K: int, nring: int) -> int:
+    """Number of Wigner-d values the ring-sum kernel evaluates (l >= max(m, k), m, k >= 0)."""
+    tot = 0
+    for k in range(K + 1):
+        for m in range(L + 1):
+            tot += max(0, L - max(m, k) + 1)
+    return tot * nring
+
+
+def stage_model(info: dict, n: int, prec: int):
+    """Algorithmic work per launch of each kernel: (bound, units, unit_name, peak)."""
+    L, K = info["lmax"], info["kmax"]
+    nm = 2 * L + 1
+    nr, rows, cols, nc, Wd = info["n_rings"], info["map_rows"], info["map_cols"], info["n_comp"], info["W"]
+    esz = 8 if prec == 0 else 4
+    dv = ring_dvalues(L, K, nr)
+    return {
+        # 3 FMA recursion + 4 FMA contraction (both signs of m) per d value
+        "ring_sums": ("alu", 14.0 * dv, "TFLOP/s", PEAK["fp64"]),
+        # read F, write the upsampled spectra
+        "theta_upsample": ("hbm", 16.0 * (K + 1) * nm * (nr + rows), "GB/s", PEAK["hbm"]),
+        # read the spectra, write the real components of the maps
+        "phi_synthesis": ("hbm", 16.0 * (K + 1) * rows * nm + esz * rows * cols * nc, "GB/s", PEAK["hbm"]),
+        # one FMA per (tap, component) per sample
+        "gather": ("alu", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"] if prec == 0 else PEAK["fp32"]),
+    }
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2201_03478_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they match this source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        ent = rec.get(workload, {}).get(stage)
+        if ent and ent.get("source_hash") == kernel_source_hash():
+            return ent["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def run_form(torch, api, dev, a, b, ptg, L, K, precision, width, steps, warmup):
+    plan = api.Plan(L, K, precision, kernel_width=width)
+    n = ptg.shape[0]
+    tod = torch.empty(n, dtype=plan.tod_dtype, device=dev)
+
+    def step():
+        plan.set_sky_beam(a, b)
+        plan.interpolate(ptg, out=tod)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    plan.stage_times()  # clear
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stages = plan.stage_times()
+    plan.enable_timing(False)
+    return plan, tod, ms, stages
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="f64maps_f32gather", choices=["f64maps_f32gather", "fp64"])
+    ap.add_argument("--width", type=int, default=8, help="interpolation kernel width W (8 meets 1e-6)")
+    ap.add_argument("--samples", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 4 per host thread)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2201_03478_amd import api
+
+    dev = torch.device("cuda", 0)
+    cfg = W.CONFIGS[2]
+    L, K, n = cfg["lmax"], cfg["kmax"], args.samples
+    a_np = W.sky_alm(L, W.config_seed(2, 1))
+    b_np = W.beam_alm(L, K, W.config_seed(2, 2), kind="sidelobe")
+    a = torch.from_numpy(a_np).to(dev)
+    b = torch.from_numpy(b_np).to(dev)
+    ptg = W.scan_pointings(n, device=dev)
+    torch.cuda.synchronize()
+    print("bench: inputs ready (lmax %d kmax %d n %d)" % (L, K, n), file=sys.stderr, flush=True)
+
+    plan, tod, ms, stages = run_form(torch, api, dev, a, b, ptg, L, K, args.precision, args.width,
+                                     args.steps, args.warmup)
+    info = plan.info()
+    prec = info["precision"]
+    print("bench: main form %.3f ms/step" % ms, file=sys.stderr, flush=True)
+
+    model = stage_model(info, n, prec)
+    per_launch = {s: (t / c if c else 0.0) for s, (t, c) in stages.items()}
+    dom = max(per_launch, key=per_launch.get)
+    bound, units, unit, peak = model[dom]
+    achieved = units / (per_launch[dom] * 1e-3)
+    workload_name = "sidelobe-lmax512-kmax100-scan1e7"
+    traffic = measured_traffic(dom, workload_name)
+    roofline = {
+        "kernel": dom,
+        "bound": bound,
+        "achieved": achieved / 1e12 if unit == "TFLOP/s" else achieved / 1e9,
+        "peak": peak / 1e12 if unit == "TFLOP/s" else peak / 1e9,
+        "unit": unit,
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "avg_launch_ms": per_launch[dom],
+        "algorithmic_per_launch": units,
+    }
+
+    result = {
+        "metric": METRIC,
+        "value": n / (ms * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": workload_name,
+            "lmax": L, "kmax": K, "n_samples": n,
+            "precision": args.precision, "W": info["W"],
+            "grid": [info["map_rows"], info["map_cols"], info["n_comp"]],
+        },
+        "stages_ms_per_step": {s: t / args.steps for s, (t, c) in stages.items()},
+        "roofline": roofline,
+    }
+
+    # oracle on a bounded random sample: CPU baseline and the error of this run
+    sel = np.sort(np.random.default_rng(W.config_seed(2, 6)).choice(n, 4096, replace=False))
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        m = args.cpu_sample or 4 * threads
+        idx = sel[:m]
+        sub = ptg[torch.as_tensor(idx, device=dev)].cpu().numpy()
+        got = tod[torch.as_tensor(idx, device=dev)].double().cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.convolve(a_np, b_np, L, K, sub, nthreads=threads)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": m / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded random samples of the 1e7-sample scan, direct sum of Eq. 2 in long double" % m,
+        }
+        result["rel_err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print("bench: oracle %d samples in %.1f s, rel err %.2e" % (m, dt, result["rel_err_vs_oracle"]),
+              file=sys.stderr, flush=True)
+        ref_sub, idx_sub = ref, idx
+    del plan, tod
+
+    if not args.no_fp64_form and args.precision != "fp64":
+        p64, tod64, ms64, st64 = run_form(torch, api, dev, a, b, ptg, L, K, "fp64", args.width,
+                                          max(1, args.steps // 2), 1)
+        form = {"precision": "fp64", "W": p64.info()["W"], "ms_per_step": ms64, "value": n / (ms64 * 1e-3),
+                "stages_ms_per_step": {s: t / max(1, args.steps // 2) for s, (t, c) in st64.items()}}
+        if not args.no_cpu_baseline:
+            got64 = tod64[torch.as_tensor(idx_sub, device=dev)].cpu().numpy()
+            form["rel_err_vs_oracle"] = float(np.linalg.norm(got64 - ref_sub) / np.linalg.norm(ref_sub))
+        result["fp64_form"] = form
+        result["speedup_vs_fp64_form"] = ms64 / ms
+        del p64, tod64
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/*
+ * sidelobe.h -- C ABI of the MI355X (gfx950) spin-harmonic total convolution.
+ *
+ * The library evaluates the total convolution of a sky and a beam
+ * (Galloway et al. 2022, "BeyondPlanck VIII", Sec. 2.1, Eqs. 1-2):
+ *
+ *   c(theta, phi, psi) = sum_{l,m,k} a_lm conj(b_lk) [D^l_mk(phi, theta, psi)]*
+ *                      = sum_{l,m,k} a_lm conj(b_lk) e^{i m phi} d^l_mk(theta) e^{i k psi},
+ *
+ * for a real sky a_lm (l <= lmax) and a real beam b_lk truncated at |k| <= kmax,
+ * by the two-step method of Sec. 2.1: one spin-k transform per beam order k
+ * (Eqs. 7 and 9) gives the component maps T_k(theta, phi); the +-k pairs
+ * combine as 2[cos k psi Re T_k - sin k psi Im T_k] (Eq. 8).  Here the maps
+ * are synthesised on an oversampled equiangular grid (Wigner-d recursion over
+ * l, per-m ring contraction, ring FFTs) and the signal is interpolated at each
+ * pointing with an exponential-of-semicircle kernel, the k-sum done per sample
+ * (the finite-resolution cube plus interpolation described at the end of
+ * Sec. 2.1).
+ *
+ * Conventions
+ *   D^l_mk(a, b, g) = e^{-i m a} d^l_mk(b) e^{-i k g}, d the standard
+ *   (Condon-Shortley compatible) small d-matrix; the beam is defined pointing
+ *   at the north pole and is placed by the active rotation
+ *   R = R_z(phi) R_y(theta) R_z(psi).
+ *
+ * Layouts (all caller buffers are DEVICE memory, owned by the caller)
+ *   alm   complex128 (re, im interleaved), m-major triangular:
+ *         index(l, m) = m (2 lmax + 1 - m) / 2 + l,  0 <= m <= l <= lmax.
+ *         Im(a_l0) is ignored (real sky).
+ *   blm   complex128, same scheme with m -> k and k <= kmax:
+ *         index(l, k) = k (2 lmax + 1 - k) / 2 + l,  0 <= k <= min(l, kmax);
+ *         (kmax + 1)(lmax + 1) - kmax (kmax + 1)/2 entries.  Im(b_l0) ignored.
+ *         Negative orders follow from the real-field symmetry (Eq. 6).
+ *   ptg   float64 [n][3] = (theta, phi, psi) in radians, theta in [0, pi];
+ *         phi and psi are reduced modulo 2 pi.
+ *   tod   float64 [n] for SC_FP64 plans, float32 [n] otherwise.
+ *
+ * Streams, ordering, threads
+ *   Every call enqueues work on the plan's HIP stream and returns without
+ *   synchronising the device.  A plan is not thread-safe: use one plan per
+ *   stream.  Inputs must stay valid until the stream reaches the work.
+ *
+ * Errors
+ *   Every entry point returns SC_OK or a negative code and never aborts or
+ *   throws.  sc_last_error() returns a message for the calling thread's last
+ *   failure.  Invalid arguments (negative sizes, kmax > lmax, null pointers,
+ *   host pointers where device memory is required, misaligned buffers) give
+ *   SC_EINVAL without touching the device; allocation failure gives
+ *   SC_ENOMEM; a failed HIP call gives SC_EHIP; calls in the wrong order
+ *   (interpolating before maps exist) give SC_ESTATE.  n = 0 is a valid no-op.
+ */
+#ifndef SIDELOBE_H
+#define SIDELOBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sc_plan sc_plan;
+
+enum sc_status {
+    SC_OK = 0,
+    SC_EINVAL = -1,
+    SC_ENOMEM = -2,
+    SC_EHIP = -3,
+    SC_ESTATE = -4
+};
+
+/* Arithmetic of a plan. */
+enum sc_precision {
+    /* FP64 recursion, transforms, maps, interpolation and k-sum; float64 TOD. */
+    SC_FP64 = 0,
+    /* FP64 recursion and transforms; maps stored in FP32; FP32 interpolation
+       and k-sum (pointing reduction and psi reduction stay FP64); float32 TOD. */
+    SC_F64MAPS_F32GATHER = 1
+};
+
+/*
+ * Create a plan for one (lmax, kmax, precision).
+ *   lmax          >= 0, band limit of sky and beam.
+ *   kmax          0 <= kmax <= lmax, beam azimuthal truncation (kmax = 0 is the
+ *                 axisymmetric case, a spin-0 transform only; Sec. 2.1).
+ *   precision     an sc_precision value.
+ *   kernel_width  interpolation kernel width W in grid cells (even, 4..16), or
+ *                 0 for the default (8 for SC_F64MAPS_F32GATHER, 14 for SC_FP64).
+ *   stream        hipStream_t to enqueue on (NULL = the null stream).
+ * The plan allocates all of its device workspace here (maps, transform
+ * buffers, tables) and fills its constant tables on the stream.
+ */
+int sc_plan_create(sc_plan **plan, int lmax, int kmax, int precision, int kernel_width, void *stream);
+
+/* Release a plan and its workspace (synchronises its stream first). NULL is a no-op. */
+int sc_plan_destroy(sc_plan *plan);
+
+/* Change the stream a plan enqueues on. */
+int sc_plan_set_stream(sc_plan *plan, void *stream);
+
+/*
+ * Plan geometry, written to out[0 .. nout-1] in this order:
+ *   0 lmax, 1 kmax, 2 precision, 3 W, 4 n_rings (theta rings of the
+ *   recursion), 5 n_fft_theta (2 n_rings), 6 n_theta_fine (oversampled
+ *   full-circle theta grid), 7 n_phi (oversampled phi grid), 8 map_rows,
+ *   9 map_cols, 10 n_comp (2 kmax + 1), 11 n_comp_padded,
+ *   12 workspace bytes.
+ * Returns the number of values available (13).
+ */
+int sc_plan_info(const sc_plan *plan, int64_t *out, int nout);
+
+/*
+ * Synthesise the component maps for a sky and a beam (the spin transforms of
+ * Eq. 9, one per k = 0..kmax; Eq. 7 reordered with the k sum outside).
+ * alm, blm: device complex128 arrays in the layouts above.  The maps stay
+ * resident in the plan until the next call.
+ */
+int sc_set_sky_beam(sc_plan *plan, const double *alm, const double *blm);
+
+/*
+ * Evaluate the convolution at n pointings from the plan's maps: interpolate
+ * every component at (theta, phi) and sum the cos k psi / sin k psi terms
+ * (Eq. 8).  ptg: device float64 [n][3]; tod: device float64/float32 [n].
+ */
+int sc_interpolate(sc_plan *plan, const double *ptg, int64_t n, void *tod);
+
+/*
+ * One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod: creates (or
+ * reuses a cached) plan for (lmax, kmax, precision, default W) on the stream,
+ * synthesises the maps and interpolates.  Same layouts as above.
+ */
+int sc_convolve(const double *alm, const double *blm, int lmax, int kmax,
+                const double *ptg, int64_t n, void *tod, int precision, void *stream);
+
+/*
+ * Device-side numerical details for tests: copies internal stage buffers to
+ * the caller's device memory.  which = 0: ring sums F (complex128
+ * [kmax+1][2 lmax+1][n_rings], F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j),
+ * theta_j = (j + 1/2) pi / n_rings); which = 1: the component maps as stored
+ * (map_rows x map_cols x n_comp_padded, FP64 or FP32 by precision).
+ * Returns the number of bytes copied, or a negative code.
+ */
+int64_t sc_debug_copy_stage(sc_plan *plan, int which, void *dst, int64_t capacity_bytes);
+
+/*
+ * Per-kernel timing.  With timing enabled the plan records a pair of HIP events
+ * on its stream around every kernel launch.  sc_plan_stage_times waits for
+ * the recorded events, adds each launch's duration to its stage total, writes
+ * ms[s] (total milliseconds) and launches[s] for the first nstage stages, and
+ * clears the records.  Stages: 0 ring sums (recursion + contraction),
+ * 1 theta upsampling, 2 phi synthesis, 3 interpolation + k-sum.
+ * Returns the number of stages (4).
+ */
+int sc_plan_enable_timing(sc_plan *plan, int enable);
+int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage);
+
+/* Human-readable text for a status code. */
+const char *sc_strerror(int code);
+
+/* Message describing the calling thread's last error (empty if none). */
+const char *sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIDELOBE_H */

@@ -1,0 +1,147 @@
+"""Python API over the C ABI: same names as the C entry points.
+
+Tensors are torch tensors on the GPU (torch provides device memory and the
+stream); the library does all of the arithmetic.  Layouts are those of
+include/sidelobe.h: alm/blm complex128 m-major triangular, ptg float64 [n, 3]
+(theta, phi, psi), tod float64 (SC_FP64) or float32.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as N
+
+PRECISIONS = {"fp64": N.SC_FP64, "f64maps_f32gather": N.SC_F64MAPS_F32GATHER}
+INFO_KEYS = ("lmax", "kmax", "precision", "W", "n_rings", "n_fft_theta", "n_theta_fine", "n_phi",
+             "map_rows", "map_cols", "n_comp", "n_comp_padded", "workspace_bytes")
+
+
+def n_alm(lmax: int, mmax: int | None = None) -> int:
+    mmax = lmax if mmax is None else mmax
+    return (mmax + 1) * (lmax + 1) - mmax * (mmax + 1) // 2
+
+
+def _prec(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+class Plan:
+    """sc_plan: geometry, workspace and resident maps for one (lmax, kmax, precision)."""
+
+    def __init__(self, lmax: int, kmax: int, precision="f64maps_f32gather", kernel_width: int = 0,
+                 stream=None):
+        lib = N.load()
+        self._lib = lib
+        self._p = ctypes.c_void_p()
+        N.check(lib.sc_plan_create(ctypes.byref(self._p), int(lmax), int(kmax), _prec(precision),
+                                   int(kernel_width), ctypes.c_void_p(_stream_handle(stream))),
+                "sc_plan_create")
+        self.lmax, self.kmax = int(lmax), int(kmax)
+        self.precision = _prec(precision)
+        self.tod_dtype = torch.float64 if self.precision == N.SC_FP64 else torch.float32
+
+    def close(self):
+        if getattr(self, "_p", None) and self._p.value:
+            N.check(self._lib.sc_plan_destroy(self._p), "sc_plan_destroy")
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        N.check(self._lib.sc_plan_set_stream(self._p, ctypes.c_void_p(_stream_handle(stream))),
+                "sc_plan_set_stream")
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * len(INFO_KEYS))()
+        N.check(self._lib.sc_plan_info(self._p, out, len(INFO_KEYS)), "sc_plan_info")
+        return dict(zip(INFO_KEYS, list(out)))
+
+    def set_sky_beam(self, alm: torch.Tensor, blm: torch.Tensor):
+        _dev(alm, "alm", torch.complex128)
+        _dev(blm, "blm", torch.complex128)
+        if alm.numel() != n_alm(self.lmax) or blm.numel() != n_alm(self.lmax, self.kmax):
+            raise ValueError("alm/blm sizes do not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
+        self.set_stream()
+        N.check(self._lib.sc_set_sky_beam(self._p, alm.data_ptr(), blm.data_ptr()), "sc_set_sky_beam")
+        self._keep = (alm, blm)
+
+    def interpolate(self, ptg: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _dev(ptg, "ptg", torch.float64)
+        if ptg.dim() != 2 or ptg.shape[1] != 3:
+            raise ValueError("ptg must be [n, 3]")
+        n = ptg.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
+        _dev(out, "tod", self.tod_dtype)
+        if out.numel() != n:
+            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
+        self.set_stream()
+        if n:
+            N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
+        return out
+
+    STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather")
+
+    def enable_timing(self, enable: bool = True):
+        N.check(self._lib.sc_plan_enable_timing(self._p, 1 if enable else 0), "sc_plan_enable_timing")
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, launches)} from the HIP events recorded since the last call."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        N.check(self._lib.sc_plan_stage_times(self._p, ms, cnt, 4), "sc_plan_stage_times")
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
+
+    def debug_stage(self, which: int) -> torch.Tensor:
+        """Copy of an internal stage: 0 = ring sums F (complex128 [kmax+1, 2 lmax+1, n_rings]),
+        1 = the stored component maps ([map_rows, map_cols, n_comp_padded])."""
+        inf = self.info()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if which == 0:
+            t = torch.empty((self.kmax + 1, 2 * self.lmax + 1, inf["n_rings"]), dtype=torch.complex128, device=dev)
+        else:
+            dt = torch.float64 if self.precision == N.SC_FP64 else torch.float32
+            t = torch.empty((inf["map_rows"], inf["map_cols"], inf["n_comp_padded"]), dtype=dt, device=dev)
+        self.set_stream()
+        N.check(self._lib.sc_debug_copy_stage(self._p, which, t.data_ptr(), t.numel() * t.element_size()),
+                "sc_debug_copy_stage")
+        return t
+
+
+def convolve(alm: torch.Tensor, blm: torch.Tensor, lmax: int, kmax: int, ptg: torch.Tensor,
+             precision="f64maps_f32gather", out: torch.Tensor | None = None) -> torch.Tensor:
+    """One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod (sc_convolve)."""
+    lib = N.load()
+    _dev(alm, "alm", torch.complex128)
+    _dev(blm, "blm", torch.complex128)
+    _dev(ptg, "ptg", torch.float64)
+    p = _prec(precision)
+    dt = torch.float64 if p == N.SC_FP64 else torch.float32
+    n = ptg.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=dt, device=ptg.device)
+    _dev(out, "tod", dt)
+    N.check(lib.sc_convolve(alm.data_ptr(), blm.data_ptr(), int(lmax), int(kmax), ptg.data_ptr(), n,
+                            out.data_ptr(), p, ctypes.c_void_p(_stream_handle())), "sc_convolve")
+    return out

@@ -1,0 +1,125 @@
+// k_fft.hip -- theta upsampling and phi synthesis of the component maps.
+//
+// After the ring sums F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j)
+// (the inner sums of Eqs. 7/9 of Galloway et al. 2022, Sec. 2.1, on rings
+// theta_j = (j + 1/2) pi / nring), each spin-k map T_k(theta, phi) =
+// sum_m F_k(theta, m) e^{i m phi} is brought onto an oversampled equiangular
+// grid ready for interpolation (the finite-resolution cube of Sec. 2.1):
+//
+//  theta: F_k(., m) is a trigonometric polynomial of degree <= lmax in theta
+//    whose continuation to the full circle obeys F(-theta) = (-1)^{m-k} F(theta)
+//    (from d^l_mk(-theta) = (-1)^{m-k} d^l_mk(theta)).  A length-2 nring FFT of
+//    the extended column gives its Fourier coefficients exactly; they are
+//    divided by the interpolation kernel's transform (theta and phi factors),
+//    zero-padded and inverse-transformed onto theta_r = r 2 pi / n2os, keeping
+//    rows r in [-W/2 + 1, n2os/2 + W/2] (ghost rows past the poles included).
+//  phi: per (k, row) the deconvolved m-spectrum is inverse-transformed onto
+//    phi_q = q 2 pi / nphi, q in [-W/2 + 1, nphi + W/2 - 1] (wrap copies), and
+//    stored as the real components M_0 = T_0, M_{2k-1} = 2 Re T_k,
+//    M_{2k} = -2 Im T_k so that c = sum_c basis_c(psi) M_c (Eq. 8).
+#include "fft_lds.h"
+
+namespace {
+
+__global__ void __launch_bounds__(SC_FFT_NT)
+k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
+                 int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
+                 const double2 *__restrict__ twos, const double2 *__restrict__ phase,
+                 const double *__restrict__ dphi) {
+    extern __shared__ double2 sbuf[];
+    const int nm = 2 * lmax + 1;
+    const int k = blockIdx.x / nm;
+    const int mi = blockIdx.x - k * nm;
+    const int m = mi - lmax;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int n2 = P2.n, nos = Pos.n;
+    double2 *A = sbuf;          // forward transform, length n2
+    double2 *B = sbuf + n2;     // inverse transform, length nos
+
+    const double sg = ((m - k) & 1) ? -1.0 : 1.0;
+    const double2 *col = F + ((size_t)k * nm + mi) * nring;
+    for (int j = tid; j < nring; j += nth) {
+        double2 f = col[j];
+        A[j] = f;
+        A[n2 - 1 - j] = cscale(f, sg);
+    }
+    for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    fft_lds<-1>(A, P2, tw2, tid, nth);
+
+    const double dm = dphi[m < 0 ? -m : m];
+    for (int t = tid; t < nm; t += nth) {
+        const int n = t - lmax;
+        double2 x = A[n < 0 ? n + n2 : n];
+        x = cscale(cmul(x, phase[t]), dm);
+        B[n < 0 ? n + nos : n] = x;
+    }
+    __syncthreads();
+    fft_lds<1>(B, Pos, twos, tid, nth);
+
+    const int r0 = -W / 2 + 1;
+    for (int row = tid; row < rows; row += nth) {
+        int r = row + r0;
+        r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
+        G[((size_t)k * rows + row) * nm + mi] = B[r];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_FFT_NT)
+k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
+                int W, FftPlan Pp, const double2 *__restrict__ twp) {
+    extern __shared__ double2 sbuf[];
+    const int nm = 2 * lmax + 1;
+    const int k = blockIdx.x / rows;
+    const int row = blockIdx.x - k * rows;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int np = Pp.n;
+    double2 *A = sbuf;
+    for (int t = tid; t < np; t += nth) A[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2 *src = G + ((size_t)k * rows + row) * nm;
+    for (int t = tid; t < nm; t += nth) {
+        const int m = t - lmax;
+        A[m < 0 ? m + np : m] = src[t];
+    }
+    __syncthreads();
+    fft_lds<1>(A, Pp, twp, tid, nth);
+
+    const int q0 = -W / 2 + 1;
+    T *dst = maps + (size_t)row * cols * ncp;
+    for (int col = tid; col < cols; col += nth) {
+        int q = col + q0;
+        q = q < 0 ? q + np : (q >= np ? q - np : q);
+        const double2 v = A[q];
+        T *o = dst + (size_t)col * ncp;
+        if (k == 0) {
+            o[0] = (T)v.x;
+        } else {
+            o[2 * k - 1] = (T)(2.0 * v.x);
+            o[2 * k] = (T)(-2.0 * v.y);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t sc_launch_theta_upsample(sc_plan *p) {
+    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
+    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
+    hipLaunchKernelGGL(k_theta_upsample, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->F, p->G, p->lmax,
+                       p->nring, p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_phi_synthesis(sc_plan *p) {
+    const int nblk = (p->kmax + 1) * p->rows;
+    const size_t lds = sizeof(double2) * (size_t)p->nphi;
+    if (p->prec == SC_FP64)
+        hipLaunchKernelGGL(k_phi_synthesis<double>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G,
+                           (double *)p->maps, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    else
+        hipLaunchKernelGGL(k_phi_synthesis<float>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G,
+                           (float *)p->maps, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    return hipGetLastError();
+}

@@ -1,0 +1,195 @@
+// k_synth.hip -- ring sums of the spin transforms (FP64).
+//
+// For each beam order k (0..kmax), sky order m (0..lmax) and ring theta_j the
+// kernel evaluates
+//     F_k(theta_j,  m)        = sum_l a_lm conj(b_lk) d^l_mk(theta_j)
+//     F_k(pi - theta_j, -m)   = sum_l (-1)^{l+k+m} conj(a_lm) conj(b_lk) d^l_mk(theta_j)
+// i.e. the inner sum of Eq. 7 / Eq. 9 of Galloway et al. (2022, Sec. 2.1) on
+// a ring, before its azimuthal Fourier synthesis.  The second line follows from
+// d^l_{-m,k}(pi - theta) = (-1)^{l+k} d^l_mk(theta) and a_{l,-m} = (-1)^m conj(a_lm)
+// (real sky), so one recursion per (k, m >= 0) serves both signs of m; rings
+// are placed symmetrically, theta_{nring-1-j} = pi - theta_j.
+//
+// d^l_mk(theta) comes from the three-term recursion in l,
+//   d^{l+1} = (alpha_l cos(theta) - beta_l) d^l - gamma_l d^{l-1},
+//   alpha_l = (2l+1)(l+1) / sqrt(((l+1)^2-m^2)((l+1)^2-k^2)),
+//   beta_l  = alpha_l m k / (l(l+1)),
+//   gamma_l = (l+1)/l sqrt((l^2-m^2)(l^2-k^2)) / sqrt(((l+1)^2-m^2)((l+1)^2-k^2)),
+// started at l0 = max(m, k) from the closed forms
+//   d^l_{l k} = (-1)^{l-k} sqrt(C(2l, l+k)) c^{l+k} s^{l-k}   (m >= k),
+//   d^l_{m l} =            sqrt(C(2l, l+m)) c^{l+m} s^{l-m}   (m <  k),
+// c = cos(theta/2), s = sin(theta/2).  Start values underflow FP64 near the
+// poles (down to ~1e-1440 at l = 512), so they are formed as extended-exponent
+// numbers and the recursion runs on a value scaled by 2^{-1200 e}: while
+// e < 0 the true value is below 2^-600 and contributes nothing; whenever the
+// scaled value passes 2^600 it is rescaled and e incremented.  Once e = 0 the
+// true values are bounded by 1 and no further rescaling happens.
+//
+// Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
+// rings.  Recursion coefficients and weights for 64 consecutive l are built
+// cooperatively in LDS (one l per lane) and read as broadcasts.
+#include "sc_common.h"
+
+namespace {
+
+struct XN {
+    double m;  // mantissa in [0.5, 1) (or 0)
+    int e;     // value = m * 2^e
+};
+
+__device__ __forceinline__ XN xn_norm(double v, int e) {
+    int ee;
+    double mm = frexp(v, &ee);
+    return {mm, e + ee};
+}
+__device__ __forceinline__ XN xn_mul(XN a, XN b) { return xn_norm(a.m * b.m, a.e + b.e); }
+__device__ XN xn_pow(double x, int n) {
+    XN r = {0.5, 1};
+    XN b = xn_norm(x, 0);
+    while (n) {
+        if (n & 1) r = xn_mul(r, b);
+        b = xn_mul(b, b);
+        n >>= 1;
+    }
+    return r;
+}
+
+constexpr int REC_STEP = 1200;  // rescaling exponent step
+constexpr double REC_BIG = 0x1p600;
+constexpr double REC_DOWN = 0x1p-1200;
+
+template <int RPT>
+__global__ void __launch_bounds__(64)
+k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
+            const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
+            int ngroups) {
+    __shared__ double cA[64], cB[64], cC[64];
+    __shared__ double2 cWp[64], cWm[64];
+
+    int b = blockIdx.x;
+    const int g = b % ngroups;
+    b /= ngroups;
+    const int k = b % (kmax + 1);
+    const int m = b / (kmax + 1);
+    const int lane = threadIdx.x;
+    const int l0 = m > k ? m : k;
+    const int mn = m < k ? m : k;
+    const int nm = 2 * lmax + 1;
+
+    double x[RPT], d[RPT], dp[RPT];
+    int e[RPT];
+    double2 fp[RPT], fm[RPT];
+
+    const double sgn = (m >= k && ((m - k) & 1)) ? -1.0 : 1.0;
+    const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int j = (g * RPT + r) * 64 + lane;
+        fp[r] = make_double2(0.0, 0.0);
+        fm[r] = make_double2(0.0, 0.0);
+        dp[r] = 0.0;
+        if (j < nring) {
+            const double t = ((double)j + 0.5) / (double)nring;  // theta / pi
+            x[r] = cospi(t);
+            const double ch = cospi(0.5 * t), sh = sinpi(0.5 * t);
+            XN v = xn_mul(xn_mul(xn_pow(ch, l0 + mn), xn_pow(sh, l0 - mn)), pref);
+            const int E = v.e;
+            const int es = (E + REC_STEP / 2 >= 0) ? 0 : -((-(E + REC_STEP / 2) + REC_STEP - 1) / REC_STEP);
+            e[r] = es;
+            d[r] = sgn * ldexp(v.m, E - REC_STEP * es);
+        } else {
+            x[r] = 0.0;
+            d[r] = 0.0;
+            e[r] = 0;
+        }
+    }
+
+    const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
+    const size_t aoff = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
+    for (int lc = l0; lc <= lmax; lc += 64) {
+        const int l = lc + lane;
+        __syncthreads();
+        if (l <= lmax) {
+            double A, B, C;
+            if (l == 0) {
+                A = 1.0;
+                B = 0.0;
+                C = 0.0;
+            } else {
+                const double L = l, L1 = l + 1.0;
+                const double q = sqrt((L1 * L1 - mm) * (L1 * L1 - kk));
+                A = (2.0 * L + 1.0) * L1 / q;
+                B = A * mk / (L * L1);
+                C = L1 / L * sqrt((L * L - mm) * (L * L - kk)) / q;
+            }
+            double2 a = alm[aoff + l];
+            double2 bb = blm[boff + l];
+            if (m == 0) a.y = 0.0;
+            if (k == 0) bb.y = 0.0;
+            const double2 wp = cmul(a, cconj(bb));
+            const double s = ((l + k + m) & 1) ? -1.0 : 1.0;
+            const double2 wm = cscale(cmul(cconj(a), cconj(bb)), s);
+            cA[lane] = A;
+            cB[lane] = B;
+            cC[lane] = C;
+            cWp[lane] = wp;
+            cWm[lane] = wm;
+        }
+        __syncthreads();
+        const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
+        for (int t = 0; t < nl; ++t) {
+            const double A = cA[t], B = cB[t], C = cC[t];
+            const double2 wp = cWp[t], wm = cWm[t];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const double dd = (e[r] == 0) ? d[r] : 0.0;
+                fp[r].x = fma(wp.x, dd, fp[r].x);
+                fp[r].y = fma(wp.y, dd, fp[r].y);
+                fm[r].x = fma(wm.x, dd, fm[r].x);
+                fm[r].y = fma(wm.y, dd, fm[r].y);
+                const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
+                dp[r] = d[r];
+                d[r] = dn;
+                if (fabs(dn) > REC_BIG) {
+                    d[r] *= REC_DOWN;
+                    dp[r] *= REC_DOWN;
+                    e[r] += 1;
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int j = (g * RPT + r) * 64 + lane;
+        if (j < nring) {
+            F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
+            if (m > 0) F[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)] = fm[r];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm) {
+    const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups;
+    switch (p->rpt) {
+        case 2:
+            hipLaunchKernelGGL(k_ring_sums<2>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
+                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
+                               p->ngroups);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_ring_sums<4>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
+                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
+                               p->ngroups);
+            break;
+        default:
+            hipLaunchKernelGGL(k_ring_sums<8>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
+                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
+                               p->ngroups);
+            break;
+    }
+    return hipGetLastError();
+}

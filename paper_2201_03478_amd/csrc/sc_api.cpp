@@ -1,0 +1,358 @@
+// sc_api.cpp -- C ABI of libsidelobe: argument validation, plan geometry and
+// workspace, and the order of kernel launches.  No arithmetic of the method
+// happens on the host: every stage runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "sc_common.h"
+
+namespace {
+
+thread_local char g_msg[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device (or managed) memory of the current HIP context?
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // unregistered host memory: clear the error
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+bool is_smooth(int n) {
+    for (int q : {2, 3, 5})
+        while (n % q == 0) n /= q;
+    return n == 1;
+}
+int next_smooth(int n, bool even) {
+    if (even && (n & 1)) ++n;
+    while (!is_smooth(n)) n += even ? 2 : 1;
+    return n;
+}
+
+bool factor_fft(int n, FftPlan *P) {
+    P->n = n;
+    P->nst = 0;
+    int m = n;
+    while (m % 4 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 4; m /= 4; }
+    while (m % 2 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 2; m /= 2; }
+    while (m % 3 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 3; m /= 3; }
+    while (m % 5 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 5; m /= 5; }
+    return m == 1 && n <= 4096;
+}
+
+// Record the start event of a timed launch; returns the slot or -1.
+int timing_begin(sc_plan *p, int stage) {
+    if (!p->timing) return -1;
+    if (p->tl_n == p->tl_cap) {
+        int cap = p->tl_cap ? 2 * p->tl_cap : 64;
+        TimedLaunch *n = (TimedLaunch *)std::realloc(p->tl, sizeof(TimedLaunch) * cap);
+        if (!n) return -1;
+        for (int i = p->tl_cap; i < cap; ++i) {
+            n[i].a = nullptr;
+            n[i].b = nullptr;
+        }
+        p->tl = n;
+        p->tl_cap = cap;
+    }
+    TimedLaunch &t = p->tl[p->tl_n];
+    if (!t.a && (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess)) return -1;
+    t.stage = stage;
+    if (hipEventRecord(t.a, p->stream) != hipSuccess) return -1;
+    return p->tl_n++;
+}
+void timing_end(sc_plan *p, int slot) {
+    if (slot >= 0) (void)hipEventRecord(p->tl[slot].b, p->stream);
+}
+
+void free_plan_buffers(sc_plan *p) {
+    for (int i = 0; i < p->tl_cap; ++i) {
+        if (p->tl[i].a) (void)hipEventDestroy(p->tl[i].a);
+        if (p->tl[i].b) (void)hipEventDestroy(p->tl[i].b);
+    }
+    std::free(p->tl);
+    p->tl = nullptr;
+    p->tl_cap = p->tl_n = 0;
+    void *bufs[] = {p->F, p->G, p->maps, p->sbin_m, p->sbin_e, p->tw2, p->tw2os, p->twphi,
+                    p->phase, p->dphi, p->glx, p->glw};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+int alloc(void **dst, size_t bytes, size_t *total) {
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return fail(SC_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    *total += bytes;
+    return SC_OK;
+}
+
+struct PlanCache {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int>, sc_plan *> plans;
+};
+PlanCache &plan_cache() {
+    static PlanCache *c = new PlanCache();  // never destroyed: plans outlive static teardown
+    return *c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sc_strerror(int code) {
+    switch (code) {
+        case SC_OK: return "success";
+        case SC_EINVAL: return "invalid argument";
+        case SC_ENOMEM: return "out of device memory";
+        case SC_EHIP: return "HIP runtime error";
+        case SC_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char *sc_last_error(void) { return g_msg; }
+
+int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_width, void *stream) {
+    g_msg[0] = 0;
+    if (!out) return fail(SC_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    if (lmax < 0) return fail(SC_EINVAL, "lmax = %d < 0", lmax);
+    if (kmax < 0 || kmax > lmax) return fail(SC_EINVAL, "kmax = %d outside [0, lmax = %d]", kmax, lmax);
+    if (kmax > 127) return fail(SC_EINVAL, "kmax = %d above the supported 127", kmax);
+    if (precision != SC_FP64 && precision != SC_F64MAPS_F32GATHER)
+        return fail(SC_EINVAL, "unknown precision %d", precision);
+    int W = kernel_width;
+    if (W == 0) W = precision == SC_FP64 ? 14 : 8;
+    if (W < 4 || W > 16 || (W & 1)) return fail(SC_EINVAL, "kernel width %d not an even number in [4, 16]", W);
+
+    sc_plan *p = new (std::nothrow) sc_plan;
+    if (!p) return fail(SC_ENOMEM, "host allocation failed");
+    std::memset(p, 0, sizeof(*p));
+    p->lmax = lmax;
+    p->kmax = kmax;
+    p->prec = precision;
+    p->W = W;
+    p->beta = 2.30 * W;  // exponential-of-semicircle shape for 2x oversampling
+    p->stream = (hipStream_t)stream;
+    // theta: 2 nring >= 2 lmax + 2 samples of the full circle represent a degree-lmax
+    // trigonometric polynomial exactly; the fine grid oversamples it >= 2x.
+    p->n2 = next_smooth(2 * lmax + 2, true);
+    p->nring = p->n2 / 2;
+    p->n2os = next_smooth(2 * p->n2, true);
+    p->nphi = next_smooth(2 * (2 * lmax + 1), false);
+    if (p->nphi < 2 * W) p->nphi = next_smooth(2 * W, false);
+    p->rows = p->n2os / 2 + W;
+    p->cols = p->nphi + W - 1;
+    p->ncomp = 2 * kmax + 1;
+    p->ncp = (p->ncomp + 3) & ~3;
+    p->nq = 128;
+    p->rpt = p->nring <= 128 ? 2 : (p->nring <= 256 ? 4 : 8);
+    p->ngroups = (p->nring + 64 * p->rpt - 1) / (64 * p->rpt);
+    if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
+        delete p;
+        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 4096 points (not supported)", lmax);
+    }
+
+    const size_t nm = 2 * (size_t)lmax + 1;
+    size_t tot = 0;
+    int rc = SC_OK;
+    rc = rc ? rc : alloc((void **)&p->F, sizeof(double2) * (kmax + 1) * nm * p->nring, &tot);
+    rc = rc ? rc : alloc((void **)&p->G, sizeof(double2) * (kmax + 1) * (size_t)p->rows * nm, &tot);
+    rc = rc ? rc : alloc(&p->maps, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, &tot);
+    rc = rc ? rc : alloc((void **)&p->sbin_m, sizeof(double) * (lmax + 1) * (kmax + 1), &tot);
+    rc = rc ? rc : alloc((void **)&p->sbin_e, sizeof(int) * (lmax + 1) * (kmax + 1), &tot);
+    rc = rc ? rc : alloc((void **)&p->tw2, sizeof(double2) * p->n2, &tot);
+    rc = rc ? rc : alloc((void **)&p->tw2os, sizeof(double2) * p->n2os, &tot);
+    rc = rc ? rc : alloc((void **)&p->twphi, sizeof(double2) * p->nphi, &tot);
+    rc = rc ? rc : alloc((void **)&p->phase, sizeof(double2) * nm, &tot);
+    rc = rc ? rc : alloc((void **)&p->dphi, sizeof(double) * (lmax + 1), &tot);
+    rc = rc ? rc : alloc((void **)&p->glx, sizeof(double) * p->nq, &tot);
+    rc = rc ? rc : alloc((void **)&p->glw, sizeof(double) * p->nq, &tot);
+    if (rc) {
+        free_plan_buffers(p);
+        delete p;
+        return rc;
+    }
+    p->ws_bytes = tot;
+    // padding components stay zero for the plan's lifetime
+    hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, p->stream);
+    if (e == hipSuccess) e = sc_launch_tables(p);
+    if (e != hipSuccess) {
+        free_plan_buffers(p);
+        delete p;
+        return hip_fail(e, "plan table setup");
+    }
+    *out = p;
+    return SC_OK;
+}
+
+int sc_plan_destroy(sc_plan *p) {
+    if (!p) return SC_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    free_plan_buffers(p);
+    delete p;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in sc_plan_destroy");
+    return SC_OK;
+}
+
+int sc_plan_set_stream(sc_plan *p, void *stream) {
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    p->stream = (hipStream_t)stream;
+    return SC_OK;
+}
+
+int sc_plan_info(const sc_plan *p, int64_t *out, int nout) {
+    if (!p || (nout > 0 && !out)) return fail(SC_EINVAL, "NULL plan or output");
+    const int64_t v[] = {p->lmax, p->kmax, p->prec, p->W, p->nring, p->n2, p->n2os, p->nphi,
+                         p->rows, p->cols, p->ncomp, p->ncp, (int64_t)p->ws_bytes};
+    const int nv = (int)(sizeof(v) / sizeof(v[0]));
+    for (int i = 0; i < nout && i < nv; ++i) out[i] = v[i];
+    return nv;
+}
+
+int sc_set_sky_beam(sc_plan *p, const double *alm, const double *blm) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (!is_device_ptr(alm)) return fail(SC_EINVAL, "alm is not device memory");
+    if (!is_device_ptr(blm)) return fail(SC_EINVAL, "blm is not device memory");
+    if (((uintptr_t)alm & 15) || ((uintptr_t)blm & 15)) return fail(SC_EINVAL, "alm/blm not 16-byte aligned");
+    int slot = timing_begin(p, SC_STAGE_RING);
+    hipError_t e = sc_launch_ring_sums(p, alm, blm);
+    timing_end(p, slot);
+    if (e == hipSuccess) {
+        slot = timing_begin(p, SC_STAGE_THETA);
+        e = sc_launch_theta_upsample(p);
+        timing_end(p, slot);
+    }
+    if (e == hipSuccess) {
+        slot = timing_begin(p, SC_STAGE_PHI);
+        e = sc_launch_phi_synthesis(p);
+        timing_end(p, slot);
+    }
+    if (e != hipSuccess) return hip_fail(e, "map synthesis launch");
+    p->have_maps = 1;
+    return SC_OK;
+}
+
+int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n == 0) return SC_OK;
+    if (!p->have_maps) return fail(SC_ESTATE, "sc_interpolate before sc_set_sky_beam");
+    if (!is_device_ptr(ptg)) return fail(SC_EINVAL, "ptg is not device memory");
+    if (!is_device_ptr(tod)) return fail(SC_EINVAL, "tod is not device memory");
+    if (((uintptr_t)ptg & 7) || ((uintptr_t)tod & (p->prec == SC_FP64 ? 7 : 3)))
+        return fail(SC_EINVAL, "ptg/tod misaligned");
+    int slot = timing_begin(p, SC_STAGE_GATHER);
+    hipError_t e = sc_launch_gather(p, ptg, n, tod);
+    timing_end(p, slot);
+    if (e != hipSuccess) return hip_fail(e, "gather launch");
+    return SC_OK;
+}
+
+int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const double *ptg, int64_t n, void *tod,
+                int precision, void *stream) {
+    g_msg[0] = 0;
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    PlanCache &pc = plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    auto key = std::make_tuple(lmax, kmax, precision, dev);
+    sc_plan *p = nullptr;
+    auto it = pc.plans.find(key);
+    if (it == pc.plans.end()) {
+        int rc = sc_plan_create(&p, lmax, kmax, precision, 0, stream);
+        if (rc) return rc;
+        pc.plans[key] = p;
+    } else {
+        p = it->second;
+        p->stream = (hipStream_t)stream;
+    }
+    int rc = sc_set_sky_beam(p, alm, blm);
+    if (rc) return rc;
+    return sc_interpolate(p, ptg, n, tod);
+}
+
+int sc_plan_enable_timing(sc_plan *p, int enable) {
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    p->timing = enable ? 1 : 0;
+    return SC_OK;
+}
+
+int sc_plan_stage_times(sc_plan *p, double *ms, int64_t *launches, int nstage) {
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    double tot[SC_NSTAGE] = {0, 0, 0, 0};
+    int64_t cnt[SC_NSTAGE] = {0, 0, 0, 0};
+    for (int i = 0; i < p->tl_n; ++i) {
+        TimedLaunch &t = p->tl[i];
+        hipError_t e = hipEventSynchronize(t.b);
+        float f = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, t.a, t.b);
+        if (e != hipSuccess) {
+            p->tl_n = 0;
+            return hip_fail(e, "stage timing events");
+        }
+        tot[t.stage] += f;
+        cnt[t.stage] += 1;
+    }
+    p->tl_n = 0;
+    for (int s = 0; s < nstage && s < SC_NSTAGE; ++s) {
+        if (ms) ms[s] = tot[s];
+        if (launches) launches[s] = cnt[s];
+    }
+    return SC_NSTAGE;
+}
+
+int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) {
+    if (!p || !dst) return fail(SC_EINVAL, "NULL plan or destination");
+    if (!is_device_ptr(dst)) return fail(SC_EINVAL, "destination is not device memory");
+    const void *src = nullptr;
+    size_t bytes = 0;
+    if (which == 0) {
+        src = p->F;
+        bytes = sizeof(double2) * (p->kmax + 1) * (2 * (size_t)p->lmax + 1) * p->nring;
+    } else if (which == 1) {
+        src = p->maps;
+        bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
+    } else {
+        return fail(SC_EINVAL, "unknown stage %d", which);
+    }
+    if ((int64_t)bytes > capacity) return fail(SC_EINVAL, "destination holds %lld bytes, need %zu",
+                                               (long long)capacity, bytes);
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "stage copy");
+    return (int64_t)bytes;
+}
+
+}  // extern "C"

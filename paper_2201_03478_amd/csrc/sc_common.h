@@ -1,0 +1,83 @@
+// sc_common.h -- internal definitions shared by the HIP sources of libsidelobe.
+//
+// The plan holds the grid geometry and every device buffer of the two-step
+// total-convolution method (Galloway et al. 2022, Sec. 2.1): ring sums of the
+// Wigner-d recursion, the theta-upsampled ring spectra, the component maps on
+// the oversampled grid, and the constant tables (transform twiddles, kernel
+// deconvolution factors, recursion seed prefactors).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/sidelobe.h"
+
+#define SC_MAX_RADICES 24
+
+// Radix schedule of one mixed-radix (2, 3, 4, 5) Stockham transform.
+struct FftPlan {
+    int n;
+    int nst;
+    int r[SC_MAX_RADICES];
+};
+
+struct sc_plan {
+    int lmax, kmax, prec, W;
+    double beta;       // exponential-of-semicircle shape parameter
+    int nring;         // theta rings of the recursion, theta_j = (j + 1/2) pi / nring
+    int n2;            // 2 nring: full-circle length of the forward theta transform
+    int n2os;          // oversampled full-circle theta grid, spacing 2 pi / n2os
+    int nphi;          // oversampled phi grid, spacing 2 pi / nphi
+    int rows, cols;    // stored map rows (theta nodes incl. ghost rows) and columns (incl. wrap)
+    int ncomp, ncp;    // 2 kmax + 1 components, padded count
+    int rpt, ngroups;  // recursion layout: rings per lane, ring groups per (k, m)
+    hipStream_t stream;
+
+    FftPlan p2, p2os, pphi;
+
+    // device buffers
+    double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums
+    double2 *G;        // [kmax+1][rows][2 lmax+1] theta-upsampled, deconvolved
+    void *maps;        // [rows][cols][ncp] float or double
+    double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
+    int *sbin_e;       // [lmax+1][kmax+1] binary exponent
+    double2 *tw2, *tw2os, *twphi;  // e^{-2 pi i t / N}
+    double2 *phase;    // [2 lmax+1] e^{-i n pi / n2} / (n2 hhat_theta(n))
+    double *dphi;      // [lmax+1] 1 / hhat_phi(m)
+    double *glx, *glw; // Gauss-Legendre nodes/weights for the kernel transform
+    int nq;
+
+    int have_maps;
+    size_t ws_bytes;
+
+    // per-kernel event timing (see sc_plan_enable_timing)
+    int timing;
+    struct TimedLaunch *tl;  // pool of event pairs
+    int tl_n, tl_cap;
+};
+
+enum { SC_STAGE_RING = 0, SC_STAGE_THETA = 1, SC_STAGE_PHI = 2, SC_STAGE_GATHER = 3, SC_NSTAGE = 4 };
+
+struct TimedLaunch {
+    int stage;
+    hipEvent_t a, b;
+};
+
+static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_FP64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- launchers
+hipError_t sc_launch_tables(sc_plan *p);
+hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
+hipError_t sc_launch_theta_upsample(sc_plan *p);
+hipError_t sc_launch_phi_synthesis(sc_plan *p);
+hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
