@@ -147,8 +147,9 @@ int64_t sc_debug_copy_stage(sc_plan *plan, int which, void *dst, int64_t capacit
  * the recorded events, adds each launch's duration to its stage total, writes
  * ms[s] (total milliseconds) and launches[s] for the first nstage stages, and
  * clears the records.  Stages: 0 ring sums (recursion + contraction),
- * 1 theta upsampling, 2 phi synthesis, 3 interpolation + k-sum.
- * Returns the number of stages (4).
+ * 1 theta upsampling, 2 phi synthesis, 3 interpolation + k-sum, 4 pointing
+ * binning (anchor keys, scan, scatter, work items).
+ * Returns the number of stages (5).
  */
 int sc_plan_enable_timing(sc_plan *plan, int enable);
 int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage);

@@ -101,16 +101,17 @@ class Plan:
             N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
         return out
 
-    STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather")
+    STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather", "binning")
 
     def enable_timing(self, enable: bool = True):
         N.check(self._lib.sc_plan_enable_timing(self._p, 1 if enable else 0), "sc_plan_enable_timing")
 
     def stage_times(self) -> dict:
         """{stage: (total ms, launches)} from the HIP events recorded since the last call."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int64 * 4)()
-        N.check(self._lib.sc_plan_stage_times(self._p, ms, cnt, 4), "sc_plan_stage_times")
+        ns = len(self.STAGES)
+        ms = (ctypes.c_double * ns)()
+        cnt = (ctypes.c_int64 * ns)()
+        N.check(self._lib.sc_plan_stage_times(self._p, ms, cnt, ns), "sc_plan_stage_times")
         return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
 
     def debug_stage(self, which: int) -> torch.Tensor:

@@ -1,0 +1,187 @@
+// k_bin.hip -- pointing preprocessing: bin samples by interpolation anchor.
+//
+// The interpolation stencil of a pointing starts at the grid node
+// (row0, col0) = (floor(theta / h_theta), floor(phi / h_phi)) in map storage
+// coordinates; every sample with the same anchor reads the same W x W x ncomp
+// block of the component maps.  A counting sort groups the samples by anchor
+// so that the gather can stage one block in LDS and reuse it for all of them:
+//
+//   k_bin_keys     anchor key and rank within the key (atomic counter) per sample
+//   k_scan_*       exclusive scan of (samples, work items) per key
+//   k_bin_scatter  samples in key order: fractional offsets and psi (FP64)
+//                  and the original index
+//   k_bin_items    work items (key, first sorted sample, count <= BIN_CHUNK)
+//
+// Integer index arithmetic is exact; the fractional offsets u - floor(u) are
+// kept in FP64 (the FP32 gather rounds them when it forms its weights).
+#include "sc_common.h"
+
+namespace {
+
+__global__ void k_fill_int(int *a, int64_t n, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__device__ __forceinline__ void anchor_of(const double *ptg, int64_t s, const BinGeom &g, int &row0, int &col0,
+                                          double &fu, double &fv, double &psi) {
+    const double two_pi = 6.283185307179586477;
+    const double th = ptg[3 * s], ph = ptg[3 * s + 1], ps = ptg[3 * s + 2];
+    double u = th * g.inv_hth;
+    u = fmin(fmax(u, 0.0), 0.5 * (double)g.n2os);  // also maps NaN to 0
+    double v = (ph - two_pi * floor(ph / two_pi)) * g.inv_hph;
+    if (!(v < (double)g.nphi) || v < 0.0) v = 0.0;
+    const double flu = floor(u), flv = floor(v);
+    row0 = (int)flu;
+    col0 = (int)flv;
+    fu = u - flu;
+    fv = v - flv;
+    psi = ps - two_pi * floor(ps / two_pi);
+    if (!(psi >= 0.0 && psi < two_pi)) psi = 0.0;
+}
+
+__global__ void k_bin_keys(const double *__restrict__ ptg, int64_t n, BinGeom g, int *__restrict__ key,
+                           int *__restrict__ rank, int *__restrict__ count) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int r0, c0;
+    double fu, fv, psi;
+    anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
+    const int k = r0 * g.nkc + c0;
+    key[s] = k;
+    rank[s] = atomicAdd(&count[k], 1);
+}
+
+// --- exclusive scan of int2 (x: samples per key, y: items per key) ------------
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_BLOCK = SCAN_NT * SCAN_PER;
+
+__device__ __forceinline__ int2 key_pair(const int *count, int64_t i, int64_t nkeys) {
+    if (i >= nkeys) return make_int2(0, 0);
+    const int c = count[i];
+    return make_int2(c, (c + BIN_CHUNK - 1) / BIN_CHUNK);
+}
+
+// block-wide exclusive scan of one int2 per thread; returns the block total
+__device__ int2 block_scan(int2 v, int2 *sh, int &excl_x, int &excl_y) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_NT; off <<= 1) {
+        int2 t = tid >= off ? sh[tid - off] : make_int2(0, 0);
+        __syncthreads();
+        sh[tid] = make_int2(sh[tid].x + t.x, sh[tid].y + t.y);
+        __syncthreads();
+    }
+    const int2 incl = sh[tid];
+    excl_x = incl.x - v.x;
+    excl_y = incl.y - v.y;
+    const int2 tot = sh[SCAN_NT - 1];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const int *__restrict__ count, int64_t nkeys,
+                                                         int2 *__restrict__ sums) {
+    __shared__ int2 sh[SCAN_NT];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER;
+    int2 acc = make_int2(0, 0);
+    for (int q = 0; q < SCAN_PER; ++q) {
+        const int2 v = key_pair(count, base + q, nkeys);
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    int ex, ey;
+    const int2 tot = block_scan(acc, sh, ex, ey);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the per-block sums; writes totals
+__global__ void __launch_bounds__(SCAN_NT) k_scan_sums(int2 *__restrict__ sums, int nblk, int *__restrict__ totals) {
+    __shared__ int2 sh[SCAN_NT];
+    int2 carry = make_int2(0, 0);
+    for (int base = 0; base < nblk; base += SCAN_NT) {
+        const int i = base + threadIdx.x;
+        const int2 v = i < nblk ? sums[i] : make_int2(0, 0);
+        int ex, ey;
+        const int2 tot = block_scan(v, sh, ex, ey);
+        if (i < nblk) sums[i] = make_int2(carry.x + ex, carry.y + ey);
+        carry.x += tot.x;
+        carry.y += tot.y;
+    }
+    if (threadIdx.x == 0) {
+        totals[0] = carry.x;  // samples
+        totals[1] = carry.y;  // work items
+        totals[2] = 0;        // work-queue cursor of the gather
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int *__restrict__ count, int64_t nkeys,
+                                                        const int2 *__restrict__ sums, int2 *__restrict__ offs) {
+    __shared__ int2 sh[SCAN_NT];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER;
+    int2 v[SCAN_PER];
+    int2 acc = make_int2(0, 0);
+    for (int q = 0; q < SCAN_PER; ++q) {
+        v[q] = key_pair(count, base + q, nkeys);
+        acc.x += v[q].x;
+        acc.y += v[q].y;
+    }
+    int ex, ey;
+    block_scan(acc, sh, ex, ey);
+    const int2 bo = sums[blockIdx.x];
+    int2 run = make_int2(bo.x + ex, bo.y + ey);
+    for (int q = 0; q < SCAN_PER; ++q) {
+        if (base + q < nkeys) offs[base + q] = run;
+        run.x += v[q].x;
+        run.y += v[q].y;
+    }
+}
+
+__global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom g, const int *__restrict__ key,
+                              const int *__restrict__ rank, const int2 *__restrict__ offs, BinSorted out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int r0, c0;
+    double fu, fv, psi;
+    anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
+    const int pos = offs[key[s]].x + rank[s];
+    out.fu[pos] = fu;
+    out.fv[pos] = fv;
+    out.psi[pos] = psi;
+    out.idx[pos] = (int)s;
+}
+
+__global__ void k_bin_items(const int *__restrict__ count, const int2 *__restrict__ offs, int64_t nkeys,
+                            int4 *__restrict__ items) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys) return;
+    const int c = count[k];
+    if (c == 0) return;
+    const int2 o = offs[k];
+    for (int q = 0; q * BIN_CHUNK < c; ++q) {
+        const int cnt = c - q * BIN_CHUNK < BIN_CHUNK ? c - q * BIN_CHUNK : BIN_CHUNK;
+        items[o.y + q] = make_int4((int)k, o.x + q * BIN_CHUNK, cnt, 0);
+    }
+}
+
+}  // namespace
+
+hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
+    BinWork &w = p->bw;
+    const BinGeom g = sc_bin_geom(p);
+    const int64_t nkeys = (int64_t)g.nkr * g.nkc;
+    const int bs = 256;
+    const unsigned gs = (unsigned)((n + bs - 1) / bs);
+    hipLaunchKernelGGL(k_fill_int, dim3(1024), dim3(256), 0, p->stream, w.count, nkeys, 0);
+    hipLaunchKernelGGL(k_bin_keys, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.count);
+    const int nblk = (int)((nkeys + SCAN_BLOCK - 1) / SCAN_BLOCK);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, p->stream, w.sums, nblk, w.totals);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, w.offs);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.offs, w.sorted);
+    hipLaunchKernelGGL(k_bin_items, dim3((unsigned)((nkeys + bs - 1) / bs)), dim3(bs), 0, p->stream, w.count,
+                       w.offs, nkeys, w.items);
+    return hipGetLastError();
+}

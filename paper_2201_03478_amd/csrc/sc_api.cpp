@@ -89,7 +89,54 @@ void timing_end(sc_plan *p, int slot) {
     if (slot >= 0) (void)hipEventRecord(p->tl[slot].b, p->stream);
 }
 
+void free_bin_work(BinWork &w) {
+    void *bufs[] = {w.count, w.offs, w.sums, w.totals, w.key, w.rank, w.sorted.fu, w.sorted.fv,
+                    w.sorted.psi, w.sorted.idx, w.items};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    std::memset(&w, 0, sizeof(w));
+}
+
+int alloc(void **dst, size_t bytes, size_t *total);
+
+// Binning workspace for passes of up to `need` samples (grown on demand).
+int ensure_bin_work(sc_plan *p, int64_t need) {
+    BinWork &w = p->bw;
+    if (w.cap >= need) return SC_OK;
+    // buffers are in use by earlier work on the stream until it completes
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail(SC_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    p->ws_bytes -= w.bytes;
+    free_bin_work(w);
+    const BinGeom g = sc_bin_geom(p);
+    const int64_t nkeys = (int64_t)g.nkr * g.nkc;
+    const int64_t nblk = (nkeys + 4095) / 4096;
+    size_t tot = 0;
+    int rc = SC_OK;
+    rc = rc ? rc : alloc((void **)&w.count, sizeof(int) * nkeys, &tot);
+    rc = rc ? rc : alloc((void **)&w.offs, sizeof(int2) * nkeys, &tot);
+    rc = rc ? rc : alloc((void **)&w.sums, sizeof(int2) * nblk, &tot);
+    rc = rc ? rc : alloc((void **)&w.totals, sizeof(int) * 4, &tot);
+    rc = rc ? rc : alloc((void **)&w.key, sizeof(int) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.rank, sizeof(int) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.sorted.fu, sizeof(double) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.sorted.fv, sizeof(double) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.sorted.psi, sizeof(double) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.sorted.idx, sizeof(int) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.items, sizeof(int4) * need, &tot);
+    if (rc) {
+        free_bin_work(w);
+        return rc;
+    }
+    w.cap = need;
+    w.nkeys = nkeys;
+    w.bytes = tot;
+    p->ws_bytes += tot;
+    return SC_OK;
+}
+
 void free_plan_buffers(sc_plan *p) {
+    free_bin_work(p->bw);
     for (int i = 0; i < p->tl_cap; ++i) {
         if (p->tl[i].a) (void)hipEventDestroy(p->tl[i].a);
         if (p->tl[i].b) (void)hipEventDestroy(p->tl[i].b);
@@ -174,6 +221,13 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->ncomp = 2 * kmax + 1;
     p->ncp = (p->ncomp + 3) & ~3;
     p->nq = 128;
+    {
+        const char *g = std::getenv("SC_GATHER_PATH");
+        p->gather_direct = (g && std::strcmp(g, "direct") == 0) ? 1 : 0;
+        const char *b = std::getenv("SC_BIN_PASS_MAX");
+        long long v = b ? std::atoll(b) : 0;
+        p->bin_pass_max = (v > 0 && v < BIN_PASS_MAX) ? (int64_t)v : (int64_t)BIN_PASS_MAX;
+    }
     p->rpt = p->nring <= 128 ? 2 : (p->nring <= 256 ? 4 : 8);
     p->ngroups = (p->nring + 64 * p->rpt - 1) / (64 * p->rpt);
     if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
@@ -272,10 +326,28 @@ int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     if (!is_device_ptr(tod)) return fail(SC_EINVAL, "tod is not device memory");
     if (((uintptr_t)ptg & 7) || ((uintptr_t)tod & (p->prec == SC_FP64 ? 7 : 3)))
         return fail(SC_EINVAL, "ptg/tod misaligned");
-    int slot = timing_begin(p, SC_STAGE_GATHER);
-    hipError_t e = sc_launch_gather(p, ptg, n, tod);
-    timing_end(p, slot);
-    if (e != hipSuccess) return hip_fail(e, "gather launch");
+    if (p->gather_direct || !sc_gather_binned_supported(p)) {
+        int slot = timing_begin(p, SC_STAGE_GATHER);
+        hipError_t e = sc_launch_gather(p, ptg, n, tod);
+        timing_end(p, slot);
+        if (e != hipSuccess) return hip_fail(e, "gather launch");
+        return SC_OK;
+    }
+    const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
+    int rc = ensure_bin_work(p, pass);
+    if (rc) return rc;
+    const size_t esz = p->prec == SC_FP64 ? 8 : 4;
+    for (int64_t off = 0; off < n; off += pass) {
+        const int64_t cnt = n - off < pass ? n - off : pass;
+        int slot = timing_begin(p, SC_STAGE_BIN);
+        hipError_t e = sc_launch_binning(p, ptg + 3 * off, cnt);
+        timing_end(p, slot);
+        if (e != hipSuccess) return hip_fail(e, "binning launch");
+        slot = timing_begin(p, SC_STAGE_GATHER);
+        e = sc_launch_gather_binned(p, (char *)tod + esz * off);
+        timing_end(p, slot);
+        if (e != hipSuccess) return hip_fail(e, "binned gather launch");
+    }
     return SC_OK;
 }
 
@@ -312,8 +384,8 @@ int sc_plan_enable_timing(sc_plan *p, int enable) {
 
 int sc_plan_stage_times(sc_plan *p, double *ms, int64_t *launches, int nstage) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
-    double tot[SC_NSTAGE] = {0, 0, 0, 0};
-    int64_t cnt[SC_NSTAGE] = {0, 0, 0, 0};
+    double tot[SC_NSTAGE] = {0, 0, 0, 0, 0};
+    int64_t cnt[SC_NSTAGE] = {0, 0, 0, 0, 0};
     for (int i = 0; i < p->tl_n; ++i) {
         TimedLaunch &t = p->tl[i];
         hipError_t e = hipEventSynchronize(t.b);

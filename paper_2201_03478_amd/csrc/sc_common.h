@@ -22,6 +22,37 @@ struct FftPlan {
     int r[SC_MAX_RADICES];
 };
 
+// Samples per work item of the binned gather, and samples per binning pass.
+#define BIN_CHUNK 256
+#define BIN_PASS_MAX (1 << 24)
+
+// Anchor grid of the binned gather: key = row0 * nkc + col0.
+struct BinGeom {
+    double inv_hth, inv_hph;
+    int n2os, nphi;
+    int nkr, nkc;
+};
+
+// Samples in anchor order (structure of arrays).
+struct BinSorted {
+    double *fu, *fv;  // u - floor(u), v - floor(v) in grid units
+    double *psi;     // psi reduced to [0, 2 pi)
+    int *idx;        // index of the sample within its pass
+};
+
+struct BinWork {
+    int64_t cap;      // samples per pass the buffers hold
+    int64_t nkeys;
+    int *count;       // [nkeys] samples per anchor
+    int2 *offs;       // [nkeys] exclusive scan of (samples, items)
+    int2 *sums;       // [scan blocks]
+    int *totals;      // [4] samples, items, work cursor
+    int *key, *rank;  // [cap]
+    BinSorted sorted; // [cap]
+    int4 *items;      // [cap] (key, first sorted sample, count, -)
+    size_t bytes;
+};
+
 struct sc_plan {
     int lmax, kmax, prec, W;
     double beta;       // exponential-of-semicircle shape parameter
@@ -50,6 +81,9 @@ struct sc_plan {
 
     int have_maps;
     size_t ws_bytes;
+    BinWork bw;
+    int gather_direct;     // force the per-sample gather (env SC_GATHER_PATH=direct)
+    int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
 
     // per-kernel event timing (see sc_plan_enable_timing)
     int timing;
@@ -57,7 +91,8 @@ struct sc_plan {
     int tl_n, tl_cap;
 };
 
-enum { SC_STAGE_RING = 0, SC_STAGE_THETA = 1, SC_STAGE_PHI = 2, SC_STAGE_GATHER = 3, SC_NSTAGE = 4 };
+enum { SC_STAGE_RING = 0, SC_STAGE_THETA = 1, SC_STAGE_PHI = 2, SC_STAGE_GATHER = 3, SC_STAGE_BIN = 4,
+       SC_NSTAGE = 5 };
 
 struct TimedLaunch {
     int stage;
@@ -72,6 +107,21 @@ hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm)
 hipError_t sc_launch_theta_upsample(sc_plan *p);
 hipError_t sc_launch_phi_synthesis(sc_plan *p);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
+hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
+hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
+bool sc_gather_binned_supported(const sc_plan *p);
+
+static inline BinGeom sc_bin_geom(const sc_plan *p) {
+    const double two_pi = 6.283185307179586477;
+    BinGeom g;
+    g.inv_hth = (double)p->n2os / two_pi;
+    g.inv_hph = (double)p->nphi / two_pi;
+    g.n2os = p->n2os;
+    g.nphi = p->nphi;
+    g.nkr = p->n2os / 2 + 1;
+    g.nkc = p->nphi;
+    return g;
+}
 
 // ------------------------------------------------------------ device helpers
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
