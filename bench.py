@@ -58,6 +58,8 @@ def stage_model(info: dict, n: int, prec: int):
         "phi_synthesis": ("hbm", 16.0 * (K + 1) * rows * nm + esz * rows * cols * nc, "GB/s", PEAK["hbm"]),
         # one FMA per (tap, component) per sample
         "gather": ("alu", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"] if prec == 0 else PEAK["fp32"]),
+        # pointings read twice (keys, scatter), key + rank written and read, sorted record written
+        "binning": ("hbm", n * (2 * 24.0 + 2 * 8.0 + 28.0), "GB/s", PEAK["hbm"]),
     }
 
 
@@ -123,6 +125,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 4 per host thread)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -131,6 +135,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n}))
+        return
 
     import workloads as W
     from paper_2201_03478_amd import api

@@ -13,6 +13,8 @@
 // v1 layout: one wave per sample, lanes over components.
 #include "sc_common.h"
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 namespace {
 
 template <typename T>
@@ -86,10 +88,24 @@ k_gather_v1(const double *__restrict__ ptg, int64_t n, const T *__restrict__ map
 // (see k_bin.hip).  The 8 x 8 x ncomp map block of the anchor is staged in LDS
 // once; the samples are processed 64 at a time as a register-blocked product
 //     X[s][c] = sum_{t < 64} w_s(t) P[t][c]      (w_s(t) = w_theta(i) w_phi(j))
-// with each lane holding 4 samples x CPT components, followed by the k-sum
-// sum_c basis_c(psi_s) X[s][c] and a reduction over the 16 lanes that hold the
-// components of a sample.  cos k psi / sin k psi are formed in FP64: one
-// sincos per lane and sample at the lane's first k, then rotations by e^{i psi}.
+// with each lane holding 4 samples x CPT consecutive components, followed by
+// the k-sum sum_c basis_c(psi_s) X[s][c] and a reduction over the 16 lanes that
+// hold the components of a sample.
+//
+// cos k psi / sin k psi in FP64: one sincos per sample gives e^{i psi}; a table
+// of e^{i k0(g) psi} at the first order k0(g) of each of the 16 component groups
+// is built by powers and a 16-step product chain (error ~16 ulp), and each lane
+// rotates from its group's entry by e^{i psi} (at most CPT/2 + 1 steps).
+__device__ __forceinline__ double2 cpowi(double2 z, int n) {
+    double2 r = make_double2(1.0, 0.0);
+    while (n) {
+        if (n & 1) r = cmul(r, z);
+        z = cmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
 template <typename T, int CPT>
 __global__ void __launch_bounds__(256)
 k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt,
@@ -97,12 +113,12 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 double beta) {
     constexpr int NC = 16 * CPT;  // staged components (zero-padded)
     extern __shared__ double smem_d[];
-    T *Psh = (T *)smem_d;       // [64 taps][NC]
-    T *Wsh = Psh + 64 * NC;     // [64 taps][64 samples]
-    T *W1 = Wsh + 64 * 64;      // [64 samples][16]: 8 theta then 8 phi weights
-    double *Psi = (double *)(W1 + 64 * 16);  // [64]
-    double2 *E1 = (double2 *)(Psi + 64);     // [64] (cos psi, sin psi)
-    int *Idx = (int *)(E1 + 64);             // [64]
+    T *Psh = (T *)smem_d;         // [64 taps][NC]
+    T *Wsh = Psh + 64 * NC;       // [64 taps][64 samples]; reused for Eg after the product
+    double2 *Eg = (double2 *)Wsh; // [64 samples][16 groups] e^{i k0(g) psi}
+    T *W1 = Wsh + 64 * 64;        // [16][64 samples]: 8 theta then 8 phi weights
+    double2 *E1 = (double2 *)(W1 + 64 * 16);  // [64] (cos psi, sin psi)
+    int *Idx = (int *)(E1 + 64);              // [64]
     __shared__ int item_sh;
 
     const int tid = threadIdx.x;
@@ -126,7 +142,7 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
             const int ns = item.z - ch < 64 ? item.z - ch : 64;
             const int pos0 = item.y + ch;
             for (int e = tid; e < 64 * 16; e += 256) {
-                const int sl = e >> 4, q = e & 15;
+                const int q = e >> 6, sl = e & 63;
                 T w = (T)0;
                 if (sl < ns) {
                     const T f = (q < 8) ? (T)srt.fu[pos0 + sl] : (T)srt.fv[pos0 + sl];
@@ -144,14 +160,13 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 }
                 double sn, cs;
                 sincos(ps, &sn, &cs);
-                Psi[tid] = ps;
                 E1[tid] = make_double2(cs, sn);
                 Idx[tid] = ix;
             }
             __syncthreads();
             for (int e = tid; e < 64 * 64; e += 256) {
                 const int t = e >> 6, sl = e & 63;
-                Wsh[e] = W1[sl * 16 + (t >> 3)] * W1[sl * 16 + 8 + (t & 7)];
+                Wsh[e] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
             }
             __syncthreads();
 
@@ -174,16 +189,31 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                     acc[3][c] = fma(w3, pv, acc[3][c]);
                 }
             }
+            __syncthreads();  // Wsh is dead: build the group phase table in its place
+            {
+                const int sl = tid >> 2, q = tid & 3;  // 4 lanes per sample, 4 groups each
+                const double2 e1 = E1[sl];
+                int kc = ((4 * q) * CPT + 1) >> 1;
+                double2 z = cpowi(e1, kc);
+#pragma unroll
+                for (int g = 4 * q; g < 4 * q + 4; ++g) {
+                    const int k0 = (g * CPT + 1) >> 1;
+                    if (k0 > kc) {
+                        z = cmul(z, cpowi(e1, k0 - kc));
+                        kc = k0;
+                    }
+                    Eg[sl * 16 + g] = z;
+                }
+            }
+            __syncthreads();
 
             const int c0 = cg * CPT;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int sl = 4 * sg + q;
-                const double ps = Psi[sl];
                 const double2 e1 = E1[sl];
+                double2 z = Eg[sl * 16 + cg];
                 int k = (c0 + 1) >> 1;
-                double sn, cs;
-                sincos((double)k * ps, &sn, &cs);
                 T part = (T)0;
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) {
@@ -193,12 +223,10 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                             part += acc[q][j];
                         } else {
                             if (((c + 1) >> 1) > k) {
-                                const double cn = cs * e1.x - sn * e1.y;
-                                sn = sn * e1.x + cs * e1.y;
-                                cs = cn;
+                                z = cmul(z, e1);
                                 ++k;
                             }
-                            part = fma((T)((c & 1) ? cs : sn), acc[q][j], part);
+                            part = fma((T)((c & 1) ? z.x : z.y), acc[q][j], part);
                         }
                     }
                 }
@@ -216,7 +244,8 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
 template <typename T, int CPT>
 hipError_t launch_binned(sc_plan *p, void *tod) {
     constexpr int NC = 16 * CPT;
-    const size_t lds = sizeof(T) * (64 * NC + 64 * 64 + 64 * 16) + 64 * (sizeof(double) + sizeof(double2) + sizeof(int));
+    static_assert(64 * 64 * sizeof(T) >= 64 * 16 * sizeof(double2), "group table must fit the weight area");
+    const size_t lds = sizeof(T) * (64 * NC + 64 * 64 + 64 * 16) + 64 * (sizeof(double2) + sizeof(int));
     auto kern = k_gather_binned<T, CPT>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -246,6 +275,169 @@ hipError_t launch_binned_t(sc_plan *p, void *tod) {
     return launch_binned<T, 16>(p, tod);
 }
 
+
+// ---------------------------------------------------------------------------
+// Binned gather on the matrix cores (FP32 maps).  Same work items, LDS staging
+// and weights as k_gather_binned; the per-chunk product
+//     X[s][c] = sum_{t < 64} w_s(t) P[t][c]     (64 samples x 16 CT comps x 64 taps)
+// runs as v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation): wave w
+// owns samples 16w .. 16w+15 and all CT component tiles.  Operand layout of
+// the 16x16x4 instruction: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16(i/4), register i%4.
+// Lane (r = lane%16, grp = lane/16) therefore holds components c = 16 ct + r of
+// samples 16w + 4 grp + v (v < 4): its orders are k = 8 ct + (r+1)/2, so the
+// k-sum needs e^{i k0 psi} (k0 = (r+1)/2 <= 8, from a per-sample table) and one
+// FP64 rotation by e^{i 8 psi} per component tile.
+template <int CT>
+__global__ void __launch_bounds__(256)
+k_gather_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt,
+              const float *__restrict__ maps, float *__restrict__ tod, int cols, int ncp, int ncomp, int nkc,
+              double beta) {
+    constexpr int NC = 16 * CT;
+    extern __shared__ double smem_d[];
+    float *Psh = (float *)smem_d;         // [64 taps][NC]
+    float *Wsh = Psh + 64 * NC;           // [64 taps][64 samples]; Z0 table after the product
+    double2 *Z0 = (double2 *)Wsh;         // [64 samples][9]: e^{i k psi}, k = 0..8
+    float *W1 = Wsh + 64 * 64;            // [16][64 samples]
+    double2 *E8 = (double2 *)(W1 + 64 * 16);  // [64] e^{i 8 psi}
+    double *Psi = (double *)(E8 + 64);        // [64]
+    int *Idx = (int *)(Psi + 64);             // [64]
+    __shared__ int item_sh;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, grp = lane >> 4;
+    const int nitems = totals[1];
+    const float fbeta = (float)beta;
+    for (;;) {
+        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
+        __syncthreads();
+        const int it = item_sh;
+        if (it >= nitems) break;
+        const int4 item = items[it];
+        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
+        for (int e = tid; e < 64 * NC; e += 256) {
+            const int t = e / NC, c = e - t * NC;
+            float v = 0.f;
+            if (c < ncp) v = maps[((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp + c];
+            Psh[e] = v;
+        }
+        for (int ch = 0; ch < item.z; ch += 64) {
+            const int ns = item.z - ch < 64 ? item.z - ch : 64;
+            const int pos0 = item.y + ch;
+            for (int e = tid; e < 64 * 16; e += 256) {
+                const int q = e >> 6, sl = e & 63;
+                float w = 0.f;
+                if (sl < ns) {
+                    const float f = (q < 8) ? (float)srt.fu[pos0 + sl] : (float)srt.fv[pos0 + sl];
+                    w = es_weight<float>((f + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                }
+                W1[e] = w;
+            }
+            if (tid < 64) {
+                double ps = 0.0;
+                int ix = -1;
+                if (tid < ns) {
+                    ps = srt.psi[pos0 + tid];
+                    ix = srt.idx[pos0 + tid];
+                }
+                Psi[tid] = ps;
+                Idx[tid] = ix;
+            }
+            __syncthreads();
+            for (int e = tid; e < 64 * 64; e += 256) {
+                const int t = e >> 6, sl = e & 63;
+                Wsh[e] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
+            }
+            __syncthreads();
+
+            floatx4 acc[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const float *wa = Wsh + grp * 64 + 16 * wv + r;  // A[i = r][k = grp] of sample tile wv
+            const float *pb = Psh + grp * NC + r;            // B[k = grp][j = r] of component tile 0
+#pragma unroll 2
+            for (int ks = 0; ks < 16; ++ks) {
+                const float a = wa[ks * 4 * 64];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, pb[ks * 4 * NC + 16 * ct], acc[ct], 0, 0, 0);
+            }
+            __syncthreads();  // Wsh is dead: per-sample e^{i k psi} table in its place
+            if (tid < 64) {
+                double sn, cs;
+                sincos(Psi[tid], &sn, &cs);
+                const double2 e1 = make_double2(cs, sn);
+                double2 z = make_double2(1.0, 0.0);
+#pragma unroll
+                for (int k = 0; k <= 8; ++k) {
+                    Z0[tid * 9 + k] = z;
+                    if (k < 8) z = cmul(z, e1);
+                }
+                E8[tid] = z;
+            }
+            __syncthreads();
+
+            const int k0 = (r + 1) >> 1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int sl = 16 * wv + 4 * grp + v;
+                double2 z = Z0[sl * 9 + k0];
+                const double2 e8 = E8[sl];
+                float part = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const int c = 16 * ct + r;
+                    const float x = acc[ct][v];
+                    if (c < ncomp) part = fmaf(c == 0 ? 1.f : (float)((c & 1) ? z.x : z.y), x, part);
+                    if (ct + 1 < CT) z = cmul(z, e8);
+                }
+                part += __shfl_xor(part, 8);
+                part += __shfl_xor(part, 4);
+                part += __shfl_xor(part, 2);
+                part += __shfl_xor(part, 1);
+                if (r == 0 && sl < ns) tod[Idx[sl]] = part;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int CT>
+hipError_t launch_mfma(sc_plan *p, void *tod) {
+    constexpr int NC = 16 * CT;
+    static_assert(64 * 64 * sizeof(float) >= 64 * 9 * sizeof(double2), "Z0 table must fit the weight area");
+    const size_t lds = sizeof(float) * (64 * NC + 64 * 64 + 64 * 16) +
+                       64 * (sizeof(double2) + sizeof(double) + sizeof(int));
+    auto kern = k_gather_mfma<CT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 256;
+    const BinGeom g = sc_bin_geom(p);
+    hipLaunchKernelGGL(kern, dim3(per_cu * ncu), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
+                       p->bw.sorted, (const float *)p->maps, (float *)tod, p->cols, p->ncp, p->ncomp, g.nkc,
+                       p->beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_any(sc_plan *p, void *tod) {
+    const int ct = (p->ncomp + 15) / 16;
+    if (ct <= 1) return launch_mfma<1>(p, tod);
+    if (ct <= 2) return launch_mfma<2>(p, tod);
+    if (ct <= 3) return launch_mfma<3>(p, tod);
+    if (ct <= 5) return launch_mfma<5>(p, tod);
+    if (ct <= 9) return launch_mfma<9>(p, tod);
+    if (ct <= 13) return launch_mfma<13>(p, tod);
+    return launch_mfma<16>(p, tod);
+}
+
 }  // namespace
 
 // W = 8 only; the FP64 staging of 208+ components would exceed the 160 KiB of LDS.
@@ -255,7 +447,8 @@ bool sc_gather_binned_supported(const sc_plan *p) {
 
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod) {
     if (p->prec == SC_FP64) return launch_binned_t<double>(p, tod);
-    return launch_binned_t<float>(p, tod);
+    if (p->gather_valu) return launch_binned_t<float>(p, tod);
+    return launch_mfma_any(p, tod);
 }
 
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod) {

@@ -58,6 +58,27 @@ constexpr int REC_STEP = 1200;  // rescaling exponent step
 constexpr double REC_BIG = 0x1p600;
 constexpr double REC_DOWN = 0x1p-1200;
 
+// One recursion step for every ring of the lane: contract d^l (its true value
+// d * 2^{1200 e}; below 2^-600 while e < 0, i.e. nothing) and advance to d^{l+1}.
+template <int RPT>
+__device__ __forceinline__ void rec_step(int t, const double *cA, const double *cB, const double *cC,
+                                         const double2 *cWp, const double2 *cWm, const double *x, double *d,
+                                         double *dp, const int *e, double2 *fp, double2 *fm) {
+    const double A = cA[t], B = cB[t], C = cC[t];
+    const double2 wp = cWp[t], wm = cWm[t];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const double dd = ldexp(d[r], REC_STEP * e[r]);
+        fp[r].x = fma(wp.x, dd, fp[r].x);
+        fp[r].y = fma(wp.y, dd, fp[r].y);
+        fm[r].x = fma(wm.x, dd, fm[r].x);
+        fm[r].y = fma(wm.y, dd, fm[r].y);
+        const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
+        dp[r] = d[r];
+        d[r] = dn;
+    }
+}
+
 template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
@@ -138,20 +159,15 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         }
         __syncthreads();
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
-        for (int t = 0; t < nl; ++t) {
-            const double A = cA[t], B = cB[t], C = cC[t];
-            const double2 wp = cWp[t], wm = cWm[t];
+        // Rescaling is checked once per 8 steps: one step grows |d| by at most
+        // ~2^10 (alpha_l <= l0 + 1), far inside the 2^424 left below overflow.
+        for (int t0 = 0; t0 < nl; t0 += 8) {
+            const int t1 = t0 + 8 < nl ? t0 + 8 : nl;
+#pragma unroll 2
+            for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cC, cWp, cWm, x, d, dp, e, fp, fm);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                const double dd = (e[r] == 0) ? d[r] : 0.0;
-                fp[r].x = fma(wp.x, dd, fp[r].x);
-                fp[r].y = fma(wp.y, dd, fp[r].y);
-                fm[r].x = fma(wm.x, dd, fm[r].x);
-                fm[r].y = fma(wm.y, dd, fm[r].y);
-                const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
-                dp[r] = d[r];
-                d[r] = dn;
-                if (fabs(dn) > REC_BIG) {
+                if (fabs(d[r]) > REC_BIG) {
                     d[r] *= REC_DOWN;
                     dp[r] *= REC_DOWN;
                     e[r] += 1;
@@ -172,24 +188,38 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 
 }  // namespace
 
+#define SC_RING_CASE(R)                                                                                      \
+    case R:                                                                                                  \
+        hipLaunchKernelGGL(k_ring_sums<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,         \
+                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,      \
+                           p->ngroups);                                                                      \
+        break;
+
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm) {
     const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups;
     switch (p->rpt) {
-        case 2:
-            hipLaunchKernelGGL(k_ring_sums<2>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
-                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
-                               p->ngroups);
-            break;
-        case 4:
-            hipLaunchKernelGGL(k_ring_sums<4>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
-                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
-                               p->ngroups);
-            break;
+        SC_RING_CASE(1)
+        SC_RING_CASE(2)
+        SC_RING_CASE(3)
         default:
-            hipLaunchKernelGGL(k_ring_sums<8>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,
-                               (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,
-                               p->ngroups);
-            break;
+        SC_RING_CASE(4)
     }
     return hipGetLastError();
+}
+
+// Rings per lane: the fewest wasted lane slots with at most 4 rings per lane
+// (more rings per lane spill registers).
+void sc_choose_ring_layout(int nring, int *rpt, int *ngroups) {
+    int best_r = 1, best_g = (nring + 63) / 64, best_w = 1 << 30;
+    for (int r = 4; r >= 1; --r) {
+        const int g = (nring + 64 * r - 1) / (64 * r);
+        const int waste = g * 64 * r - nring;
+        if (waste < best_w) {
+            best_w = waste;
+            best_r = r;
+            best_g = g;
+        }
+    }
+    *rpt = best_r;
+    *ngroups = best_g;
 }

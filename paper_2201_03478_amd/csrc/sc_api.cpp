@@ -224,12 +224,12 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     {
         const char *g = std::getenv("SC_GATHER_PATH");
         p->gather_direct = (g && std::strcmp(g, "direct") == 0) ? 1 : 0;
+        p->gather_valu = (g && std::strcmp(g, "valu") == 0) ? 1 : 0;
         const char *b = std::getenv("SC_BIN_PASS_MAX");
         long long v = b ? std::atoll(b) : 0;
         p->bin_pass_max = (v > 0 && v < BIN_PASS_MAX) ? (int64_t)v : (int64_t)BIN_PASS_MAX;
     }
-    p->rpt = p->nring <= 128 ? 2 : (p->nring <= 256 ? 4 : 8);
-    p->ngroups = (p->nring + 64 * p->rpt - 1) / (64 * p->rpt);
+    sc_choose_ring_layout(p->nring, &p->rpt, &p->ngroups);
     if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
         delete p;
         return fail(SC_EINVAL, "lmax = %d needs transforms longer than 4096 points (not supported)", lmax);

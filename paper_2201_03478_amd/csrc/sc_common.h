@@ -83,6 +83,7 @@ struct sc_plan {
     size_t ws_bytes;
     BinWork bw;
     int gather_direct;     // force the per-sample gather (env SC_GATHER_PATH=direct)
+    int gather_valu;       // FP32 binned gather on the VALU instead of MFMA (env SC_GATHER_PATH=valu)
     int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
 
     // per-kernel event timing (see sc_plan_enable_timing)
@@ -104,6 +105,7 @@ static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_
 // ---------------------------------------------------------------- launchers
 hipError_t sc_launch_tables(sc_plan *p);
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
+void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_theta_upsample(sc_plan *p);
 hipError_t sc_launch_phi_synthesis(sc_plan *p);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);

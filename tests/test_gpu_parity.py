@@ -194,7 +194,10 @@ def test_binned_gather_edge_cases(torch_dev, api, oracle_lib, prec):
 
     binned = _run_env({"SC_BIN_PASS_MAX": "1000"}, run)  # 4 passes, ragged last pass
     direct = _run_env({"SC_GATHER_PATH": "direct"}, run)
+    valu = _run_env({"SC_GATHER_PATH": "valu"}, run)  # FP32: VALU product instead of MFMA
     ref = oracle_lib.convolve(a, b, L, K, p)
     tol_same = 1e-6 if prec != "fp64" else 1e-13
     assert np.max(np.abs(binned - direct)) <= tol_same * np.max(np.abs(ref))
-    assert _rel_l2(binned, ref) <= (1e-6 if prec != "fp64" else 1e-7)
+    assert np.max(np.abs(valu - direct)) <= tol_same * np.max(np.abs(ref))
+    for got in (binned, direct, valu):
+        assert _rel_l2(got, ref) <= (1e-6 if prec != "fp64" else 1e-7)
