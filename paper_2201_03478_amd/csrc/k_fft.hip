@@ -28,8 +28,9 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
                  const double *__restrict__ dphi) {
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
-    const int k = blockIdx.x / nm;
-    const int mi = blockIdx.x - k * nm;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive m share an XCD
+    const int k = blk / nm;
+    const int mi = blk - k * nm;
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
@@ -71,8 +72,10 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
                 int W, FftPlan Pp, const double2 *__restrict__ twp) {
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
-    const int k = blockIdx.x / rows;
-    const int row = blockIdx.x - k * rows;
+    const int nk = gridDim.x / rows;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive k of one row share an XCD
+    const int row = blk / nk;
+    const int k = blk - row * nk;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int np = Pp.n;
     double2 *A = sbuf;

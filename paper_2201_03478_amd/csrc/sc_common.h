@@ -126,6 +126,16 @@ static inline BinGeom sc_bin_geom(const sc_plan *p) {
 }
 
 // ------------------------------------------------------------ device helpers
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap the hardware block index so that consecutive logical indices run on
+// the same XCD at about the same time: their partial-line writes to
+// neighbouring addresses then merge in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int x = b & 7, i = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
