@@ -132,6 +132,24 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax,
                 const double *ptg, int64_t n, void *tod, int precision, void *stream);
 
 /*
+ * Adjoint of the convolution with respect to the sky coefficients (the
+ * transpose of every stage above: scatter of the TOD gradient onto gradient
+ * maps, adjoint phi and theta transforms, adjoint Wigner-d ring sums).  For a
+ * TOD gradient y it returns g_lm = dL/dRe(a_lm) + i dL/dIm(a_lm) of
+ * L = sum_t y_t c_t, i.e. <y, A a> = Re sum_{l, m >= 0} conj(g_lm) a_lm;
+ * g_l0 is real.  This is torch's complex-gradient convention.
+ *   blm       device complex128, the beam the plan's maps were made with.
+ *   ptg       device float64 [n][3].
+ *   tod_grad  device float64 [n] (SC_FP64) or float32 [n].
+ *   alm_grad  device complex128, alm layout (overwritten).
+ * The scatter accumulates with floating-point atomics, so the last bits vary
+ * between runs.  Uses (and overwrites) the plan's transform buffers; the maps
+ * made by sc_set_sky_beam are kept.
+ */
+int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
+                        double *alm_grad);
+
+/*
  * Device-side numerical details for tests: copies internal stage buffers to
  * the caller's device memory.  which = 0: ring sums F (complex128
  * [kmax+1][2 lmax+1][n_rings], F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j),
@@ -148,8 +166,9 @@ int64_t sc_debug_copy_stage(sc_plan *plan, int which, void *dst, int64_t capacit
  * ms[s] (total milliseconds) and launches[s] for the first nstage stages, and
  * clears the records.  Stages: 0 ring sums (recursion + contraction),
  * 1 theta upsampling, 2 phi synthesis, 3 interpolation + k-sum, 4 pointing
- * binning (anchor keys, scan, scatter, work items).
- * Returns the number of stages (5).
+ * binning (anchor keys, scan, scatter, work items), 5 adjoint scatter,
+ * 6 adjoint transforms, 7 adjoint ring sums.
+ * Returns the number of stages (8).
  */
 int sc_plan_enable_timing(sc_plan *plan, int enable);
 int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage);

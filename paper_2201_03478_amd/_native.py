@@ -18,7 +18,7 @@ SC_FP64, SC_F64MAPS_F32GATHER = 0, 1
 
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",
-    "sc_interpolate", "sc_convolve", "sc_debug_copy_stage", "sc_plan_enable_timing",
+    "sc_interpolate", "sc_convolve", "sc_convolve_adjoint", "sc_debug_copy_stage", "sc_plan_enable_timing",
     "sc_plan_stage_times", "sc_strerror", "sc_last_error",
 )
 
@@ -49,6 +49,7 @@ def load():
     lib.sc_set_sky_beam.argtypes = [vp, vp, vp]
     lib.sc_interpolate.argtypes = [vp, vp, i64, vp]
     lib.sc_convolve.argtypes = [vp, vp, i32, i32, vp, i64, vp, i32, vp]
+    lib.sc_convolve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.sc_debug_copy_stage.argtypes = [vp, i32, vp, i64]
     lib.sc_debug_copy_stage.restype = i64
     lib.sc_plan_enable_timing.argtypes = [vp, i32]

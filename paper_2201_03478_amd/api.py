@@ -101,7 +101,27 @@ class Plan:
             N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
         return out
 
-    STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather", "binning")
+    def adjoint(self, blm: torch.Tensor, ptg: torch.Tensor, tod_grad: torch.Tensor,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """sc_convolve_adjoint: g_lm = dL/dRe a_lm + i dL/dIm a_lm of L = sum_t y_t c_t (complex128)."""
+        _dev(blm, "blm", torch.complex128)
+        _dev(ptg, "ptg", torch.float64)
+        _dev(tod_grad, "tod_grad", self.tod_dtype)
+        if blm.numel() != n_alm(self.lmax, self.kmax):
+            raise ValueError("blm size does not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
+        n = ptg.shape[0]
+        if tod_grad.numel() != n:
+            raise ValueError("tod_grad has %d entries, need %d" % (tod_grad.numel(), n))
+        if out is None:
+            out = torch.empty(n_alm(self.lmax), dtype=torch.complex128, device=ptg.device)
+        _dev(out, "alm_grad", torch.complex128)
+        self.set_stream()
+        N.check(self._lib.sc_convolve_adjoint(self._p, blm.data_ptr(), ptg.data_ptr(), tod_grad.data_ptr(), n,
+                                              out.data_ptr()), "sc_convolve_adjoint")
+        return out
+
+    STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather", "binning", "scatter",
+              "adjoint_transforms", "adjoint_ring_sums")
 
     def enable_timing(self, enable: bool = True):
         N.check(self._lib.sc_plan_enable_timing(self._p, 1 if enable else 0), "sc_plan_enable_timing")
@@ -146,3 +166,32 @@ def convolve(alm: torch.Tensor, blm: torch.Tensor, lmax: int, kmax: int, ptg: to
     N.check(lib.sc_convolve(alm.data_ptr(), blm.data_ptr(), int(lmax), int(kmax), ptg.data_ptr(), n,
                             out.data_ptr(), p, ctypes.c_void_p(_stream_handle())), "sc_convolve")
     return out
+
+
+class SidelobeConv(torch.autograd.Function):
+    """tod = A(alm) for a fixed beam and pointing; backward is the library's adjoint.
+
+    Gradients follow torch's complex convention dL/dRe + i dL/dIm (what
+    sc_convolve_adjoint returns); beam and pointing gradients are not provided.
+    """
+
+    @staticmethod
+    def forward(ctx, alm, blm, ptg, plan):
+        plan.set_sky_beam(alm.detach(), blm.detach())
+        tod = plan.interpolate(ptg.detach())
+        ctx.plan = plan
+        ctx.save_for_backward(blm, ptg)
+        return tod
+
+    @staticmethod
+    def backward(ctx, g):
+        blm, ptg = ctx.saved_tensors
+        grad = None
+        if ctx.needs_input_grad[0]:
+            grad = ctx.plan.adjoint(blm.detach(), ptg.detach(), g.detach().to(ctx.plan.tod_dtype).contiguous())
+        return grad, None, None, None
+
+
+def sidelobe_convolve(alm: torch.Tensor, blm: torch.Tensor, ptg: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable convolution (gradient with respect to alm)."""
+    return SidelobeConv.apply(alm, blm, ptg, plan)

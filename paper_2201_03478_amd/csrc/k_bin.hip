@@ -166,7 +166,26 @@ __global__ void k_bin_items(const int *__restrict__ count, const int2 *__restric
     }
 }
 
+__global__ void k_zero_words(uint4 *a, int64_t nw) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_zero_bytes(unsigned char *a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
 }  // namespace
+
+// Zero a device buffer with a kernel (no memset node if the caller captures a graph).
+hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream) {
+    const int64_t nw = (int64_t)(bytes / 16);
+    if (nw > 0) hipLaunchKernelGGL(k_zero_words, dim3(2048), dim3(256), 0, stream, (uint4 *)dst, nw);
+    const int64_t tail = (int64_t)(bytes - 16 * (size_t)nw);
+    if (tail > 0) hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, stream, (unsigned char *)dst + 16 * nw, tail);
+    return hipGetLastError();
+}
 
 hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
     BinWork &w = p->bw;

@@ -105,6 +105,106 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoints of the two transform stages (for the gradient with respect to the
+// sky coefficients).  With <u, v> = Re sum conj(u) v on complex arrays:
+//
+//  phi: T_k(row, q) = sum_m G(row, m) e^{i m q h_phi} and the stored real maps
+//    M_0 = Re T_0, M_{2k-1} = 2 Re T_k, M_{2k} = -2 Im T_k (wrap columns are
+//    copies).  Given map gradients GM, U_k = 2 (GM_{2k-1} - i GM_{2k})
+//    (U_0 = GM_0), wrap columns folded onto q mod nphi; then
+//    Gadj(row, m) = sum_q e^{-i m q h_phi} U(q)  (forward FFT).
+//  theta: G(r) = sum_n e^{i n r h} D_phi(m) p(n) X(n), X = FFT_{n2}(f),
+//    f the parity-extended column; so Y(n) = sum_r e^{-i n r h} Gadj(r)
+//    (forward FFT of the rows placed at r mod n2os), X_adj(n) =
+//    conj(p(n)) D_phi(m) Y(n), f_adj = inverse FFT_{n2}(X_adj) and
+//    F_adj(j) = f_adj(j) + (-1)^{m-k} f_adj(n2 - 1 - j).
+template <typename T>
+__global__ void __launch_bounds__(SC_FFT_NT)
+k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, int rows, int cols, int ncp, int W,
+              FftPlan Pp, const double2 *__restrict__ twp) {
+    extern __shared__ double2 sbuf[];
+    const int nm = 2 * lmax + 1;
+    const int nk = gridDim.x / rows;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int row = blk / nk;
+    const int k = blk - row * nk;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int np = Pp.n;
+    const int q0 = -W / 2 + 1;
+    double2 *A = sbuf;
+    const T *src = gmaps + (size_t)row * cols * ncp;
+    // columns q = 0 .. np-1 appear once at col = q - q0; the rest are wrap copies
+    for (int q = tid; q < np; q += nth) {
+        const T *o = src + (size_t)(q - q0) * ncp;
+        A[q] = k == 0 ? make_double2((double)o[0], 0.0)
+                      : make_double2(2.0 * (double)o[2 * k - 1], -2.0 * (double)o[2 * k]);
+    }
+    __syncthreads();
+    if (tid < W - 1) {
+        // the W - 1 wrap copies: cols [0, W/2 - 1) and [nphi + W/2 - 1, cols); distinct q
+        const int col = tid < W / 2 - 1 ? tid : np + tid;
+        const int q = col + q0;
+        const int qq = q < 0 ? q + np : q - np;
+        const T *o = src + (size_t)col * ncp;
+        if (k == 0) {
+            A[qq].x += (double)o[0];
+        } else {
+            A[qq].x += 2.0 * (double)o[2 * k - 1];
+            A[qq].y -= 2.0 * (double)o[2 * k];
+        }
+    }
+    __syncthreads();
+    fft_lds<-1>(A, Pp, twp, tid, nth);
+    double2 *dst = G + ((size_t)k * rows + row) * nm;
+    for (int t = tid; t < nm; t += nth) {
+        const int m = t - lmax;
+        dst[t] = A[m < 0 ? m + np : m];
+    }
+}
+
+__global__ void __launch_bounds__(SC_FFT_NT)
+k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax, int nring, int rows, int W,
+                FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2, const double2 *__restrict__ twos,
+                const double2 *__restrict__ phase, const double *__restrict__ dphi) {
+    extern __shared__ double2 sbuf[];
+    const int nm = 2 * lmax + 1;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = blk / nm;
+    const int mi = blk - k * nm;
+    const int m = mi - lmax;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int n2 = P2.n, nos = Pos.n;
+    double2 *A = sbuf;       // length n2
+    double2 *B = sbuf + n2;  // length nos
+    for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
+    for (int t = tid; t < n2; t += nth) A[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int r0 = -W / 2 + 1;
+    for (int row = tid; row < rows; row += nth) {
+        int r = row + r0;
+        r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
+        B[r] = G[((size_t)k * rows + row) * nm + mi];  // rows land on distinct indices
+    }
+    __syncthreads();
+    fft_lds<-1>(B, Pos, twos, tid, nth);
+    const double dm = dphi[m < 0 ? -m : m];
+    for (int t = tid; t < nm; t += nth) {
+        const int n = t - lmax;
+        const double2 y = B[n < 0 ? n + nos : n];
+        A[n < 0 ? n + n2 : n] = cscale(cmul(cconj(phase[t]), y), dm);
+    }
+    __syncthreads();
+    fft_lds<1>(A, P2, tw2, tid, nth);
+    const double sg = ((m - k) & 1) ? -1.0 : 1.0;
+    double2 *col = F + ((size_t)k * nm + mi) * nring;
+    for (int j = tid; j < nring; j += nth) {
+        const double2 a = A[j], b = A[n2 - 1 - j];
+        col[j] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+    }
+}
+
 }  // namespace
 
 hipError_t sc_launch_theta_upsample(sc_plan *p) {
@@ -124,5 +224,25 @@ hipError_t sc_launch_phi_synthesis(sc_plan *p) {
     else
         hipLaunchKernelGGL(k_phi_synthesis<float>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G,
                            (float *)p->maps, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {
+    const int nblk = (p->kmax + 1) * p->rows;
+    const size_t lds = sizeof(double2) * (size_t)p->nphi;
+    if (p->prec == SC_FP64)
+        hipLaunchKernelGGL(k_phi_adjoint<double>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream,
+                           (const double *)gmaps, p->G, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    else
+        hipLaunchKernelGGL(k_phi_adjoint<float>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream,
+                           (const float *)gmaps, p->G, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_theta_adjoint(sc_plan *p) {
+    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
+    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
+    hipLaunchKernelGGL(k_theta_adjoint, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G, p->F, p->lmax, p->nring,
+                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
     return hipGetLastError();
 }

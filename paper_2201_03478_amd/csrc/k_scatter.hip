@@ -1,0 +1,267 @@
+// k_scatter.hip -- adjoint of the interpolation + k-sum (scatter to gradient maps).
+//
+// The gather computes c_t = sum_{taps} w_t(tap) sum_c basis_c(psi_t) M_c[tap]
+// (k_gather.hip).  Its adjoint for a TOD gradient y is
+//     GM_c[p] = sum_t y_t w_t(p) basis_c(psi_t)
+// over the samples whose stencil covers map pixel p.  Different samples and
+// anchors add into the same pixels, so the result is accumulated with
+// hardware floating-point atomics (order-dependent rounding, Z15).
+//
+//  * k_scatter_mfma (FP32 maps, W = 8): per work item (samples of one anchor,
+//    k_bin.hip) the 64 x ncomp patch gradient PG[t][c] = sum_s w_s(t) V[s][c],
+//    V[s][c] = y_s basis_c(psi_s), is a v_mfma_f32_16x16x4_f32 product summed
+//    over all chunks of the item, then added to the maps with one atomic per
+//    (tap, component).
+//  * k_scatter_direct (any W, FP32 or FP64): one wave per sample, lanes over
+//    components, one atomic per (tap, component, sample).
+#include "sc_common.h"
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T es_w(T z, T beta) {
+    const T q = (T)1 - z * z;
+    return q > (T)0 ? exp(beta * (sqrt(q) - (T)1)) : (T)0;
+}
+
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+__device__ __forceinline__ double2 cpow_int(double2 z, int n) {
+    double2 r = make_double2(1.0, 0.0);
+    while (n) {
+        if (n & 1) r = cmul(r, z);
+        z = cmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_scatter_direct(const double *__restrict__ ptg, int64_t n, const T *__restrict__ y, T *__restrict__ gmaps, int cols,
+                 int ncp, int ncomp, int W, double beta, double inv_hth, double inv_hph, int n2os, int nphi) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int half = W / 2;
+    const double two_pi = 6.283185307179586477;
+    for (int64_t s = wave; s < n; s += nwaves) {
+        const double th = ptg[3 * s], ph = ptg[3 * s + 1], ps = ptg[3 * s + 2];
+        double u = th * inv_hth;
+        u = fmin(fmax(u, 0.0), 0.5 * (double)n2os);
+        const int r0 = (int)floor(u) - half + 1;
+        double v = (ph - two_pi * floor(ph / two_pi)) * inv_hph;
+        if (!(v < (double)nphi) || v < 0.0) v = 0.0;
+        const int q0 = (int)floor(v) - half + 1;
+        T w = (T)0;
+        if (lane < W)
+            w = es_w<T>((T)((u - (double)(r0 + lane)) / half), (T)beta);
+        else if (lane < 2 * W)
+            w = es_w<T>((T)((v - (double)(q0 + lane - W)) / half), (T)beta);
+        const double psr = ps - two_pi * floor(ps / two_pi);
+        const T ys = y[s];
+        T val[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = lane + 64 * t;
+            T bas = (T)0;
+            if (c < ncomp) {
+                bas = (T)1;
+                if (c > 0) {
+                    double sn, cs;
+                    sincos((double)((c + 1) >> 1) * psr, &sn, &cs);
+                    bas = (T)((c & 1) ? cs : sn);
+                }
+            }
+            val[t] = ys * bas;
+        }
+        const int row0 = r0 + half - 1, col0 = q0 + half - 1;
+        for (int i = 0; i < W; ++i) {
+            const T wi = __shfl(w, i);
+            for (int j = 0; j < W; ++j) {
+                const T wij = wi * __shfl(w, W + j);
+                T *base = gmaps + ((size_t)(row0 + i) * cols + (col0 + j)) * ncp;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int c = lane + 64 * t;
+                    if (c < ncomp) atomic_add(base + c, wij * val[t]);
+                }
+            }
+        }
+    }
+}
+
+constexpr int WROW = 68;  // (4 tap + sample) mod 64 banks: distinct over a wave
+
+template <int CT>
+__global__ void __launch_bounds__(256)
+k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt, const float *__restrict__ y,
+               float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
+    constexpr int NC = 16 * CT;
+    extern __shared__ double smem_d[];
+    float *Vsh = (float *)smem_d;     // [64 samples][NC]
+    float *Wsh = Vsh + 64 * NC;       // [64 taps][WROW]: 64 samples + pad (conflict-free A reads)
+    float *W1 = Wsh + 64 * WROW;      // [16][64 samples]
+    double2 *E1 = (double2 *)(W1 + 64 * 16);  // [64] e^{i psi}
+    float *Ys = (float *)(E1 + 64);           // [64]
+    __shared__ int item_sh;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, grp = lane >> 4;
+    const int nitems = totals[1];
+    const float fbeta = (float)beta;
+    for (;;) {
+        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
+        __syncthreads();
+        const int it = item_sh;
+        if (it >= nitems) break;
+        const int4 item = items[it];
+        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
+        floatx4 acc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ch = 0; ch < item.z; ch += 64) {
+            const int ns = item.z - ch < 64 ? item.z - ch : 64;
+            const int pos0 = item.y + ch;
+            for (int e = tid; e < 64 * 16; e += 256) {
+                const int q = e >> 6, sl = e & 63;
+                float w = 0.f;
+                if (sl < ns) {
+                    const float f = (q < 8) ? (float)srt.fu[pos0 + sl] : (float)srt.fv[pos0 + sl];
+                    w = es_w<float>((f + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                }
+                W1[e] = w;
+            }
+            if (tid < 64) {
+                double ps = 0.0;
+                float yy = 0.f;
+                if (tid < ns) {
+                    ps = srt.psi[pos0 + tid];
+                    yy = y[srt.idx[pos0 + tid]];
+                }
+                double sn, cs;
+                sincos(ps, &sn, &cs);
+                E1[tid] = make_double2(cs, sn);
+                Ys[tid] = yy;
+            }
+            __syncthreads();
+            for (int e = tid; e < 64 * 64; e += 256) {
+                const int t = e >> 6, sl = e & 63;
+                Wsh[t * WROW + sl] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
+            }
+            {
+                // V[s][c] = y_s basis_c(psi_s): 4 lanes per sample, NC/4 components each
+                const int sl = tid >> 2, qq = tid & 3;
+                constexpr int PER = NC / 4;
+                const int c0 = qq * PER;
+                const double2 e1 = E1[sl];
+                const float yy = Ys[sl];
+                int kc = (c0 + 1) >> 1;
+                double2 z = cpow_int(e1, kc);
+                float *vrow = Vsh + sl * NC;
+                for (int j = 0; j < PER; ++j) {
+                    const int c = c0 + j;
+                    float vv = 0.f;
+                    if (c < ncomp) {
+                        if (c == 0) {
+                            vv = yy;
+                        } else {
+                            if (((c + 1) >> 1) > kc) {
+                                z = cmul(z, e1);
+                                ++kc;
+                            }
+                            vv = yy * (float)((c & 1) ? z.x : z.y);
+                        }
+                    }
+                    vrow[c] = vv;
+                }
+            }
+            __syncthreads();
+            // PG[tap][c] += sum_s W[tap][s] V[s][c]: wave wv owns taps 16 wv .. 16 wv + 15
+            const float *wa = Wsh + (16 * wv + r) * WROW + grp;  // A[i = tap r][k = sample grp]
+            const float *vb = Vsh + grp * NC + r;              // B[k = sample grp][j = comp r]
+#pragma unroll 2
+            for (int ks = 0; ks < 16; ++ks) {
+                const float a = wa[4 * ks];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, vb[4 * ks * NC + 16 * ct], acc[ct], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int t = 16 * wv + 4 * grp + v;
+            float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int c = 16 * ct + r;
+                if (c < ncomp) atomic_add(base + c, acc[ct][v]);
+            }
+        }
+    }
+}
+
+template <int CT>
+hipError_t launch_scatter_mfma(sc_plan *p, const void *y, void *gmaps) {
+    constexpr int NC = 16 * CT;
+    const size_t lds = sizeof(float) * (64 * NC + 64 * WROW + 64 * 16) + 64 * (sizeof(double2) + sizeof(float));
+    auto kern = k_scatter_mfma<CT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 256;
+    const BinGeom g = sc_bin_geom(p);
+    hipLaunchKernelGGL(kern, dim3(per_cu * ncu), dim3(256), lds, p->stream, p->bw.items, p->bw.totals, p->bw.sorted,
+                       (const float *)y, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_mfma_any(sc_plan *p, const void *y, void *gmaps) {
+    const int ct = (p->ncomp + 15) / 16;
+    if (ct <= 1) return launch_scatter_mfma<1>(p, y, gmaps);
+    if (ct <= 2) return launch_scatter_mfma<2>(p, y, gmaps);
+    if (ct <= 3) return launch_scatter_mfma<3>(p, y, gmaps);
+    if (ct <= 5) return launch_scatter_mfma<5>(p, y, gmaps);
+    if (ct <= 9) return launch_scatter_mfma<9>(p, y, gmaps);
+    if (ct <= 13) return launch_scatter_mfma<13>(p, y, gmaps);
+    return launch_scatter_mfma<16>(p, y, gmaps);
+}
+
+}  // namespace
+
+bool sc_scatter_binned_supported(const sc_plan *p) {
+    return p->prec != SC_FP64 && p->W == 8 && p->ncomp <= 256 && !p->gather_direct;
+}
+
+// Scatter of one pass (binned: binning already done for these samples).
+hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps) {
+    return launch_scatter_mfma_any(p, y, gmaps);
+}
+
+hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps) {
+    const double two_pi = 6.283185307179586477;
+    const double inv_hth = (double)p->n2os / two_pi, inv_hph = (double)p->nphi / two_pi;
+    int64_t nblk = (n + 3) / 4;
+    if (nblk > 65536) nblk = 65536;
+    if (p->prec == SC_FP64)
+        hipLaunchKernelGGL(k_scatter_direct<double>, dim3((unsigned)nblk), dim3(256), 0, p->stream, ptg, n,
+                           (const double *)y, (double *)gmaps, p->cols, p->ncp, p->ncomp, p->W, p->beta, inv_hth,
+                           inv_hph, p->n2os, p->nphi);
+    else
+        hipLaunchKernelGGL(k_scatter_direct<float>, dim3((unsigned)nblk), dim3(256), 0, p->stream, ptg, n,
+                           (const float *)y, (float *)gmaps, p->cols, p->ncp, p->ncomp, p->W, p->beta, inv_hth,
+                           inv_hph, p->n2os, p->nphi);
+    return hipGetLastError();
+}

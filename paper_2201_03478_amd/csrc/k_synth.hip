@@ -28,35 +28,11 @@
 // Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
 // rings.  Recursion coefficients and weights for 64 consecutive l are built
 // cooperatively in LDS (one l per lane) and read as broadcasts.
-#include "sc_common.h"
+#include "wigner_rec.h"
 
 namespace {
 
-struct XN {
-    double m;  // mantissa in [0.5, 1) (or 0)
-    int e;     // value = m * 2^e
-};
-
-__device__ __forceinline__ XN xn_norm(double v, int e) {
-    int ee;
-    double mm = frexp(v, &ee);
-    return {mm, e + ee};
-}
-__device__ __forceinline__ XN xn_mul(XN a, XN b) { return xn_norm(a.m * b.m, a.e + b.e); }
-__device__ XN xn_pow(double x, int n) {
-    XN r = {0.5, 1};
-    XN b = xn_norm(x, 0);
-    while (n) {
-        if (n & 1) r = xn_mul(r, b);
-        b = xn_mul(b, b);
-        n >>= 1;
-    }
-    return r;
-}
-
-constexpr int REC_STEP = 1200;  // rescaling exponent step
-constexpr double REC_BIG = 0x1p600;
-constexpr double REC_DOWN = 0x1p-1200;
+using namespace wrec;
 
 // One recursion step for every ring of the lane: contract d^l (its true value
 // d * 2^{1200 e}; below 2^-600 while e < 0, i.e. nothing) and advance to d^{l+1}.
@@ -101,7 +77,6 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     int e[RPT];
     double2 fp[RPT], fm[RPT];
 
-    const double sgn = (m >= k && ((m - k) & 1)) ? -1.0 : 1.0;
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -110,14 +85,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         fm[r] = make_double2(0.0, 0.0);
         dp[r] = 0.0;
         if (j < nring) {
-            const double t = ((double)j + 0.5) / (double)nring;  // theta / pi
-            x[r] = cospi(t);
-            const double ch = cospi(0.5 * t), sh = sinpi(0.5 * t);
-            XN v = xn_mul(xn_mul(xn_pow(ch, l0 + mn), xn_pow(sh, l0 - mn)), pref);
-            const int E = v.e;
-            const int es = (E + REC_STEP / 2 >= 0) ? 0 : -((-(E + REC_STEP / 2) + REC_STEP - 1) / REC_STEP);
-            e[r] = es;
-            d[r] = sgn * ldexp(v.m, E - REC_STEP * es);
+            start_value(j, nring, m, k, pref, x[r], d[r], e[r]);
         } else {
             x[r] = 0.0;
             d[r] = 0.0;
@@ -133,17 +101,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         __syncthreads();
         if (l <= lmax) {
             double A, B, C;
-            if (l == 0) {
-                A = 1.0;
-                B = 0.0;
-                C = 0.0;
-            } else {
-                const double L = l, L1 = l + 1.0;
-                const double q = sqrt((L1 * L1 - mm) * (L1 * L1 - kk));
-                A = (2.0 * L + 1.0) * L1 / q;
-                B = A * mk / (L * L1);
-                C = L1 / L * sqrt((L * L - mm) * (L * L - kk)) / q;
-            }
+            rec_coefs(l, mm, kk, mk, A, B, C);
             double2 a = alm[aoff + l];
             double2 bb = blm[boff + l];
             if (m == 0) a.y = 0.0;

@@ -1,0 +1,220 @@
+// k_synth_adj.hip -- adjoint of the ring sums (gradient w.r.t. the sky a_lm).
+//
+// The forward ring sums are (k_synth.hip)
+//     F_k(theta_j, m)      = sum_l a_lm conj(b_lk) d^l_mk(theta_j)
+//     F_k(pi - theta_j, -m) = sum_l (-1)^{l+k+m} conj(a_lm) conj(b_lk) d^l_mk(theta_j),
+// the inner sums of Eqs. 7/9 of Galloway et al. (2022, Sec. 2.1).  Given the
+// ring-sum gradients F_adj (from the adjoint transforms), with the real inner
+// product Re sum conj(u) v, the gradient g = dL/dRe a_lm + i dL/dIm a_lm is
+//     Q+(l) = sum_j d^l_mk(theta_j) F_adj_k(theta_j, m),
+//     Q-(l) = sum_j d^l_mk(theta_j) F_adj_k(pi - theta_j, -m),
+//     g_lm  = sum_k [ Q+ b_lk + (-1)^{l+k+m} conj(Q- b_lk) ]      (m > 0),
+//     g_l0  = sum_k Re(Q+ b_lk)                                  (m = 0).
+// The d values come from the same recursion and start values as the forward
+// kernel.  The sums over rings are reductions across lanes for every l: each
+// lane adds its rings' products, writes the 4 real partials of each l to a
+// padded LDS buffer, and every 8 l the buffer is reduced by reading it
+// transposed (two lanes per (l, value) row).  One wave per ring group; the
+// waves of a workgroup are the groups of one (k, m) and are combined in LDS.
+// Per-k contributions go to GA[k][alm index]; a second kernel sums over k in a
+// fixed order (deterministic).
+#include "wigner_rec.h"
+
+namespace {
+
+using namespace wrec;
+
+constexpr int ADJ_FLUSH = 8;   // l steps per LDS flush
+constexpr int ADJ_ROW = 65;    // padded row length (doubles) of the partial buffer
+
+template <int RPT>
+__global__ void __launch_bounds__(1024)
+k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ blm, double2 *__restrict__ GA,
+                    const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax,
+                    int nring) {
+    extern __shared__ double adj_smem[];
+    const int nw = blockDim.x >> 6;
+    double *cA = adj_smem, *cB = cA + 64, *cC = cB + 64;                   // [64]
+    double *Qw = cC + 64;                                                  // [nw][64][4]
+    double *PB = Qw + nw * 64 * 4;                                          // [nw][4][FLUSH][ROW]
+    const int b = blockIdx.x;
+    const int k = b % (kmax + 1);
+    const int m = b / (kmax + 1);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l0 = m > k ? m : k;
+    const int mn = m < k ? m : k;
+    const int nm = 2 * lmax + 1;
+    const size_t aoff = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const size_t nalm = (size_t)(lmax + 1) * (lmax + 2) / 2;
+    double2 *gk = GA + (size_t)k * nalm + aoff;
+    // orders below l0 have no d^l_mk: their contribution is zero
+    for (int l = m + tid; l < l0 && l <= lmax; l += blockDim.x) gk[l] = make_double2(0.0, 0.0);
+    if (l0 > lmax) return;
+
+    double x[RPT], d[RPT], dp[RPT];
+    int e[RPT];
+    double2 fap[RPT], fam[RPT];
+    const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int j = (w * RPT + r) * 64 + lane;
+        dp[r] = 0.0;
+        fap[r] = make_double2(0.0, 0.0);
+        fam[r] = make_double2(0.0, 0.0);
+        if (j < nring) {
+            start_value(j, nring, m, k, pref, x[r], d[r], e[r]);
+            fap[r] = FA[((size_t)k * nm + (m + lmax)) * nring + j];
+            if (m > 0) fam[r] = FA[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)];
+        } else {
+            x[r] = 0.0;
+            d[r] = 0.0;
+            e[r] = 0;
+        }
+    }
+
+    double *pbw = PB + (size_t)w * 4 * ADJ_FLUSH * ADJ_ROW;
+    const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
+    for (int lc = l0; lc <= lmax; lc += 64) {
+        __syncthreads();  // previous chunk's coefficients and Qw are consumed
+        if (tid < 64 && lc + tid <= lmax) {
+            double A, B, C;
+            rec_coefs(lc + tid, mm, kk, mk, A, B, C);
+            cA[tid] = A;
+            cB[tid] = B;
+            cC[tid] = C;
+        }
+        __syncthreads();
+        const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
+        for (int t0 = 0; t0 < nl; t0 += ADJ_FLUSH) {
+            const int t1 = t0 + ADJ_FLUSH < nl ? t0 + ADJ_FLUSH : nl;
+            for (int t = t0; t < t1; ++t) {
+                const double A = cA[t], B = cB[t], C = cC[t];
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const double dd = ldexp(d[r], REC_STEP * e[r]);
+                    p0 = fma(dd, fap[r].x, p0);
+                    p1 = fma(dd, fap[r].y, p1);
+                    p2 = fma(dd, fam[r].x, p2);
+                    p3 = fma(dd, fam[r].y, p3);
+                    const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
+                    dp[r] = d[r];
+                    d[r] = dn;
+                }
+                double *row = pbw + (t - t0) * ADJ_ROW + lane;
+                row[0 * ADJ_FLUSH * ADJ_ROW] = p0;
+                row[1 * ADJ_FLUSH * ADJ_ROW] = p1;
+                row[2 * ADJ_FLUSH * ADJ_ROW] = p2;
+                row[3 * ADJ_FLUSH * ADJ_ROW] = p3;
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                if (fabs(d[r]) > REC_BIG) {
+                    d[r] *= REC_DOWN;
+                    dp[r] *= REC_DOWN;
+                    e[r] += 1;
+                }
+            }
+            // wave-local transpose-reduce: row (v, tt) summed by lanes 2 row, 2 row + 1
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const int rr = lane >> 1, half = lane & 1;  // rr in [0, 32): v = rr / 8, tt = rr % 8
+            const int v = rr / ADJ_FLUSH, tt = rr % ADJ_FLUSH;
+            const double *src = pbw + (v * ADJ_FLUSH + tt) * ADJ_ROW + half * 32;
+            double s = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < 32; ++q) s += src[q];
+            s += __shfl_xor(s, 1);
+            if (half == 0 && t0 + tt < t1) Qw[(w * 64 + t0 + tt) * 4 + v] = s;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        if (tid < nl) {
+            const int l = lc + tid;
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+            for (int ww = 0; ww < nw; ++ww) {
+                const double *qq = Qw + (ww * 64 + tid) * 4;
+                q0 += qq[0];
+                q1 += qq[1];
+                q2 += qq[2];
+                q3 += qq[3];
+            }
+            double2 bb = blm[(size_t)k * (2 * lmax + 1 - k) / 2 + l];
+            if (k == 0) bb.y = 0.0;
+            const double2 gp = cmul(make_double2(q0, q1), bb);
+            double2 g;
+            if (m == 0) {
+                g = make_double2(gp.x, 0.0);
+            } else {
+                const double2 gm = cmul(make_double2(q2, q3), bb);
+                const double sg = ((l + k + m) & 1) ? -1.0 : 1.0;
+                g = make_double2(gp.x + sg * gm.x, gp.y - sg * gm.y);
+            }
+            gk[l] = g;
+        }
+    }
+}
+
+// grad[i] = sum_k GA[k][i] in increasing k (entries with k > l are zero).
+__global__ void k_reduce_over_k(const double2 *__restrict__ GA, double2 *__restrict__ grad, int64_t nalm,
+                                int kmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nalm) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k <= kmax; ++k) {
+        const double2 v = GA[(size_t)k * nalm + i];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    grad[i] = s;
+}
+
+}  // namespace
+
+// Waves per (k, m) workgroup and rings per lane for the adjoint.
+static void adj_layout(int nring, int *rpt, int *nw) {
+    int best_r = 4, best_w = (nring + 255) / 256, best_waste = 1 << 30;
+    for (int r = 4; r >= 1; --r) {
+        const int waves = (nring + 64 * r - 1) / (64 * r);
+        if (waves > 16) continue;
+        const int waste = waves * 64 * r - nring;
+        if (waste < best_waste) {
+            best_waste = waste;
+            best_r = r;
+            best_w = waves;
+        }
+    }
+    *rpt = best_r;
+    *nw = best_w;
+}
+
+#define SC_ADJ_CASE(R)                                                                                       \
+    case R: {                                                                                                \
+        auto kern = k_ring_sums_adjoint<R>;                                                                  \
+        e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        if (e != hipSuccess) return e;                                                                       \
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)blm,      \
+                           p->GA, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring);                          \
+    } break;
+
+hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad) {
+    int rpt, nw;
+    adj_layout(p->nring, &rpt, &nw);
+    const int nblk = (p->lmax + 1) * (p->kmax + 1);
+    const size_t lds = sizeof(double) * (3 * 64 + (size_t)nw * 64 * 4 + (size_t)nw * 4 * ADJ_FLUSH * ADJ_ROW);
+    hipError_t e = hipSuccess;
+    switch (rpt) {
+        SC_ADJ_CASE(1)
+        SC_ADJ_CASE(2)
+        SC_ADJ_CASE(3)
+        default:
+        SC_ADJ_CASE(4)
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nalm = (int64_t)(p->lmax + 1) * (p->lmax + 2) / 2;
+    hipLaunchKernelGGL(k_reduce_over_k, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, p->stream, p->GA,
+                       (double2 *)grad, nalm, p->kmax);
+    return hipGetLastError();
+}

@@ -137,6 +137,10 @@ int ensure_bin_work(sc_plan *p, int64_t need) {
 
 void free_plan_buffers(sc_plan *p) {
     free_bin_work(p->bw);
+    if (p->gmaps) (void)hipFree(p->gmaps);
+    if (p->GA) (void)hipFree(p->GA);
+    p->gmaps = nullptr;
+    p->GA = nullptr;
     for (int i = 0; i < p->tl_cap; ++i) {
         if (p->tl[i].a) (void)hipEventDestroy(p->tl[i].a);
         if (p->tl[i].b) (void)hipEventDestroy(p->tl[i].b);
@@ -376,6 +380,72 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const 
     return sc_interpolate(p, ptg, n, tod);
 }
 
+int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
+                        double *alm_grad) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (!is_device_ptr(blm)) return fail(SC_EINVAL, "blm is not device memory");
+    if (!is_device_ptr(alm_grad)) return fail(SC_EINVAL, "alm_grad is not device memory");
+    if (n > 0 && (!is_device_ptr(ptg) || !is_device_ptr(tod_grad)))
+        return fail(SC_EINVAL, "ptg/tod_grad is not device memory");
+    if (((uintptr_t)blm & 15) || ((uintptr_t)alm_grad & 15)) return fail(SC_EINVAL, "blm/alm_grad not 16-byte aligned");
+    if (n > 0 && (((uintptr_t)ptg & 7) || ((uintptr_t)tod_grad & (p->prec == SC_FP64 ? 7 : 3))))
+        return fail(SC_EINVAL, "ptg/tod_grad misaligned");
+    const size_t map_bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
+    const size_t nalm = (size_t)(p->lmax + 1) * (p->lmax + 2) / 2;
+    if (!p->gmaps) {
+        size_t tot = 0;
+        int rc = alloc(&p->gmaps, map_bytes, &tot);
+        if (!rc) rc = alloc((void **)&p->GA, sizeof(double2) * (p->kmax + 1) * nalm, &tot);
+        if (rc) {
+            if (p->gmaps) (void)hipFree(p->gmaps);
+            p->gmaps = nullptr;
+            return rc;
+        }
+        p->adj_bytes = tot;
+        p->ws_bytes += tot;
+    }
+    int slot = timing_begin(p, SC_STAGE_SCATTER);
+    hipError_t e = sc_launch_zero(p->gmaps, map_bytes, p->stream);
+    timing_end(p, slot);
+    if (e != hipSuccess) return hip_fail(e, "gradient map clear");
+    if (n > 0) {
+        if (sc_scatter_binned_supported(p)) {
+            const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
+            int rc = ensure_bin_work(p, pass);
+            if (rc) return rc;
+            const size_t esz = p->prec == SC_FP64 ? 8 : 4;
+            for (int64_t off = 0; off < n; off += pass) {
+                const int64_t cnt = n - off < pass ? n - off : pass;
+                slot = timing_begin(p, SC_STAGE_BIN);
+                e = sc_launch_binning(p, ptg + 3 * off, cnt);
+                timing_end(p, slot);
+                if (e != hipSuccess) return hip_fail(e, "binning launch");
+                slot = timing_begin(p, SC_STAGE_SCATTER);
+                e = sc_launch_scatter_binned(p, (const char *)tod_grad + esz * off, p->gmaps);
+                timing_end(p, slot);
+                if (e != hipSuccess) return hip_fail(e, "binned scatter launch");
+            }
+        } else {
+            slot = timing_begin(p, SC_STAGE_SCATTER);
+            e = sc_launch_scatter(p, ptg, n, tod_grad, p->gmaps);
+            timing_end(p, slot);
+            if (e != hipSuccess) return hip_fail(e, "scatter launch");
+        }
+    }
+    slot = timing_begin(p, SC_STAGE_ADJ_FFT);
+    e = sc_launch_phi_adjoint(p, p->gmaps);
+    if (e == hipSuccess) e = sc_launch_theta_adjoint(p);
+    timing_end(p, slot);
+    if (e != hipSuccess) return hip_fail(e, "adjoint transform launch");
+    slot = timing_begin(p, SC_STAGE_ADJ_RING);
+    e = sc_launch_ring_sums_adjoint(p, blm, alm_grad);
+    timing_end(p, slot);
+    if (e != hipSuccess) return hip_fail(e, "adjoint ring-sum launch");
+    return SC_OK;
+}
+
 int sc_plan_enable_timing(sc_plan *p, int enable) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
     p->timing = enable ? 1 : 0;
@@ -384,8 +454,8 @@ int sc_plan_enable_timing(sc_plan *p, int enable) {
 
 int sc_plan_stage_times(sc_plan *p, double *ms, int64_t *launches, int nstage) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
-    double tot[SC_NSTAGE] = {0, 0, 0, 0, 0};
-    int64_t cnt[SC_NSTAGE] = {0, 0, 0, 0, 0};
+    double tot[SC_NSTAGE] = {};
+    int64_t cnt[SC_NSTAGE] = {};
     for (int i = 0; i < p->tl_n; ++i) {
         TimedLaunch &t = p->tl[i];
         hipError_t e = hipEventSynchronize(t.b);

@@ -82,6 +82,9 @@ struct sc_plan {
     int have_maps;
     size_t ws_bytes;
     BinWork bw;
+    void *gmaps;       // adjoint: gradient maps, same layout as maps (allocated on first use)
+    double2 *GA;       // adjoint: per-k gradient contributions [kmax+1][n_alm]
+    size_t adj_bytes;
     int gather_direct;     // force the per-sample gather (env SC_GATHER_PATH=direct)
     int gather_valu;       // FP32 binned gather on the VALU instead of MFMA (env SC_GATHER_PATH=valu)
     int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
@@ -93,7 +96,7 @@ struct sc_plan {
 };
 
 enum { SC_STAGE_RING = 0, SC_STAGE_THETA = 1, SC_STAGE_PHI = 2, SC_STAGE_GATHER = 3, SC_STAGE_BIN = 4,
-       SC_NSTAGE = 5 };
+       SC_STAGE_SCATTER = 5, SC_STAGE_ADJ_FFT = 6, SC_STAGE_ADJ_RING = 7, SC_NSTAGE = 8 };
 
 struct TimedLaunch {
     int stage;
@@ -108,6 +111,13 @@ hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm)
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_theta_upsample(sc_plan *p);
 hipError_t sc_launch_phi_synthesis(sc_plan *p);
+hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps);
+hipError_t sc_launch_theta_adjoint(sc_plan *p);
+hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad);
+hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps);
+hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps);
+bool sc_scatter_binned_supported(const sc_plan *p);
+hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
 hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);

@@ -1,0 +1,144 @@
+"""GPU adjoint (gradient with respect to a_lm) against the oracle, the dot-product
+test and finite differences, through the C ABI and the autograd wrapper.
+
+The GPU adjoint is the exact transpose of the GPU forward, which approximates the
+convolution of Eq. 2 (Galloway et al. 2022, Sec. 2.1) to the interpolation
+tolerance; so against the oracle's exact adjoint it agrees to that tolerance,
+and against its own forward (dot product, finite differences) to rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2201_03478_amd import api
+    api.N.load()
+    return torch, api, torch.device("cuda", 0)
+
+
+def _to(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _rel(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("f64maps_f32gather", 1e-5)])
+@pytest.mark.parametrize("L,K,n", [(20, 5, 600), (48, 12, 3000), (33, 0, 400)])
+def test_adjoint_matches_oracle(env, oracle_lib, prec, tol, L, K, n):
+    torch, api, dev = env
+    b = W.beam_alm(L, K, 4000 + L)
+    p = W.uniform_pointings(n, 4100 + L)
+    p[0] = [0.0, 0.2, 0.3]
+    p[1] = [math.pi, 6.2, 1.0]
+    y = np.random.default_rng(4200 + L).standard_normal(n)
+    plan = api.Plan(L, K, prec)
+    a = W.sky_alm(L, 4300 + L)
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    yt = _to(torch, dev, y).to(plan.tod_dtype)
+    g = plan.adjoint(_to(torch, dev, b), _to(torch, dev, p), yt).cpu().numpy()
+    ref = oracle_lib.adjoint(b, L, K, p, yt.double().cpu().numpy())
+    e = _rel(g, ref)
+    print("adjoint %s L=%d K=%d rel %.3e" % (prec, L, K, e))
+    assert e <= tol
+    assert np.all(g[:L + 1].imag == 0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f64maps_f32gather", 1e-5)])
+def test_dot_product_and_finite_differences(env, prec, tol):
+    """<y, A x> = Re sum conj(A^T y) x, and central differences of <y, A(a)> at 16 seeded entries."""
+    torch, api, dev = env
+    L, K, n = 40, 10, 20000
+    a = W.sky_alm(L, 51)
+    b = W.beam_alm(L, K, 52)
+    p = _to(torch, dev, W.uniform_pointings(n, 53))
+    bt = _to(torch, dev, b)
+    plan = api.Plan(L, K, prec)
+    y = torch.randn(n, generator=torch.Generator().manual_seed(54), dtype=torch.float64).to(dev).to(plan.tod_dtype)
+
+    def fwd(alm):
+        plan.set_sky_beam(_to(torch, dev, alm), bt)
+        return float(torch.dot(plan.interpolate(p).double(), y.double()))
+
+    lhs = fwd(a)
+    g = plan.adjoint(bt, p, y).cpu().numpy()
+    rhs = float(np.real(np.sum(np.conj(g) * a)))
+    print("dot test %s: %.3e" % (prec, abs(lhs - rhs) / abs(lhs)))
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    rng = np.random.default_rng(W.config_seed(5, 5))
+    idx = rng.choice(W.n_alm(L), 16, replace=False)
+    scale = np.max(np.abs(g))
+    for i in idx:
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            if part == "im" and i <= L:  # m = 0: imaginary part is ignored
+                continue
+            e = np.zeros_like(a)
+            e[i] = unit
+            h = 1.0  # the map is linear: any step gives the derivative up to rounding
+            fd = (fwd(a + h * e) - fwd(a - h * e)) / (2 * h)
+            ref = g[i].real if part == "re" else g[i].imag
+            assert abs(fd - ref) <= (1e-10 if prec == "fp64" else 1e-4) * scale, (i, part, fd, ref)
+
+
+def test_autograd_function(env, oracle_lib):
+    torch, api, dev = env
+    L, K, n = 24, 6, 2000
+    a = W.sky_alm(L, 61)
+    b = W.beam_alm(L, K, 62)
+    pn = W.uniform_pointings(n, 63)
+    plan = api.Plan(L, K, "fp64")
+    alm = _to(torch, dev, a).requires_grad_(True)
+    y = torch.randn(n, dtype=torch.float64, device=dev)
+    tod = api.sidelobe_convolve(alm, _to(torch, dev, b), _to(torch, dev, pn), plan)
+    (tod * y).sum().backward()
+    ref = oracle_lib.adjoint(b, L, K, pn, y.cpu().numpy())
+    assert alm.grad is not None and alm.grad.dtype == torch.complex128
+    assert _rel(alm.grad.cpu().numpy(), ref) <= 1e-10
+
+
+def test_adjoint_workload_full_size(env):
+    """lmax 512, kmax 32, 1e8 scan samples, float32 residual y ~ N(0, 1):
+    <y, A a> = <A^T y, a> to 1e-5 and central differences at 16 seeded a_lm."""
+    torch, api, dev = env
+    cfg = W.CONFIGS[5]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    a = W.sky_alm(L, W.config_seed(5, 1))
+    b = W.beam_alm(L, K, W.config_seed(5, 2))
+    bt = _to(torch, dev, b)
+    ptg = W.scan_pointings(n, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(W.config_seed(5, 4))
+    y = torch.randn(n, generator=gen, device=dev, dtype=torch.float32)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    tod = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def fwd(alm):
+        plan.set_sky_beam(_to(torch, dev, alm), bt)
+        plan.interpolate(ptg, out=tod)
+        return float(torch.dot(tod.double(), y.double()))
+
+    lhs = fwd(a)
+    g = plan.adjoint(bt, ptg, y).cpu().numpy()
+    rhs = float(np.real(np.sum(np.conj(g) * a)))
+    rel = abs(lhs - rhs) / abs(lhs)
+    print("full-size dot test: <y,Ax> %.9e <A^T y,x> %.9e rel %.3e" % (lhs, rhs, rel))
+    assert rel <= 1e-5
+    rng = np.random.default_rng(W.config_seed(5, 5))
+    idx = rng.choice(W.n_alm(L), 16, replace=False)
+    scale = np.max(np.abs(g))
+    worst = 0.0
+    for i in idx:
+        e = np.zeros_like(a)
+        e[i] = 1.0
+        fd = (fwd(a + e) - fwd(a - e)) / 2.0
+        worst = max(worst, abs(fd - g[i].real) / scale)
+    print("full-size FD worst %.3e (relative to max |g|)" % worst)
+    assert worst <= 1e-4
