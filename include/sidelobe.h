@@ -74,7 +74,12 @@ enum sc_precision {
     SC_FP64 = 0,
     /* FP64 recursion and transforms; maps stored in FP32; FP32 interpolation
        and k-sum (pointing reduction and psi reduction stay FP64); float32 TOD. */
-    SC_F64MAPS_F32GATHER = 1
+    SC_F64MAPS_F32GATHER = 1,
+    /* Precision variant: FP64 start values, FP32 Wigner-d recursion, ring
+       contraction on the matrix cores (FP32 products and accumulation); FP64
+       transforms; FP32 maps, interpolation and k-sum; float32 TOD.  Its error
+       grows with lmax (~1e-6 relative at lmax 1024). */
+    SC_MIXED = 2
 };
 
 /*

@@ -11,7 +11,7 @@ use so that importing the package has no torch/HIP side effects.
 """
 import importlib
 
-from ._native import SC_F64MAPS_F32GATHER, SC_FP64  # noqa: F401
+from ._native import SC_F64MAPS_F32GATHER, SC_FP64, SC_MIXED  # noqa: F401
 
 
 def __getattr__(name):

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsidelobe.so")
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EHIP, SC_ESTATE = 0, -1, -2, -3, -4
-SC_FP64, SC_F64MAPS_F32GATHER = 0, 1
+SC_FP64, SC_F64MAPS_F32GATHER, SC_MIXED = 0, 1, 2
 
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",

@@ -11,8 +11,11 @@
 
 #include "sc_common.h"
 
-#define SC_FFT_MAXN 4096
+// Threads per transform workgroup and the longest transform each size handles
+// (register staging holds ceil(MAXN / (R * NT)) radix-R butterflies per thread).
 #define SC_FFT_NT 256
+#define SC_FFT_NT_BIG 512
+#define SC_FFT_MAXN_PER_THREAD 16
 
 __device__ __forceinline__ double2 mul_i(double2 a, int dir) {
     // dir * i * a
@@ -87,10 +90,10 @@ __device__ __forceinline__ void dft_small<5, -1>(double2 *v) { dft5<-1>(v); }
 template <>
 __device__ __forceinline__ void dft_small<5, 1>(double2 *v) { dft5<1>(v); }
 
-template <int R, int DIR>
+template <int R, int DIR, int NT>
 __device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, const double2 *__restrict__ tw,
                                                int tid, int nth) {
-    constexpr int B = (SC_FFT_MAXN / R + SC_FFT_NT - 1) / SC_FFT_NT;
+    constexpr int B = (SC_FFT_MAXN_PER_THREAD * NT / R + NT - 1) / NT;
     const int nb = N / R;
     const int twstep = N / (Ns * R);
     double2 v[B][R];
@@ -126,21 +129,21 @@ __device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, cons
     __syncthreads();
 }
 
-// In-place transform of buf[0 .. P.n) (LDS).  Requires P.n <= SC_FFT_MAXN and
-// nth == SC_FFT_NT threads.  Starts and ends with a barrier-complete buffer.
-template <int DIR>
+// In-place transform of buf[0 .. P.n) (LDS) by NT threads; requires
+// P.n <= SC_FFT_MAXN_PER_THREAD * NT.  Starts and ends with a barrier-complete buffer.
+template <int DIR, int NT>
 __device__ void fft_lds(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
     int Ns = 1;
     for (int s = 0; s < P.nst; ++s) {
         const int R = P.r[s];
         if (R == 4)
-            stockham_stage<4, DIR>(buf, P.n, Ns, tw, tid, nth);
+            stockham_stage<4, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
         else if (R == 2)
-            stockham_stage<2, DIR>(buf, P.n, Ns, tw, tid, nth);
+            stockham_stage<2, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
         else if (R == 3)
-            stockham_stage<3, DIR>(buf, P.n, Ns, tw, tid, nth);
+            stockham_stage<3, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
         else
-            stockham_stage<5, DIR>(buf, P.n, Ns, tw, tid, nth);
+            stockham_stage<5, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
         Ns *= R;
     }
 }

@@ -21,7 +21,8 @@
 
 namespace {
 
-__global__ void __launch_bounds__(SC_FFT_NT)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
                  const double2 *__restrict__ twos, const double2 *__restrict__ phase,
@@ -46,7 +47,7 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
     for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    fft_lds<-1>(A, P2, tw2, tid, nth);
+    fft_lds<-1, NT>(A, P2, tw2, tid, nth);
 
     const double dm = dphi[m < 0 ? -m : m];
     for (int t = tid; t < nm; t += nth) {
@@ -56,7 +57,7 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
         B[n < 0 ? n + nos : n] = x;
     }
     __syncthreads();
-    fft_lds<1>(B, Pos, twos, tid, nth);
+    fft_lds<1, NT>(B, Pos, twos, tid, nth);
 
     const int r0 = -W / 2 + 1;
     for (int row = tid; row < rows; row += nth) {
@@ -66,8 +67,8 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(SC_FFT_NT)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
                 int W, FftPlan Pp, const double2 *__restrict__ twp) {
     extern __shared__ double2 sbuf[];
@@ -87,7 +88,7 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
         A[m < 0 ? m + np : m] = src[t];
     }
     __syncthreads();
-    fft_lds<1>(A, Pp, twp, tid, nth);
+    fft_lds<1, NT>(A, Pp, twp, tid, nth);
 
     const int q0 = -W / 2 + 1;
     T *dst = maps + (size_t)row * cols * ncp;
@@ -120,8 +121,8 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
 //    (forward FFT of the rows placed at r mod n2os), X_adj(n) =
 //    conj(p(n)) D_phi(m) Y(n), f_adj = inverse FFT_{n2}(X_adj) and
 //    F_adj(j) = f_adj(j) + (-1)^{m-k} f_adj(n2 - 1 - j).
-template <typename T>
-__global__ void __launch_bounds__(SC_FFT_NT)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, int rows, int cols, int ncp, int W,
               FftPlan Pp, const double2 *__restrict__ twp) {
     extern __shared__ double2 sbuf[];
@@ -156,7 +157,7 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
         }
     }
     __syncthreads();
-    fft_lds<-1>(A, Pp, twp, tid, nth);
+    fft_lds<-1, NT>(A, Pp, twp, tid, nth);
     double2 *dst = G + ((size_t)k * rows + row) * nm;
     for (int t = tid; t < nm; t += nth) {
         const int m = t - lmax;
@@ -164,7 +165,8 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
     }
 }
 
-__global__ void __launch_bounds__(SC_FFT_NT)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax, int nring, int rows, int W,
                 FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2, const double2 *__restrict__ twos,
                 const double2 *__restrict__ phase, const double *__restrict__ dphi) {
@@ -188,7 +190,7 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
         B[r] = G[((size_t)k * rows + row) * nm + mi];  // rows land on distinct indices
     }
     __syncthreads();
-    fft_lds<-1>(B, Pos, twos, tid, nth);
+    fft_lds<-1, NT>(B, Pos, twos, tid, nth);
     const double dm = dphi[m < 0 ? -m : m];
     for (int t = tid; t < nm; t += nth) {
         const int n = t - lmax;
@@ -196,7 +198,7 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
         A[n < 0 ? n + n2 : n] = cscale(cmul(cconj(phase[t]), y), dm);
     }
     __syncthreads();
-    fft_lds<1>(A, P2, tw2, tid, nth);
+    fft_lds<1, NT>(A, P2, tw2, tid, nth);
     const double sg = ((m - k) & 1) ? -1.0 : 1.0;
     double2 *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
@@ -207,42 +209,76 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
 
 }  // namespace
 
-hipError_t sc_launch_theta_upsample(sc_plan *p) {
+// 256 threads up to 4096-point transforms, 512 above (lmax ~ 1024).
+static inline bool fft_big(const sc_plan *p) {
+    return p->n2os > SC_FFT_MAXN_PER_THREAD * SC_FFT_NT || p->nphi > SC_FFT_MAXN_PER_THREAD * SC_FFT_NT;
+}
+
+template <int NT>
+static hipError_t theta_up(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
     const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipLaunchKernelGGL(k_theta_upsample, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->F, p->G, p->lmax,
-                       p->nring, p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    hipError_t e = hipFuncSetAttribute((const void *)k_theta_upsample<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_theta_upsample<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring,
+                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
     return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t phi_syn(sc_plan *p) {
+    const int nblk = (p->kmax + 1) * p->rows;
+    const size_t lds = sizeof(double2) * (size_t)p->nphi;
+    auto kern = k_phi_synthesis<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
+                       p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
+    const int nblk = (p->kmax + 1) * p->rows;
+    const size_t lds = sizeof(double2) * (size_t)p->nphi;
+    auto kern = k_phi_adjoint<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const T *)gmaps, p->G, p->lmax,
+                       p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+    return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t theta_adj(sc_plan *p) {
+    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
+    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
+    hipError_t e = hipFuncSetAttribute((const void *)k_theta_adjoint<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_theta_adjoint<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->G, p->F, p->lmax, p->nring,
+                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_theta_upsample(sc_plan *p) {
+    return fft_big(p) ? theta_up<SC_FFT_NT_BIG>(p) : theta_up<SC_FFT_NT>(p);
 }
 
 hipError_t sc_launch_phi_synthesis(sc_plan *p) {
-    const int nblk = (p->kmax + 1) * p->rows;
-    const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    if (p->prec == SC_FP64)
-        hipLaunchKernelGGL(k_phi_synthesis<double>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G,
-                           (double *)p->maps, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
-    else
-        hipLaunchKernelGGL(k_phi_synthesis<float>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G,
-                           (float *)p->maps, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
-    return hipGetLastError();
+    if (p->prec == SC_FP64) return fft_big(p) ? phi_syn<double, SC_FFT_NT_BIG>(p) : phi_syn<double, SC_FFT_NT>(p);
+    return fft_big(p) ? phi_syn<float, SC_FFT_NT_BIG>(p) : phi_syn<float, SC_FFT_NT>(p);
 }
 
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {
-    const int nblk = (p->kmax + 1) * p->rows;
-    const size_t lds = sizeof(double2) * (size_t)p->nphi;
     if (p->prec == SC_FP64)
-        hipLaunchKernelGGL(k_phi_adjoint<double>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream,
-                           (const double *)gmaps, p->G, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
-    else
-        hipLaunchKernelGGL(k_phi_adjoint<float>, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream,
-                           (const float *)gmaps, p->G, p->lmax, p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
-    return hipGetLastError();
+        return fft_big(p) ? phi_adj<double, SC_FFT_NT_BIG>(p, gmaps) : phi_adj<double, SC_FFT_NT>(p, gmaps);
+    return fft_big(p) ? phi_adj<float, SC_FFT_NT_BIG>(p, gmaps) : phi_adj<float, SC_FFT_NT>(p, gmaps);
 }
 
 hipError_t sc_launch_theta_adjoint(sc_plan *p) {
-    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
-    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipLaunchKernelGGL(k_theta_adjoint, dim3(nblk), dim3(SC_FFT_NT), lds, p->stream, p->G, p->F, p->lmax, p->nring,
-                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
-    return hipGetLastError();
+    return fft_big(p) ? theta_adj<SC_FFT_NT_BIG>(p) : theta_adj<SC_FFT_NT>(p);
 }

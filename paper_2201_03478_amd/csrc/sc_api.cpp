@@ -62,7 +62,7 @@ bool factor_fft(int n, FftPlan *P) {
     while (m % 2 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 2; m /= 2; }
     while (m % 3 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 3; m /= 3; }
     while (m % 5 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 5; m /= 5; }
-    return m == 1 && n <= 4096;
+    return m == 1 && n <= 16 * 512;  // longest transform the LDS kernels handle
 }
 
 // Record the start event of a timed launch; returns the slot or -1.
@@ -198,7 +198,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     if (lmax < 0) return fail(SC_EINVAL, "lmax = %d < 0", lmax);
     if (kmax < 0 || kmax > lmax) return fail(SC_EINVAL, "kmax = %d outside [0, lmax = %d]", kmax, lmax);
     if (kmax > 127) return fail(SC_EINVAL, "kmax = %d above the supported 127", kmax);
-    if (precision != SC_FP64 && precision != SC_F64MAPS_F32GATHER)
+    if (precision != SC_FP64 && precision != SC_F64MAPS_F32GATHER && precision != SC_MIXED)
         return fail(SC_EINVAL, "unknown precision %d", precision);
     int W = kernel_width;
     if (W == 0) W = precision == SC_FP64 ? 14 : 8;
@@ -234,9 +234,10 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
         p->bin_pass_max = (v > 0 && v < BIN_PASS_MAX) ? (int64_t)v : (int64_t)BIN_PASS_MAX;
     }
     sc_choose_ring_layout(p->nring, &p->rpt, &p->ngroups);
+    sc_choose_ring_layout_mixed(p->nring, &p->rpt_mx, &p->ngroups_mx);
     if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
         delete p;
-        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 4096 points (not supported)", lmax);
+        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 8192 points (not supported)", lmax);
     }
 
     const size_t nm = 2 * (size_t)lmax + 1;
@@ -303,7 +304,7 @@ int sc_set_sky_beam(sc_plan *p, const double *alm, const double *blm) {
     if (!is_device_ptr(blm)) return fail(SC_EINVAL, "blm is not device memory");
     if (((uintptr_t)alm & 15) || ((uintptr_t)blm & 15)) return fail(SC_EINVAL, "alm/blm not 16-byte aligned");
     int slot = timing_begin(p, SC_STAGE_RING);
-    hipError_t e = sc_launch_ring_sums(p, alm, blm);
+    hipError_t e = p->prec == SC_MIXED ? sc_launch_ring_sums_mixed(p, alm, blm) : sc_launch_ring_sums(p, alm, blm);
     timing_end(p, slot);
     if (e == hipSuccess) {
         slot = timing_begin(p, SC_STAGE_THETA);

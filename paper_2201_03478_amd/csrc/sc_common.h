@@ -63,6 +63,7 @@ struct sc_plan {
     int rows, cols;    // stored map rows (theta nodes incl. ghost rows) and columns (incl. wrap)
     int ncomp, ncp;    // 2 kmax + 1 components, padded count
     int rpt, ngroups;  // recursion layout: rings per lane, ring groups per (k, m)
+    int rpt_mx, ngroups_mx;  // the same for the FP32 (mixed-precision) recursion
     hipStream_t stream;
 
     FftPlan p2, p2os, pphi;
@@ -109,6 +110,8 @@ static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_
 hipError_t sc_launch_tables(sc_plan *p);
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
+hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm);
+void sc_choose_ring_layout_mixed(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_theta_upsample(sc_plan *p);
 hipError_t sc_launch_phi_synthesis(sc_plan *p);
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps);
