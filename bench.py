@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 4 per host thread)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision, adjoint and batched workloads (extra objects in the JSON line)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -242,7 +244,112 @@ def main():
         result["speedup_vs_fp64_form"] = ms64 / ms
         del p64, tod64
 
+    if not args.no_extras:
+        for name, fn in (("precision_variant", extra_precision), ("adjoint", extra_adjoint),
+                         ("batched", extra_batched)):
+            try:
+                result[name] = fn(torch, api, W, dev, args.no_cpu_baseline)
+            except Exception as exc:  # an extra must not lose the headline line
+                result[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
+            torch.cuda.empty_cache()
+            print("bench: %s done" % name, file=sys.stderr, flush=True)
+
     print(json.dumps(result), flush=True)
+
+
+def _event_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, tod, m, seed):
+    import oracle
+    n = ptg.shape[0]
+    idx = torch.as_tensor(np.sort(np.random.default_rng(seed).choice(n, m, replace=False)), device=dev)
+    ref = oracle.convolve(a_np, b_np, L, K, ptg[idx].cpu().numpy(), nthreads=min(os.cpu_count() or 1, 16))
+    got = tod[idx].double().cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def extra_precision(torch, api, W, dev, no_oracle):
+    """lmax 1024, kmax 16, 1e8 scan samples: mixed form vs the FP64-recursion form."""
+    cfg = W.CONFIGS[3]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    a_np, b_np = W.sky_alm(L, W.config_seed(3, 1)), W.beam_alm(L, K, W.config_seed(3, 2))
+    a, b = torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev)
+    ptg = W.scan_pointings(n, device=dev)
+    out = {"workload": "precision-lmax1024-kmax16-scan1e8", "n_samples": n}
+    for prec in ("mixed", "f64maps_f32gather"):
+        plan, tod, ms, stages = run_form(torch, api, dev, a, b, ptg, L, K, prec, 8, 3, 1)
+        rec = {"ms_per_step": ms, "value": n / (ms * 1e-3),
+               "stages_ms_per_step": {k: t / 3 for k, (t, c) in stages.items() if c}}
+        if not no_oracle:
+            rec["rel_err_vs_oracle"] = _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, tod, 8, W.config_seed(3, 6))
+        out[prec] = rec
+        del plan, tod
+    return out
+
+
+def extra_adjoint(torch, api, W, dev, no_oracle):
+    """lmax 512, kmax 32, 1e8 scan samples: forward and adjoint, with the dot-product test."""
+    cfg = W.CONFIGS[5]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    a_np, b_np = W.sky_alm(L, W.config_seed(5, 1)), W.beam_alm(L, K, W.config_seed(5, 2))
+    a, b = torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev)
+    ptg = W.scan_pointings(n, device=dev)
+    y = torch.randn(n, generator=torch.Generator(device=dev).manual_seed(W.config_seed(5, 4)), device=dev)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    tod = torch.empty(n, dtype=torch.float32, device=dev)
+    grad = torch.empty_like(a)
+
+    def fwd():
+        plan.set_sky_beam(a, b)
+        plan.interpolate(ptg, out=tod)
+
+    def adj():
+        plan.adjoint(b, ptg, y, out=grad)
+
+    fms = _event_ms(torch, fwd, 3)
+    plan.enable_timing(True)
+    plan.stage_times()
+    ams = _event_ms(torch, adj, 3)
+    st = plan.stage_times()
+    plan.enable_timing(False)
+    fwd()
+    lhs = float(torch.dot(tod.double(), y.double()))
+    rhs = float(torch.sum(torch.conj(grad) * a).real)
+    return {"workload": "adjoint-lmax512-kmax32-scan1e8", "n_samples": n,
+            "forward_ms": fms, "adjoint_ms": ams, "adjoint_value": n / (ams * 1e-3),
+            "adjoint_stages_ms": {k: t / 4 for k, (t, c) in st.items() if c},
+            "dot_test_rel": abs(lhs - rhs) / abs(lhs)}
+
+
+def extra_batched(torch, api, W, dev, no_oracle):
+    """12 detectors (lmax 256/512/1024, kmax 8/32/100, 4e7 scan samples), autotuned, one gather launch."""
+    from paper_2201_03478_amd import autotune
+    sky = torch.from_numpy(W.sky_alm(1024, W.config_seed(4, 1))).to(dev)
+    dets = []
+    for i, (L, K, n) in enumerate(W.DETECTORS):
+        dets.append(dict(lmax=L, kmax=K, blm=torch.from_numpy(W.beam_alm(L, K, W.config_seed(4, 10 + i))).to(dev),
+                         ptg=W.scan_pointings(n, t0=1000.0 * i, psi0=i * math.pi / 12, device=dev)))
+    ntot = sum(d["ptg"].shape[0] for d in dets)
+    bt = api.Batch(dets, 1024)
+    eager_default = _event_ms(torch, lambda: bt.run(sky, use_graph=False), 2)
+    chosen = autotune.tune_batch(bt, sky, reps=2)
+    eager = _event_ms(torch, lambda: bt.run(sky, use_graph=False), 3)
+    graph = _event_ms(torch, lambda: bt.run(sky, use_graph=True), 3)
+    out = {"workload": "batched-12det-scan4e7", "n_samples": ntot, "ms_per_step_graph": graph,
+           "value": ntot / (graph * 1e-3), "ms_per_step_eager": eager, "ms_per_step_eager_untuned": eager_default,
+           "tuned": [dict(det=i, lmax=d["lmax"], kmax=d["kmax"], **c) for i, (d, c) in enumerate(zip(bt.dets, chosen))]}
+    bt.close()
+    return out
 
 
 if __name__ == "__main__":

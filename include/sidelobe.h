@@ -178,6 +178,71 @@ int64_t sc_debug_copy_stage(sc_plan *plan, int which, void *dst, int64_t capacit
 int sc_plan_enable_timing(sc_plan *plan, int enable);
 int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage);
 
+/*
+ * Tunable parameters of a plan (chosen by the autotuner in the Python
+ * package; defaults work everywhere).
+ *   SC_PARAM_BIN_CHUNK          samples per gather/scatter work item, 16 .. 2^20 (default 256)
+ *   SC_PARAM_GATHER_WGS_PER_CU  persistent gather/scatter workgroups per CU, 0 = as many as fit
+ *   SC_PARAM_RING_RPT           rings per lane of the ring-sum kernel, 1..4 (1..8 for SC_MIXED)
+ *   SC_PARAM_SKY_LMAX           band limit of the layout of the alm array given to
+ *                               sc_set_sky_beam (>= lmax; a shared sky may have a larger one)
+ */
+enum sc_param {
+    SC_PARAM_BIN_CHUNK = 1,
+    SC_PARAM_GATHER_WGS_PER_CU = 2,
+    SC_PARAM_RING_RPT = 3,
+    SC_PARAM_SKY_LMAX = 4
+};
+int sc_plan_set_param(sc_plan *plan, int param, int64_t value);
+int sc_plan_get_param(const sc_plan *plan, int param, int64_t *value);
+
+/*
+ * Batches: several detectors convolved with one sky (the per-detector use of
+ * the method; each detector has its own beam, band limit, truncation and
+ * pointing).  Each detector gets its own maps; the interpolation of all
+ * detectors runs as ONE persistent launch that takes work items (samples of one
+ * stencil anchor of one detector) from a shared queue.
+ *
+ *   lmax, kmax  the detector's beam band limit and truncation (lmax <= lmax_sky)
+ *   blm         device complex128, layout of (lmax, kmax)
+ *   ptg, n      device float64 [n][3], 0 <= n <= 2^24
+ *   tod         device float32 [n] output
+ */
+typedef struct sc_det_desc {
+    int lmax;
+    int kmax;
+    const double *blm;
+    const double *ptg;
+    int64_t n;
+    float *tod;
+} sc_det_desc;
+
+typedef struct sc_batch sc_batch;
+
+/* Create a batch (precision SC_F64MAPS_F32GATHER or SC_MIXED).  The descriptors
+   are copied; their buffers must stay valid (contents may change) for the
+   batch's lifetime. */
+int sc_batch_create(sc_batch **batch, const sc_det_desc *dets, int ndet, int lmax_sky, int precision,
+                    void *stream);
+
+/* Synthesise every detector's maps from alm_sky (complex128, layout lmax_sky)
+   and write every tod.  use_graph = 0: plain launches.  use_graph = 1: the first
+   call runs eagerly once, then captures the whole sequence in a hipGraph and
+   launches it; later calls with the same alm_sky pointer replay the graph (a
+   different pointer or a parameter change re-captures). */
+int sc_batch_run(sc_batch *batch, const double *alm_sky, int use_graph);
+
+/* Tunables: det = -1 applies to every detector.  SC_PARAM_GATHER_WGS_PER_CU is
+   batch-wide (the single gather launch). */
+int sc_batch_set_param(sc_batch *batch, int det, int param, int64_t value);
+int sc_batch_get_param(const sc_batch *batch, int det, int param, int64_t *value);
+
+/* The plan of detector det (owned by the batch; for inspection and timing). */
+int sc_batch_plan(sc_batch *batch, int det, sc_plan **plan);
+
+/* Release a batch (synchronises its stream). */
+int sc_batch_destroy(sc_batch *batch);
+
 /* Human-readable text for a status code. */
 const char *sc_strerror(int code);
 

@@ -16,11 +16,21 @@ LIB_PATH = os.path.join(HERE, "libsidelobe.so")
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EHIP, SC_ESTATE = 0, -1, -2, -3, -4
 SC_FP64, SC_F64MAPS_F32GATHER, SC_MIXED = 0, 1, 2
 
+SC_PARAM_BIN_CHUNK, SC_PARAM_GATHER_WGS_PER_CU, SC_PARAM_RING_RPT, SC_PARAM_SKY_LMAX = 1, 2, 3, 4
+
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",
     "sc_interpolate", "sc_convolve", "sc_convolve_adjoint", "sc_debug_copy_stage", "sc_plan_enable_timing",
-    "sc_plan_stage_times", "sc_strerror", "sc_last_error",
+    "sc_plan_stage_times", "sc_plan_set_param", "sc_plan_get_param", "sc_batch_create", "sc_batch_run",
+    "sc_batch_set_param", "sc_batch_get_param", "sc_batch_plan", "sc_batch_destroy", "sc_strerror",
+    "sc_last_error",
 )
+
+
+class DetDesc(ctypes.Structure):
+    """sc_det_desc."""
+    _fields_ = [("lmax", ctypes.c_int), ("kmax", ctypes.c_int), ("blm", ctypes.c_void_p),
+                ("ptg", ctypes.c_void_p), ("n", ctypes.c_int64), ("tod", ctypes.c_void_p)]
 
 _lib = None
 
@@ -54,6 +64,14 @@ def load():
     lib.sc_debug_copy_stage.restype = i64
     lib.sc_plan_enable_timing.argtypes = [vp, i32]
     lib.sc_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
+    lib.sc_plan_set_param.argtypes = [vp, i32, i64]
+    lib.sc_plan_get_param.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.sc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DetDesc), i32, i32, i32, vp]
+    lib.sc_batch_run.argtypes = [vp, vp, i32]
+    lib.sc_batch_set_param.argtypes = [vp, i32, i32, i64]
+    lib.sc_batch_get_param.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    lib.sc_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.sc_batch_destroy.argtypes = [vp]
     lib.sc_strerror.argtypes = [i32]
     lib.sc_strerror.restype = ctypes.c_char_p
     lib.sc_last_error.argtypes = []

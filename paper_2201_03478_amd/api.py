@@ -42,25 +42,41 @@ def _dev(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
     return t
 
 
+PARAMS = {"bin_chunk": N.SC_PARAM_BIN_CHUNK, "gather_wgs_per_cu": N.SC_PARAM_GATHER_WGS_PER_CU,
+          "ring_rpt": N.SC_PARAM_RING_RPT, "sky_lmax": N.SC_PARAM_SKY_LMAX}
+
+
 class Plan:
     """sc_plan: geometry, workspace and resident maps for one (lmax, kmax, precision)."""
 
     def __init__(self, lmax: int, kmax: int, precision="f64maps_f32gather", kernel_width: int = 0,
-                 stream=None):
+                 stream=None, _handle=None):
         lib = N.load()
         self._lib = lib
-        self._p = ctypes.c_void_p()
-        N.check(lib.sc_plan_create(ctypes.byref(self._p), int(lmax), int(kmax), _prec(precision),
-                                   int(kernel_width), ctypes.c_void_p(_stream_handle(stream))),
-                "sc_plan_create")
+        self._owned = _handle is None
+        if _handle is None:
+            self._p = ctypes.c_void_p()
+            N.check(lib.sc_plan_create(ctypes.byref(self._p), int(lmax), int(kmax), _prec(precision),
+                                       int(kernel_width), ctypes.c_void_p(_stream_handle(stream))),
+                    "sc_plan_create")
+        else:
+            self._p = _handle
         self.lmax, self.kmax = int(lmax), int(kmax)
         self.precision = _prec(precision)
         self.tod_dtype = torch.float64 if self.precision == N.SC_FP64 else torch.float32
 
     def close(self):
-        if getattr(self, "_p", None) and self._p.value:
+        if self._owned and getattr(self, "_p", None) and self._p.value:
             N.check(self._lib.sc_plan_destroy(self._p), "sc_plan_destroy")
             self._p = ctypes.c_void_p()
+
+    def set_param(self, name: str, value: int):
+        N.check(self._lib.sc_plan_set_param(self._p, PARAMS[name], int(value)), "sc_plan_set_param")
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_int64()
+        N.check(self._lib.sc_plan_get_param(self._p, PARAMS[name], ctypes.byref(v)), "sc_plan_get_param")
+        return v.value
 
     def __del__(self):
         try:
@@ -80,7 +96,7 @@ class Plan:
     def set_sky_beam(self, alm: torch.Tensor, blm: torch.Tensor):
         _dev(alm, "alm", torch.complex128)
         _dev(blm, "blm", torch.complex128)
-        if alm.numel() != n_alm(self.lmax) or blm.numel() != n_alm(self.lmax, self.kmax):
+        if alm.numel() != n_alm(self.get_param("sky_lmax")) or blm.numel() != n_alm(self.lmax, self.kmax):
             raise ValueError("alm/blm sizes do not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
         self.set_stream()
         N.check(self._lib.sc_set_sky_beam(self._p, alm.data_ptr(), blm.data_ptr()), "sc_set_sky_beam")
@@ -195,3 +211,69 @@ class SidelobeConv(torch.autograd.Function):
 def sidelobe_convolve(alm: torch.Tensor, blm: torch.Tensor, ptg: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Differentiable convolution (gradient with respect to alm)."""
     return SidelobeConv.apply(alm, blm, ptg, plan)
+
+
+class Batch:
+    """sc_batch: detectors sharing one sky; one persistent gather launch, optional hipGraph replay.
+
+    dets: list of dicts with lmax, kmax, blm (complex128), ptg (float64 [n, 3]) and optionally
+    tod (float32 [n]); outputs are written to each det's "tod" (allocated if missing).
+    """
+
+    def __init__(self, dets, lmax_sky: int, precision="f64maps_f32gather", stream=None):
+        lib = N.load()
+        self._lib = lib
+        self.lmax_sky = int(lmax_sky)
+        self.precision = _prec(precision)
+        self.dets = []
+        arr = (N.DetDesc * len(dets))()
+        for i, d in enumerate(dets):
+            blm = _dev(d["blm"], "blm", torch.complex128)
+            ptg = _dev(d["ptg"], "ptg", torch.float64)
+            n = ptg.shape[0]
+            tod = d.get("tod")
+            if tod is None:
+                tod = torch.empty(n, dtype=torch.float32, device=ptg.device)
+            _dev(tod, "tod", torch.float32)
+            if blm.numel() != n_alm(d["lmax"], d["kmax"]) or tod.numel() != n:
+                raise ValueError("detector %d: blm/tod sizes do not match" % i)
+            self.dets.append(dict(lmax=int(d["lmax"]), kmax=int(d["kmax"]), blm=blm, ptg=ptg, tod=tod))
+            arr[i] = N.DetDesc(int(d["lmax"]), int(d["kmax"]), blm.data_ptr(), ptg.data_ptr(), n, tod.data_ptr())
+        self._b = ctypes.c_void_p()
+        N.check(lib.sc_batch_create(ctypes.byref(self._b), arr, len(dets), self.lmax_sky, self.precision,
+                                    ctypes.c_void_p(_stream_handle(stream))), "sc_batch_create")
+
+    def run(self, alm_sky: torch.Tensor, use_graph: bool = True):
+        _dev(alm_sky, "alm_sky", torch.complex128)
+        if alm_sky.numel() != n_alm(self.lmax_sky):
+            raise ValueError("alm_sky size does not match lmax_sky=%d" % self.lmax_sky)
+        self._sky = alm_sky
+        N.check(self._lib.sc_batch_run(self._b, alm_sky.data_ptr(), 1 if use_graph else 0), "sc_batch_run")
+        return [d["tod"] for d in self.dets]
+
+    def set_param(self, name: str, value: int, det: int = -1):
+        N.check(self._lib.sc_batch_set_param(self._b, int(det), PARAMS[name], int(value)), "sc_batch_set_param")
+
+    def get_param(self, name: str, det: int = 0) -> int:
+        v = ctypes.c_int64()
+        N.check(self._lib.sc_batch_get_param(self._b, int(det), PARAMS[name], ctypes.byref(v)),
+                "sc_batch_get_param")
+        return v.value
+
+    def plan(self, det: int) -> Plan:
+        """Non-owning view of detector det's plan (its sky layout is lmax_sky)."""
+        h = ctypes.c_void_p()
+        N.check(self._lib.sc_batch_plan(self._b, int(det), ctypes.byref(h)), "sc_batch_plan")
+        d = self.dets[det]
+        return Plan(d["lmax"], d["kmax"], self.precision, _handle=h)
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            N.check(self._lib.sc_batch_destroy(self._b), "sc_batch_destroy")
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,7 +10,7 @@
 //   k_scan_*       exclusive scan of (samples, work items) per key
 //   k_bin_scatter  samples in key order: fractional offsets and psi (FP64)
 //                  and the original index
-//   k_bin_items    work items (key, first sorted sample, count <= BIN_CHUNK)
+//   k_bin_items    work items (key, first sorted sample, count <= the plan's bin chunk)
 //
 // Integer index arithmetic is exact; the fractional offsets u - floor(u) are
 // kept in FP64 (the FP32 gather rounds them when it forms its weights).
@@ -57,10 +57,10 @@ constexpr int SCAN_NT = 256;
 constexpr int SCAN_PER = 16;
 constexpr int SCAN_BLOCK = SCAN_NT * SCAN_PER;
 
-__device__ __forceinline__ int2 key_pair(const int *count, int64_t i, int64_t nkeys) {
+__device__ __forceinline__ int2 key_pair(const int *count, int64_t i, int64_t nkeys, int chunk) {
     if (i >= nkeys) return make_int2(0, 0);
     const int c = count[i];
-    return make_int2(c, (c + BIN_CHUNK - 1) / BIN_CHUNK);
+    return make_int2(c, (c + chunk - 1) / chunk);
 }
 
 // block-wide exclusive scan of one int2 per thread; returns the block total
@@ -83,12 +83,12 @@ __device__ int2 block_scan(int2 v, int2 *sh, int &excl_x, int &excl_y) {
 }
 
 __global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const int *__restrict__ count, int64_t nkeys,
-                                                         int2 *__restrict__ sums) {
+                                                         int2 *__restrict__ sums, int chunk) {
     __shared__ int2 sh[SCAN_NT];
     const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER;
     int2 acc = make_int2(0, 0);
     for (int q = 0; q < SCAN_PER; ++q) {
-        const int2 v = key_pair(count, base + q, nkeys);
+        const int2 v = key_pair(count, base + q, nkeys, chunk);
         acc.x += v.x;
         acc.y += v.y;
     }
@@ -118,13 +118,14 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_sums(int2 *__restrict__ sums, 
 }
 
 __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int *__restrict__ count, int64_t nkeys,
-                                                        const int2 *__restrict__ sums, int2 *__restrict__ offs) {
+                                                        const int2 *__restrict__ sums, int2 *__restrict__ offs,
+                                                        int chunk) {
     __shared__ int2 sh[SCAN_NT];
     const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER;
     int2 v[SCAN_PER];
     int2 acc = make_int2(0, 0);
     for (int q = 0; q < SCAN_PER; ++q) {
-        v[q] = key_pair(count, base + q, nkeys);
+        v[q] = key_pair(count, base + q, nkeys, chunk);
         acc.x += v[q].x;
         acc.y += v[q].y;
     }
@@ -154,15 +155,15 @@ __global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom
 }
 
 __global__ void k_bin_items(const int *__restrict__ count, const int2 *__restrict__ offs, int64_t nkeys,
-                            int4 *__restrict__ items) {
+                            int4 *__restrict__ items, int chunk) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nkeys) return;
     const int c = count[k];
     if (c == 0) return;
     const int2 o = offs[k];
-    for (int q = 0; q * BIN_CHUNK < c; ++q) {
-        const int cnt = c - q * BIN_CHUNK < BIN_CHUNK ? c - q * BIN_CHUNK : BIN_CHUNK;
-        items[o.y + q] = make_int4((int)k, o.x + q * BIN_CHUNK, cnt, 0);
+    for (int q = 0; q * chunk < c; ++q) {
+        const int cnt = c - q * chunk < chunk ? c - q * chunk : chunk;
+        items[o.y + q] = make_int4((int)k, o.x + q * chunk, cnt, 0);
     }
 }
 
@@ -196,11 +197,12 @@ hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
     hipLaunchKernelGGL(k_fill_int, dim3(1024), dim3(256), 0, p->stream, w.count, nkeys, 0);
     hipLaunchKernelGGL(k_bin_keys, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.count);
     const int nblk = (int)((nkeys + SCAN_BLOCK - 1) / SCAN_BLOCK);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, p->bin_chunk);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, p->stream, w.sums, nblk, w.totals);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, w.offs);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, w.offs,
+                       p->bin_chunk);
     hipLaunchKernelGGL(k_bin_scatter, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.offs, w.sorted);
     hipLaunchKernelGGL(k_bin_items, dim3((unsigned)((nkeys + bs - 1) / bs)), dim3(bs), 0, p->stream, w.count,
-                       w.offs, nkeys, w.items);
+                       w.offs, nkeys, w.items, p->bin_chunk);
     return hipGetLastError();
 }

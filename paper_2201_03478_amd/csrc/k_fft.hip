@@ -218,8 +218,7 @@ template <int NT>
 static hipError_t theta_up(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
     const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipError_t e = hipFuncSetAttribute((const void *)k_theta_upsample<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)k_theta_upsample<NT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_theta_upsample<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring,
                        p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
@@ -231,8 +230,7 @@ static hipError_t phi_syn(sc_plan *p) {
     const int nblk = (p->kmax + 1) * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
     auto kern = k_phi_synthesis<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
                        p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
@@ -244,8 +242,7 @@ static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
     const int nblk = (p->kmax + 1) * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
     auto kern = k_phi_adjoint<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const T *)gmaps, p->G, p->lmax,
                        p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
@@ -256,8 +253,7 @@ template <int NT>
 static hipError_t theta_adj(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
     const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipError_t e = hipFuncSetAttribute((const void *)k_theta_adjoint<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)k_theta_adjoint<NT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_theta_adjoint<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->G, p->F, p->lmax, p->nring,
                        p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);

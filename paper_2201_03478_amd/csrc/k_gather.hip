@@ -17,6 +17,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+int ct_class(int ncomp);
+
 template <typename T>
 __device__ __forceinline__ T es_weight(T z, T beta) {
     const T q = (T)1 - z * z;
@@ -247,18 +249,11 @@ hipError_t launch_binned(sc_plan *p, void *tod) {
     static_assert(64 * 64 * sizeof(T) >= 64 * 16 * sizeof(double2), "group table must fit the weight area");
     const size_t lds = sizeof(T) * (64 * NC + 64 * 64 + 64 * 16) + 64 * (sizeof(double2) + sizeof(int));
     auto kern = k_gather_binned<T, CPT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu < 1) ncu = 256;
+    const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
     const BinGeom g = sc_bin_geom(p);
-    hipLaunchKernelGGL(kern, dim3(per_cu * ncu), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
                        p->bw.sorted, (const T *)p->maps, (T *)tod, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
     return hipGetLastError();
 }
@@ -288,13 +283,19 @@ hipError_t launch_binned_t(sc_plan *p, void *tod) {
 // samples 16w + 4 grp + v (v < 4): its orders are k = 8 ct + (r+1)/2, so the
 // k-sum needs e^{i k0 psi} (k0 = (r+1)/2 <= 8, from a per-sample table) and one
 // FP64 rotation by e^{i 8 psi} per component tile.
-template <int CT>
-__global__ void __launch_bounds__(256)
-k_gather_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt,
-              const float *__restrict__ maps, float *__restrict__ tod, int cols, int ncp, int ncomp, int nkc,
-              double beta) {
-    constexpr int NC = 16 * CT;
-    extern __shared__ double smem_d[];
+// LDS bytes of one work item with CT component tiles.
+__host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
+    return sizeof(float) * (64 * 16 * (size_t)CT + 64 * 64 + 64 * 16) +
+           64 * (sizeof(double2) + sizeof(double) + sizeof(int));
+}
+
+// One work item: stage the anchor's map block, then contract its samples 64 at a
+// time.  CTMAX register tiles are reserved; the item uses its detector's ct <= CTMAX
+// (a wave-uniform bound, so the batch kernel serves detectors of any kmax with one
+// instantiation and work proportional to their own component count).
+template <int CTMAX>
+__device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 item, double *smem_d, int ct_n) {
+    const int NC = 16 * ct_n;
     float *Psh = (float *)smem_d;         // [64 taps][NC]
     float *Wsh = Psh + 64 * NC;           // [64 taps][64 samples]; Z0 table after the product
     double2 *Z0 = (double2 *)Wsh;         // [64 samples][9]: e^{i k psi}, k = 0..8
@@ -302,142 +303,183 @@ k_gather_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorte
     double2 *E8 = (double2 *)(W1 + 64 * 16);  // [64] e^{i 8 psi}
     double *Psi = (double *)(E8 + 64);        // [64]
     int *Idx = (int *)(Psi + 64);             // [64]
-    __shared__ int item_sh;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
-    const int nitems = totals[1];
-    const float fbeta = (float)beta;
-    for (;;) {
-        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
-        __syncthreads();
-        const int it = item_sh;
-        if (it >= nitems) break;
-        const int4 item = items[it];
-        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
-        for (int e = tid; e < 64 * NC; e += 256) {
-            const int t = e / NC, c = e - t * NC;
-            float v = 0.f;
-            if (c < ncp) v = maps[((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp + c];
-            Psh[e] = v;
+    const int row0 = item.x / D.nkc, col0 = item.x - (item.x / D.nkc) * D.nkc;
+    for (int e = tid; e < 64 * NC; e += 256) {
+        const int t = e / NC, c = e - t * NC;
+        float v = 0.f;
+        if (c < D.ncp) v = D.maps[((size_t)(row0 + (t >> 3)) * D.cols + (col0 + (t & 7))) * D.ncp + c];
+        Psh[e] = v;
+    }
+    for (int ch = 0; ch < item.z; ch += 64) {
+        const int ns = item.z - ch < 64 ? item.z - ch : 64;
+        const int pos0 = item.y + ch;
+        for (int e = tid; e < 64 * 16; e += 256) {
+            const int q = e >> 6, sl = e & 63;
+            float w = 0.f;
+            if (sl < ns) {
+                const float f = (q < 8) ? (float)D.srt.fu[pos0 + sl] : (float)D.srt.fv[pos0 + sl];
+                w = es_weight<float>((f + (float)(3 - (q & 7))) * 0.25f, D.beta);
+            }
+            W1[e] = w;
         }
-        for (int ch = 0; ch < item.z; ch += 64) {
-            const int ns = item.z - ch < 64 ? item.z - ch : 64;
-            const int pos0 = item.y + ch;
-            for (int e = tid; e < 64 * 16; e += 256) {
-                const int q = e >> 6, sl = e & 63;
-                float w = 0.f;
-                if (sl < ns) {
-                    const float f = (q < 8) ? (float)srt.fu[pos0 + sl] : (float)srt.fv[pos0 + sl];
-                    w = es_weight<float>((f + (float)(3 - (q & 7))) * 0.25f, fbeta);
-                }
-                W1[e] = w;
+        if (tid < 64) {
+            double ps = 0.0;
+            int ix = -1;
+            if (tid < ns) {
+                ps = D.srt.psi[pos0 + tid];
+                ix = D.srt.idx[pos0 + tid];
             }
-            if (tid < 64) {
-                double ps = 0.0;
-                int ix = -1;
-                if (tid < ns) {
-                    ps = srt.psi[pos0 + tid];
-                    ix = srt.idx[pos0 + tid];
-                }
-                Psi[tid] = ps;
-                Idx[tid] = ix;
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * 64; e += 256) {
-                const int t = e >> 6, sl = e & 63;
-                Wsh[e] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
-            }
-            __syncthreads();
+            Psi[tid] = ps;
+            Idx[tid] = ix;
+        }
+        __syncthreads();
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int t = e >> 6, sl = e & 63;
+            Wsh[e] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
+        }
+        __syncthreads();
 
-            floatx4 acc[CT];
+        floatx4 acc[CTMAX];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const float *wa = Wsh + grp * 64 + 16 * wv + r;  // A[i = r][k = grp] of sample tile wv
-            const float *pb = Psh + grp * NC + r;            // B[k = grp][j = r] of component tile 0
+        for (int ct = 0; ct < CTMAX; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float *wa = Wsh + grp * 64 + 16 * wv + r;  // A[i = r][k = grp] of sample tile wv
+        const float *pb = Psh + grp * NC + r;            // B[k = grp][j = r] of component tile 0
 #pragma unroll 2
-            for (int ks = 0; ks < 16; ++ks) {
-                const float a = wa[ks * 4 * 64];
+        for (int ks = 0; ks < 16; ++ks) {
+            const float a = wa[ks * 4 * 64];
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
+            for (int ct = 0; ct < CTMAX; ++ct)
+                if (ct < ct_n)
                     acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, pb[ks * 4 * NC + 16 * ct], acc[ct], 0, 0, 0);
-            }
-            __syncthreads();  // Wsh is dead: per-sample e^{i k psi} table in its place
-            if (tid < 64) {
-                double sn, cs;
-                sincos(Psi[tid], &sn, &cs);
-                const double2 e1 = make_double2(cs, sn);
-                double2 z = make_double2(1.0, 0.0);
+        }
+        __syncthreads();  // Wsh is dead: per-sample e^{i k psi} table in its place
+        if (tid < 64) {
+            double sn, cs;
+            sincos(Psi[tid], &sn, &cs);
+            const double2 e1 = make_double2(cs, sn);
+            double2 z = make_double2(1.0, 0.0);
 #pragma unroll
-                for (int k = 0; k <= 8; ++k) {
-                    Z0[tid * 9 + k] = z;
-                    if (k < 8) z = cmul(z, e1);
-                }
-                E8[tid] = z;
+            for (int k = 0; k <= 8; ++k) {
+                Z0[tid * 9 + k] = z;
+                if (k < 8) z = cmul(z, e1);
             }
-            __syncthreads();
+            E8[tid] = z;
+        }
+        __syncthreads();
 
-            const int k0 = (r + 1) >> 1;
+        const int k0 = (r + 1) >> 1;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int sl = 16 * wv + 4 * grp + v;
-                double2 z = Z0[sl * 9 + k0];
-                const double2 e8 = E8[sl];
-                float part = 0.f;
+        for (int v = 0; v < 4; ++v) {
+            const int sl = 16 * wv + 4 * grp + v;
+            double2 z = Z0[sl * 9 + k0];
+            const double2 e8 = E8[sl];
+            float part = 0.f;
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
+            for (int ct = 0; ct < CTMAX; ++ct) {
+                if (ct < ct_n) {
                     const int c = 16 * ct + r;
                     const float x = acc[ct][v];
-                    if (c < ncomp) part = fmaf(c == 0 ? 1.f : (float)((c & 1) ? z.x : z.y), x, part);
-                    if (ct + 1 < CT) z = cmul(z, e8);
+                    if (c < D.ncomp) part = fmaf(c == 0 ? 1.f : (float)((c & 1) ? z.x : z.y), x, part);
+                    if (ct + 1 < ct_n) z = cmul(z, e8);
                 }
-                part += __shfl_xor(part, 8);
-                part += __shfl_xor(part, 4);
-                part += __shfl_xor(part, 2);
-                part += __shfl_xor(part, 1);
-                if (r == 0 && sl < ns) tod[Idx[sl]] = part;
             }
-            __syncthreads();
+            part += __shfl_xor(part, 8);
+            part += __shfl_xor(part, 4);
+            part += __shfl_xor(part, 2);
+            part += __shfl_xor(part, 1);
+            if (r == 0 && sl < ns) D.tod[Idx[sl]] = part;
         }
+        __syncthreads();
     }
 }
 
 template <int CT>
+__global__ void __launch_bounds__(256)
+k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
+    extern __shared__ double smem_d[];
+    __shared__ int item_sh;
+    const int nitems = D.totals[1];
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+        __syncthreads();
+        const int it = item_sh;
+        if (it >= nitems) break;
+        gather_mfma_item<CT>(D, D.items[it], smem_d, CT);
+    }
+}
+
+// All detectors of a batch in one persistent launch: one queue over the items
+// of every detector (detector d's items follow detector d-1's); each item uses
+// its detector's component-tile count (<= CTMAX).
+template <int CTMAX>
+__global__ void __launch_bounds__(256)
+k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ cursor) {
+    extern __shared__ double smem_d[];
+    __shared__ int start[SC_MAX_DET + 1];
+    __shared__ int item_sh;
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int d = 0; d < ndet; ++d) {
+            start[d] = s;
+            s += dets[d].totals[1];
+        }
+        start[ndet] = s;
+    }
+    __syncthreads();
+    const int total = start[ndet];
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+        __syncthreads();
+        const int it = item_sh;
+        if (it >= total) break;
+        int d = 0;
+        while (d + 1 < ndet && it >= start[d + 1]) ++d;
+        const GatherDet D = dets[d];
+        gather_mfma_item<CTMAX>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);
+    }
+}
+
+// Component tiles as instantiated: 1, 2, 3, 5, 9, 13, 16.
+int ct_class(int ncomp) {
+    const int ct = (ncomp + 15) / 16;
+    if (ct <= 3) return ct < 1 ? 1 : ct;
+    if (ct <= 5) return 5;
+    if (ct <= 9) return 9;
+    if (ct <= 13) return 13;
+    return 16;
+}
+
+int persistent_grid(const void *kern, size_t lds, int wgs_per_cu) {
+    return sc_persistent_grid(kern, 256, lds, wgs_per_cu);
+}
+
+template <int CT>
 hipError_t launch_mfma(sc_plan *p, void *tod) {
-    constexpr int NC = 16 * CT;
     static_assert(64 * 64 * sizeof(float) >= 64 * 9 * sizeof(double2), "Z0 table must fit the weight area");
-    const size_t lds = sizeof(float) * (64 * NC + 64 * 64 + 64 * 16) +
-                       64 * (sizeof(double2) + sizeof(double) + sizeof(int));
+    const size_t lds = mfma_lds_bytes(CT);
     auto kern = k_gather_mfma<CT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu < 1) ncu = 256;
-    const BinGeom g = sc_bin_geom(p);
-    hipLaunchKernelGGL(kern, dim3(per_cu * ncu), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
-                       p->bw.sorted, (const float *)p->maps, (float *)tod, p->cols, p->ncp, p->ncomp, g.nkc,
-                       p->beta);
+    const int grid = persistent_grid((const void *)kern, lds, p->gather_wgs_per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, sc_gather_det(p, tod), p->bw.totals + 2);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_any(sc_plan *p, void *tod) {
-    const int ct = (p->ncomp + 15) / 16;
-    if (ct <= 1) return launch_mfma<1>(p, tod);
-    if (ct <= 2) return launch_mfma<2>(p, tod);
-    if (ct <= 3) return launch_mfma<3>(p, tod);
-    if (ct <= 5) return launch_mfma<5>(p, tod);
-    if (ct <= 9) return launch_mfma<9>(p, tod);
-    if (ct <= 13) return launch_mfma<13>(p, tod);
-    return launch_mfma<16>(p, tod);
+    switch (ct_class(p->ncomp)) {
+        case 1: return launch_mfma<1>(p, tod);
+        case 2: return launch_mfma<2>(p, tod);
+        case 3: return launch_mfma<3>(p, tod);
+        case 5: return launch_mfma<5>(p, tod);
+        case 9: return launch_mfma<9>(p, tod);
+        case 13: return launch_mfma<13>(p, tod);
+        default: return launch_mfma<16>(p, tod);
+    }
 }
-
 }  // namespace
 
 // W = 8 only; the FP64 staging of 208+ components would exceed the 160 KiB of LDS.
@@ -449,6 +491,43 @@ hipError_t sc_launch_gather_binned(sc_plan *p, void *tod) {
     if (p->prec == SC_FP64) return launch_binned_t<double>(p, tod);
     if (p->gather_valu) return launch_binned_t<float>(p, tod);
     return launch_mfma_any(p, tod);
+}
+
+GatherDet sc_gather_det(const sc_plan *p, void *tod) {
+    GatherDet D;
+    D.items = p->bw.items;
+    D.totals = p->bw.totals;
+    D.srt = p->bw.sorted;
+    D.maps = (const float *)p->maps;
+    D.tod = (float *)tod;
+    D.cols = p->cols;
+    D.ncp = p->ncp;
+    D.ncomp = p->ncomp;
+    D.nkc = sc_bin_geom(p).nkc;
+    D.beta = (float)p->beta;
+    D.ct = ct_class(p->ncomp);
+    return D;
+}
+
+template <int CTMAX>
+static hipError_t gather_batch(const GatherDet *dets_dev, int ndet, int *cursor, int wgs_per_cu, hipStream_t stream) {
+    const size_t lds = mfma_lds_bytes(CTMAX);
+    auto kern = k_gather_batch<CTMAX>;
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
+    if (e != hipSuccess) return e;
+    const int grid = persistent_grid((const void *)kern, lds, wgs_per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, stream, dets_dev, ndet, cursor);
+    return hipGetLastError();
+}
+
+// One persistent launch over the binned items of several FP32 plans; max_ct is
+// the largest component-tile count among them.
+hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
+                                  hipStream_t stream) {
+    if (max_ct <= 2) return gather_batch<2>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 5) return gather_batch<5>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 13) return gather_batch<13>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    return gather_batch<16>(dets_dev, ndet, cursor, wgs_per_cu, stream);
 }
 
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod) {

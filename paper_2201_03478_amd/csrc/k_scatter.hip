@@ -212,18 +212,11 @@ hipError_t launch_scatter_mfma(sc_plan *p, const void *y, void *gmaps) {
     constexpr int NC = 16 * CT;
     const size_t lds = sizeof(float) * (64 * NC + 64 * WROW + 64 * 16) + 64 * (sizeof(double2) + sizeof(float));
     auto kern = k_scatter_mfma<CT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu < 1) ncu = 256;
+    const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
     const BinGeom g = sc_bin_geom(p);
-    hipLaunchKernelGGL(kern, dim3(per_cu * ncu), dim3(256), lds, p->stream, p->bw.items, p->bw.totals, p->bw.sorted,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals, p->bw.sorted,
                        (const float *)y, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
     return hipGetLastError();
 }

@@ -59,7 +59,7 @@ template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
-            int ngroups) {
+            int ngroups, int alm_lmax) {
     __shared__ double cA[64], cB[64], cC[64];
     __shared__ double2 cWp[64], cWm[64];
 
@@ -94,7 +94,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     }
 
     const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
-    const size_t aoff = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     for (int lc = l0; lc <= lmax; lc += 64) {
         const int l = lc + lane;
@@ -150,7 +150,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     case R:                                                                                                  \
         hipLaunchKernelGGL(k_ring_sums<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,         \
                            (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,      \
-                           p->ngroups);                                                                      \
+                           p->ngroups, p->alm_lmax);                                                         \
         break;
 
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm) {

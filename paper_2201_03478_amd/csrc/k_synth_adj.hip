@@ -192,7 +192,7 @@ static void adj_layout(int nring, int *rpt, int *nw) {
 #define SC_ADJ_CASE(R)                                                                                       \
     case R: {                                                                                                \
         auto kern = k_ring_sums_adjoint<R>;                                                                  \
-        e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        e = sc_set_lds_attr((const void *)kern, lds);   \
         if (e != hipSuccess) return e;                                                                       \
         hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)blm,      \
                            p->GA, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring);                          \

@@ -39,7 +39,7 @@ template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
                   const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
-                  int ngroups) {
+                  int ngroups, int alm_lmax) {
     __shared__ float cA[64], cB[64], cC[64];
     __shared__ float cW[64][4];
     __shared__ float Fs[RPT][64][4];
@@ -88,7 +88,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
     }
 
     const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
-    const size_t aoff = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     const int comp = lane & 3;
     for (int lc = l0; lc <= lmax; lc += 64) {
@@ -163,7 +163,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
     case R:                                                                                                  \
         hipLaunchKernelGGL(k_ring_sums_mixed<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,   \
                            (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,      \
-                           p->ngroups_mx);                                                                   \
+                           p->ngroups_mx, p->alm_lmax);                                                     \
         break;
 
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm) {

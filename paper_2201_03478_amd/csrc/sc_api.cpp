@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <vector>
 
 #include "sc_common.h"
 
@@ -103,6 +104,9 @@ int alloc(void **dst, size_t bytes, size_t *total);
 int ensure_bin_work(sc_plan *p, int64_t need) {
     BinWork &w = p->bw;
     if (w.cap >= need) return SC_OK;
+    if (p->bin_fixed)
+        return fail(SC_ESTATE, "plan belongs to a batch: %lld samples exceed its %lld-sample buffers",
+                    (long long)need, (long long)w.cap);
     // buffers are in use by earlier work on the stream until it completes
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return fail(SC_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
@@ -165,6 +169,16 @@ int alloc(void **dst, size_t bytes, size_t *total) {
     return SC_OK;
 }
 
+struct AttrCache {
+    std::mutex mu;
+    std::map<const void *, size_t> lds;
+    std::map<std::tuple<const void *, int, size_t, int, int>, int> grid;
+};
+AttrCache &attr_cache() {
+    static AttrCache *c = new AttrCache();
+    return *c;
+}
+
 struct PlanCache {
     std::mutex mu;
     std::map<std::tuple<int, int, int, int>, sc_plan *> plans;
@@ -175,6 +189,38 @@ PlanCache &plan_cache() {
 }
 
 }  // namespace
+
+hipError_t sc_set_lds_attr(const void *kern, size_t lds) {
+    AttrCache &c = attr_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto it = c.lds.find(kern);
+    if (it != c.lds.end() && it->second >= lds) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) c.lds[kern] = lds;
+    return e;
+}
+
+int sc_persistent_grid(const void *kern, int block, size_t lds, int wgs_per_cu) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    AttrCache &c = attr_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto key = std::make_tuple(kern, block, lds, wgs_per_cu, dev);
+    auto it = c.grid.find(key);
+    if (it != c.grid.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    if (per_cu < 1) per_cu = 1;
+    if (wgs_per_cu > 0 && wgs_per_cu < per_cu) per_cu = wgs_per_cu;
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 256;
+    c.grid[key] = per_cu * ncu;
+    return per_cu * ncu;
+}
 
 extern "C" {
 
@@ -225,6 +271,9 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->ncomp = 2 * kmax + 1;
     p->ncp = (p->ncomp + 3) & ~3;
     p->nq = 128;
+    p->alm_lmax = lmax;
+    p->bin_chunk = BIN_CHUNK;
+    p->gather_wgs_per_cu = 0;
     {
         const char *g = std::getenv("SC_GATHER_PATH");
         p->gather_direct = (g && std::strcmp(g, "direct") == 0) ? 1 : 0;
@@ -447,6 +496,50 @@ int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const 
     return SC_OK;
 }
 
+int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    switch (param) {
+        case SC_PARAM_BIN_CHUNK:
+            if (v < 16 || v > (1 << 20)) return fail(SC_EINVAL, "bin chunk %lld outside [16, 2^20]", (long long)v);
+            p->bin_chunk = (int)v;
+            return SC_OK;
+        case SC_PARAM_GATHER_WGS_PER_CU:
+            if (v < 0 || v > 16) return fail(SC_EINVAL, "workgroups per CU %lld outside [0, 16]", (long long)v);
+            p->gather_wgs_per_cu = (int)v;
+            return SC_OK;
+        case SC_PARAM_RING_RPT: {
+            const int vmax = p->prec == SC_MIXED ? 8 : 4;
+            if (v < 1 || v > vmax) return fail(SC_EINVAL, "rings per lane %lld outside [1, %d]", (long long)v, vmax);
+            const int g = (p->nring + 64 * (int)v - 1) / (64 * (int)v);
+            if (p->prec == SC_MIXED) {
+                p->rpt_mx = (int)v;
+                p->ngroups_mx = g;
+            } else {
+                p->rpt = (int)v;
+                p->ngroups = g;
+            }
+            return SC_OK;
+        }
+        case SC_PARAM_SKY_LMAX:
+            if (v < p->lmax || v > 65535) return fail(SC_EINVAL, "sky lmax %lld below the plan's lmax %d", (long long)v, p->lmax);
+            p->alm_lmax = (int)v;
+            return SC_OK;
+        default:
+            return fail(SC_EINVAL, "unknown parameter %d", param);
+    }
+}
+
+int sc_plan_get_param(const sc_plan *p, int param, int64_t *v) {
+    if (!p || !v) return fail(SC_EINVAL, "NULL plan or output");
+    switch (param) {
+        case SC_PARAM_BIN_CHUNK: *v = p->bin_chunk; return SC_OK;
+        case SC_PARAM_GATHER_WGS_PER_CU: *v = p->gather_wgs_per_cu; return SC_OK;
+        case SC_PARAM_RING_RPT: *v = p->prec == SC_MIXED ? p->rpt_mx : p->rpt; return SC_OK;
+        case SC_PARAM_SKY_LMAX: *v = p->alm_lmax; return SC_OK;
+        default: return fail(SC_EINVAL, "unknown parameter %d", param);
+    }
+}
+
 int sc_plan_enable_timing(sc_plan *p, int enable) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
     p->timing = enable ? 1 : 0;
@@ -496,6 +589,220 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(e, "stage copy");
     return (int64_t)bytes;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of detectors: one shared sky, one plan (maps) per detector, one
+// persistent gather launch over all detectors' work items; the whole sequence
+// can be captured in a hipGraph and replayed.
+struct sc_batch {
+    int ndet, lmax_sky, prec;
+    hipStream_t stream;
+    std::vector<sc_plan *> plans;
+    std::vector<sc_det_desc> dets;
+    GatherDet *dets_dev;
+    int *cursor;
+    int max_ct;
+    int wgs_per_cu;
+    int warmed;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    const double *graph_alm;
+    hipStream_t cap_stream;  // private stream for capture (the legacy null stream cannot be captured)
+};
+
+namespace {
+
+void batch_drop_graph(sc_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_alm = nullptr;
+}
+
+// Enqueue one full batch pass on stream s (no host synchronisation, capture-safe).
+hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s) {
+    for (sc_plan *p : b->plans) p->stream = s;
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < b->ndet && e == hipSuccess; ++d) {
+        sc_plan *p = b->plans[d];
+        const sc_det_desc &D = b->dets[d];
+        e = p->prec == SC_MIXED ? sc_launch_ring_sums_mixed(p, alm, D.blm) : sc_launch_ring_sums(p, alm, D.blm);
+        if (e == hipSuccess) e = sc_launch_theta_upsample(p);
+        if (e == hipSuccess) e = sc_launch_phi_synthesis(p);
+        if (e == hipSuccess)
+            e = D.n > 0 ? sc_launch_binning(p, D.ptg, D.n) : sc_launch_zero(p->bw.totals, 4 * sizeof(int), s);
+    }
+    if (e == hipSuccess) e = sc_launch_zero(b->cursor, sizeof(int), s);
+    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, s);
+    for (sc_plan *p : b->plans) p->stream = b->stream;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sc_batch_destroy(sc_batch *b) {
+    if (!b) return SC_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (sc_plan *p : b->plans) sc_plan_destroy(p);
+    if (b->dets_dev) (void)hipFree(b->dets_dev);
+    if (b->cursor) (void)hipFree(b->cursor);
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in sc_batch_destroy");
+    return SC_OK;
+}
+
+int sc_batch_create(sc_batch **out, const sc_det_desc *dets, int ndet, int lmax_sky, int precision, void *stream) {
+    g_msg[0] = 0;
+    if (!out) return fail(SC_EINVAL, "batch output pointer is NULL");
+    *out = nullptr;
+    if (!dets || ndet < 1 || ndet > SC_MAX_DET) return fail(SC_EINVAL, "ndet = %d outside [1, %d]", ndet, SC_MAX_DET);
+    if (precision != SC_F64MAPS_F32GATHER && precision != SC_MIXED)
+        return fail(SC_EINVAL, "batches need FP32 maps (precision %d)", precision);
+    for (int d = 0; d < ndet; ++d) {
+        const sc_det_desc &D = dets[d];
+        if (D.lmax < 0 || D.lmax > lmax_sky || D.kmax < 0 || D.kmax > D.lmax)
+            return fail(SC_EINVAL, "detector %d: lmax %d / kmax %d invalid for sky lmax %d", d, D.lmax, D.kmax, lmax_sky);
+        if (D.n < 0 || D.n > BIN_PASS_MAX)
+            return fail(SC_EINVAL, "detector %d: n = %lld outside [0, %d]", d, (long long)D.n, BIN_PASS_MAX);
+        if (!is_device_ptr(D.blm) || (D.n > 0 && (!is_device_ptr(D.ptg) || !is_device_ptr(D.tod))))
+            return fail(SC_EINVAL, "detector %d: blm/ptg/tod is not device memory", d);
+    }
+    sc_batch *b = new (std::nothrow) sc_batch();
+    if (!b) return fail(SC_ENOMEM, "host allocation failed");
+    b->ndet = ndet;
+    b->lmax_sky = lmax_sky;
+    b->prec = precision;
+    b->stream = (hipStream_t)stream;
+    b->dets.assign(dets, dets + ndet);
+    std::vector<GatherDet> gd(ndet);
+    for (int d = 0; d < ndet; ++d) {
+        sc_plan *p = nullptr;
+        int rc = sc_plan_create(&p, dets[d].lmax, dets[d].kmax, precision, 8, stream);
+        if (!rc) {
+            b->plans.push_back(p);
+            p->alm_lmax = lmax_sky;
+            rc = ensure_bin_work(p, dets[d].n > 0 ? dets[d].n : 1);
+            p->bin_fixed = 1;
+        }
+        if (rc) {
+            sc_batch_destroy(b);
+            return rc;
+        }
+        gd[d] = sc_gather_det(p, dets[d].tod);
+        const int ct = (p->ncomp + 15) / 16;
+        if (ct > b->max_ct) b->max_ct = ct;
+    }
+    size_t tot = 0;
+    int rc = alloc((void **)&b->dets_dev, sizeof(GatherDet) * ndet, &tot);
+    if (!rc) rc = alloc((void **)&b->cursor, sizeof(int), &tot);
+    if (rc) {
+        sc_batch_destroy(b);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(b->dets_dev, gd.data(), sizeof(GatherDet) * ndet, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        sc_batch_destroy(b);
+        return hip_fail(e, "batch descriptor upload");
+    }
+    *out = b;
+    return SC_OK;
+}
+
+int sc_batch_set_param(sc_batch *b, int det, int param, int64_t value) {
+    if (!b) return fail(SC_EINVAL, "batch is NULL");
+    if (param == SC_PARAM_GATHER_WGS_PER_CU) {
+        if (value < 0 || value > 16) return fail(SC_EINVAL, "workgroups per CU outside [0, 16]");
+        b->wgs_per_cu = (int)value;
+        batch_drop_graph(b);
+        return SC_OK;
+    }
+    if (param == SC_PARAM_SKY_LMAX) return fail(SC_EINVAL, "the sky lmax of a batch is fixed at creation");
+    if (det < -1 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [-1, %d)", det, b->ndet);
+    for (int d = 0; d < b->ndet; ++d) {
+        if (det >= 0 && d != det) continue;
+        int rc = sc_plan_set_param(b->plans[d], param, value);
+        if (rc) return rc;
+    }
+    batch_drop_graph(b);
+    return SC_OK;
+}
+
+int sc_batch_get_param(const sc_batch *b, int det, int param, int64_t *value) {
+    if (!b || !value) return fail(SC_EINVAL, "NULL batch or output");
+    if (param == SC_PARAM_GATHER_WGS_PER_CU) {
+        *value = b->wgs_per_cu;
+        return SC_OK;
+    }
+    if (det < 0 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [0, %d)", det, b->ndet);
+    return sc_plan_get_param(b->plans[det], param, value);
+}
+
+int sc_batch_run(sc_batch *b, const double *alm_sky, int use_graph) {
+    g_msg[0] = 0;
+    if (!b) return fail(SC_EINVAL, "batch is NULL");
+    if (!is_device_ptr(alm_sky) || ((uintptr_t)alm_sky & 15)) return fail(SC_EINVAL, "alm_sky is not aligned device memory");
+    hipError_t e = hipSuccess;
+    if (!use_graph) {
+        e = batch_enqueue(b, alm_sky, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        return SC_OK;
+    }
+    if (b->exec && b->graph_alm == alm_sky) {
+        e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        return SC_OK;
+    }
+    if (!b->warmed) {
+        // one eager pass first: kernel attributes and launch shapes get cached
+        // outside the capture
+        e = batch_enqueue(b, alm_sky, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        b->warmed = 1;
+    }
+    batch_drop_graph(b);
+    if (!b->cap_stream) {
+        e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            b->cap_stream = nullptr;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+    }
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t e2 = batch_enqueue(b, alm_sky, b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &b->graph);
+    if (e2 != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(e2, "batch capture");
+    }
+    if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph_alm = alm_sky;
+    e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SC_OK;
+}
+
+int sc_batch_plan(sc_batch *b, int det, sc_plan **plan) {
+    if (!b || !plan || det < 0 || det >= b->ndet) return fail(SC_EINVAL, "bad batch, detector or output");
+    *plan = b->plans[det];
+    return SC_OK;
 }
 
 }  // extern "C"

@@ -22,7 +22,7 @@ struct FftPlan {
     int r[SC_MAX_RADICES];
 };
 
-// Samples per work item of the binned gather, and samples per binning pass.
+// Default samples per work item of the binned gather, and samples per binning pass.
 #define BIN_CHUNK 256
 #define BIN_PASS_MAX (1 << 24)
 
@@ -39,6 +39,20 @@ struct BinSorted {
     double *psi;     // psi reduced to [0, 2 pi)
     int *idx;        // index of the sample within its pass
 };
+
+// One detector's inputs to the persistent (batched) FP32 gather.
+struct GatherDet {
+    const int4 *items;
+    const int *totals;
+    BinSorted srt;
+    const float *maps;
+    float *tod;
+    int cols, ncp, ncomp, nkc;
+    float beta;
+    int ct;  // component tiles (instantiated class)
+};
+
+#define SC_MAX_DET 64
 
 struct BinWork {
     int64_t cap;      // samples per pass the buffers hold
@@ -86,6 +100,10 @@ struct sc_plan {
     void *gmaps;       // adjoint: gradient maps, same layout as maps (allocated on first use)
     double2 *GA;       // adjoint: per-k gradient contributions [kmax+1][n_alm]
     size_t adj_bytes;
+    int alm_lmax;          // band limit of the sky array's layout (>= lmax; a shared sky may be larger)
+    int bin_fixed;         // binning buffers are referenced by a batch: never reallocate them
+    int bin_chunk;         // samples per gather work item (tunable)
+    int gather_wgs_per_cu; // persistent gather workgroups per CU (0: as many as fit; tunable)
     int gather_direct;     // force the per-sample gather (env SC_GATHER_PATH=direct)
     int gather_valu;       // FP32 binned gather on the VALU instead of MFMA (env SC_GATHER_PATH=valu)
     int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
@@ -124,6 +142,9 @@ hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
 hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
+GatherDet sc_gather_det(const sc_plan *p, void *tod);
+hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
+                                  hipStream_t stream);
 bool sc_gather_binned_supported(const sc_plan *p);
 
 static inline BinGeom sc_bin_geom(const sc_plan *p) {
@@ -137,6 +158,12 @@ static inline BinGeom sc_bin_geom(const sc_plan *p) {
     g.nkc = p->nphi;
     return g;
 }
+
+// Set a kernel's dynamic-LDS limit once (cached; safe to call while a stream is
+// being captured into a graph, since a cached call makes no runtime call).
+hipError_t sc_set_lds_attr(const void *kern, size_t lds);
+// Workgroups of a persistent launch: occupancy per CU (optionally capped) x CUs (cached).
+int sc_persistent_grid(const void *kern, int block, size_t lds, int wgs_per_cu);
 
 // ------------------------------------------------------------ device helpers
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).

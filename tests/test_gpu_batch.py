@@ -1,0 +1,132 @@
+"""Batched detectors: one shared sky, per-detector beams/band limits/pointings,
+one persistent gather launch, hipGraph capture and replay, the autotuner.
+
+Each detector is the convolution of Eq. 2 (Galloway et al. 2022, Sec. 2.1) with
+its own beam; the batch must give exactly what separate plans give (same
+kernels and per-sample arithmetic), and match the oracle to the FP32-form bar.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.generators import truncate_alm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2201_03478_amd import api
+    api.N.load()
+    return torch, api, torch.device("cuda", 0)
+
+
+def _to(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+SMALL = [(64, 8, 3000), (40, 32, 2500), (32, 4, 1000), (80, 0, 777), (48, 20, 0)]
+
+
+def _small_batch(torch, dev, lmax_sky=80):
+    dets = []
+    for i, (L, K, n) in enumerate(SMALL):
+        p = W.uniform_pointings(n, 500 + i)
+        if n:
+            p[0] = [0.0, 1.0, 2.0]
+        dets.append(dict(lmax=L, kmax=K, blm=_to(torch, dev, W.beam_alm(L, K, 600 + i)),
+                         ptg=_to(torch, dev, p.reshape(-1, 3))))
+    sky = _to(torch, dev, W.sky_alm(lmax_sky, 700))
+    return dets, sky
+
+
+def _single(torch, api, d, sky, lmax_sky):
+    plan = api.Plan(d["lmax"], d["kmax"])
+    plan.set_param("sky_lmax", lmax_sky)
+    plan.set_sky_beam(sky, d["blm"])
+    return plan.interpolate(d["ptg"])
+
+
+def test_batch_equals_separate_plans(env):
+    torch, api, dev = env
+    dets, sky = _small_batch(torch, dev)
+    b = api.Batch(dets, 80)
+    outs = [t.clone() for t in b.run(sky, use_graph=False)]
+    torch.cuda.synchronize()
+    for d, o in zip(b.dets, outs):
+        ref = _single(torch, api, d, sky, 80)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref), (d["lmax"], d["kmax"])
+
+
+def test_batch_graph_replays_match_eager(env):
+    """Replays interleaved with eager work; the captured graph reads the current sky contents."""
+    torch, api, dev = env
+    dets, sky = _small_batch(torch, dev)
+    b = api.Batch(dets, 80)
+    for rep in range(4):
+        if rep:
+            sky.mul_(1.25)  # same buffer, new contents
+        graph_out = [t.clone() for t in b.run(sky, use_graph=True)]
+        torch.cuda.synchronize()
+        eager_out = [t.clone() for t in b.run(sky, use_graph=False)]
+        torch.cuda.synchronize()
+        for g, e in zip(graph_out, eager_out):
+            assert torch.equal(g, e), rep
+
+
+def test_batch_matches_oracle_and_autotune_keeps_results(env, oracle_lib, tmp_path):
+    torch, api, dev = env
+    from paper_2201_03478_amd import autotune
+    dets, sky = _small_batch(torch, dev)
+    b = api.Batch(dets, 80)
+    before = [t.clone() for t in b.run(sky, use_graph=False)]
+    torch.cuda.synchronize()
+    sky_np = sky.cpu().numpy()
+    for d, o in zip(b.dets, before):
+        if d["ptg"].shape[0] == 0:
+            continue
+        ref = oracle_lib.convolve(truncate_alm(sky_np, 80, d["lmax"]), d["blm"].cpu().numpy(), d["lmax"],
+                                  d["kmax"], d["ptg"].cpu().numpy())
+        e = np.linalg.norm(o.double().cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert e <= 1e-6, (d["lmax"], d["kmax"], e)
+    os.environ["SC_AUTOTUNE_CACHE"] = str(tmp_path / "tune.json")
+    try:
+        chosen = autotune.tune_batch(b, sky, reps=1)
+    finally:
+        os.environ.pop("SC_AUTOTUNE_CACHE")
+    assert len(chosen) == len(SMALL)
+    after = [t.clone() for t in b.run(sky, use_graph=True)]
+    torch.cuda.synchronize()
+    for x, y in zip(before, after):
+        assert torch.equal(x, y)
+
+
+def test_batched_workload_full_size(env, oracle_lib):
+    """12 detectors, lmax in {256, 512, 1024}, kmax in {8, 32, 100}, 4e7 scan samples in one
+    persistent launch (hipGraph replay); 4 sampled outputs per detector against the oracle."""
+    torch, api, dev = env
+    sky_np = W.sky_alm(1024, W.config_seed(4, 1))
+    sky = _to(torch, dev, sky_np)
+    dets = []
+    for i, (L, K, n) in enumerate(W.DETECTORS):
+        dets.append(dict(lmax=L, kmax=K, blm=_to(torch, dev, W.beam_alm(L, K, W.config_seed(4, 10 + i))),
+                         ptg=W.scan_pointings(n, t0=1000.0 * i, psi0=i * math.pi / 12, device=dev)))
+    b = api.Batch(dets, 1024)
+    b.run(sky, use_graph=True)  # eager pass + capture + replay
+    b.run(sky, use_graph=True)  # replay
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(W.config_seed(4, 6))
+    for i, d in enumerate(b.dets):
+        n = d["ptg"].shape[0]
+        idx = torch.as_tensor(np.sort(rng.choice(n, 4, replace=False)), device=dev)
+        got = d["tod"][idx].double().cpu().numpy()
+        ref = oracle_lib.convolve(truncate_alm(sky_np, 1024, d["lmax"]), d["blm"].cpu().numpy(), d["lmax"],
+                                  d["kmax"], d["ptg"][idx].cpu().numpy())
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print("detector %d (lmax %d kmax %d n %d): rel-L2 %.3e" % (i, d["lmax"], d["kmax"], n, e))
+        assert e <= 1e-6
