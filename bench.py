@@ -50,8 +50,8 @@ def stage_model(info: dict, n: int, prec: int):
     esz = 8 if prec == 0 else 4
     dv = ring_dvalues(L, K, nr)
     return {
-        # 3 FMA recursion + 4 FMA contraction (both signs of m) per d value
-        "ring_sums": ("alu", 14.0 * dv, "TFLOP/s", PEAK["fp64"]),
+        # 2 FMA recursion (normalised three-term form) + 4 FMA contraction (both signs of m) per d value
+        "ring_sums": ("alu", 12.0 * dv, "TFLOP/s", PEAK["fp64"]),
         # read F, write the upsampled spectra
         "theta_upsample": ("hbm", 16.0 * (K + 1) * nm * (nr + rows), "GB/s", PEAK["hbm"]),
         # read the spectra, write the real components of the maps
@@ -210,6 +210,10 @@ def main():
         "roofline": roofline,
     }
 
+    # steady state with the maps already built (binning + gather only)
+    ms_g = _event_ms(torch, lambda: plan.interpolate(ptg, out=tod), args.steps)
+    result["gather_only"] = {"ms_per_step": ms_g, "value": n / (ms_g * 1e-3)}
+
     # oracle on a bounded random sample: CPU baseline and the error of this run
     sel = np.sort(np.random.default_rng(W.config_seed(2, 6)).choice(n, 4096, replace=False))
     if not args.no_cpu_baseline:
@@ -230,6 +234,11 @@ def main():
         print("bench: oracle %d samples in %.1f s, rel err %.2e" % (m, dt, result["rel_err_vs_oracle"]),
               file=sys.stderr, flush=True)
         ref_sub, idx_sub = ref, idx
+        m1 = 2
+        t0 = time.perf_counter()
+        oracle.convolve(a_np, b_np, L, K, sub[:m1], nthreads=1)
+        result["cpu_baseline_1core"] = {"value": m1 / (time.perf_counter() - t0), "unit": "samples/s", "cores": 1,
+                                        "kind": "oracle", "sample": "the first %d of the samples above" % m1}
     del plan, tod
 
     if not args.no_fp64_form and args.precision != "fp64":
@@ -243,6 +252,16 @@ def main():
         result["fp64_form"] = form
         result["speedup_vs_fp64_form"] = ms64 / ms
         del p64, tod64
+        # the FP64 form at its own 1e-12 width (W = 14)
+        p14, tod14, ms14, st14 = run_form(torch, api, dev, a, b, ptg, L, K, "fp64", 14, 1, 1)
+        form = {"precision": "fp64", "W": 14, "ms_per_step": ms14, "value": n / (ms14 * 1e-3),
+                "stages_ms_per_step": {s: t for s, (t, c) in st14.items() if c}}
+        if not args.no_cpu_baseline:
+            got14 = tod14[torch.as_tensor(idx_sub, device=dev)].cpu().numpy()
+            form["rel_err_vs_oracle"] = float(np.linalg.norm(got14 - ref_sub) / np.linalg.norm(ref_sub))
+        result["fp64_w14_form"] = form
+        del p14, tod14
+        print("bench: fp64 forms done", file=sys.stderr, flush=True)
 
     if not args.no_extras:
         for name, fn in (("precision_variant", extra_precision), ("adjoint", extra_adjoint),

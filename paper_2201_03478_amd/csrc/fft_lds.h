@@ -1,39 +1,105 @@
-// fft_lds.h -- mixed-radix (2, 3, 4, 5) Stockham autosort FFT of one complex
-// FP64 sequence held in LDS, computed by one workgroup.
+// fft_lds.h -- mixed-radix Stockham autosort FFT of one complex FP64 sequence
+// held in LDS, computed by one workgroup.
 //
-// Each stage of radix R reads R strided inputs per butterfly, applies the
-// twiddles e^{DIR 2 pi i r (j mod Ns) / (Ns R)}, does a radix-R DFT in
-// registers and writes the R outputs Ns apart; all reads of a stage finish
-// (barrier) before its writes, so one LDS buffer suffices.  DIR = -1 is the
-// forward transform sum_j x_j e^{-2 pi i n j / N}, DIR = +1 the unnormalised
-// inverse.  Twiddles come from a table tw[t] = e^{-2 pi i t / N}.
+// A transform of length N = 2^a 3^b 5^c is split into passes of radix
+// R in {2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16}.  A pass of radix R reads R
+// inputs N / R apart per butterfly, applies the twiddles
+// e^{DIR 2 pi i r (j mod Ns) / (Ns R)}, does the R-point DFT in registers and
+// writes the R outputs Ns apart (Ns = product of the earlier radices); all
+// reads of a pass finish (barrier) before its writes, so one LDS buffer
+// suffices.  Radices above 5 are register sub-transforms R = R1 R2 (R2 DFTs of
+// length R1, constant twiddles e^{DIR 2 pi i n2 k1 / R}, R1 DFTs of length R2),
+// so the data crosses LDS once per pass, not once per prime factor.
+// DIR = -1 is the forward transform sum_j x_j e^{-2 pi i n j / N}, DIR = +1 the
+// unnormalised inverse.  Pass twiddles come from a table tw[t] = e^{-2 pi i t / N};
+// the first pass (Ns = 1) has unit twiddles and loads none.
+//
+// Size classes: NT threads per workgroup and at most PT points per thread
+// (N <= NT PT); a radix-R pass holds ceil(PT / R) butterflies per thread.
 #pragma once
 
 #include "sc_common.h"
 
-// Threads per transform workgroup and the longest transform each size handles
-// (register staging holds ceil(MAXN / (R * NT)) radix-R butterflies per thread).
 #define SC_FFT_NT 256
 #define SC_FFT_NT_BIG 512
-#define SC_FFT_MAXN_PER_THREAD 16
+#define SC_FFT_PT 9
+#define SC_FFT_NT_HUGE 1024
+#define SC_FFT_PT_HUGE 8
+
+// ---------------------------------------------------------------------------
+// Compile-time cos / sin of 2 pi a / R (constants of the register sub-transforms):
+// reduce to an octant, then Taylor series on |x| <= pi / 4.
+namespace fftc {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double sin_small(double x) {
+    double t = x, s = x;
+    for (int n = 1; n <= 12; ++n) {
+        t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        s += t;
+    }
+    return s;
+}
+
+constexpr double cos_small(double x) {
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n <= 12; ++n) {
+        t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        s += t;
+    }
+    return s;
+}
+
+struct CS {
+    double c, s;
+};
+
+// cos and sin of the angle q pi / 2 + phi
+constexpr CS quadrant(int q, double cphi, double sphi) {
+    q &= 3;
+    return q == 0 ? CS{cphi, sphi} : q == 1 ? CS{-sphi, cphi} : q == 2 ? CS{-cphi, -sphi} : CS{sphi, -cphi};
+}
+
+// e^{2 pi i a / R} = (cos, sin)
+constexpr CS cis(int a, int R) {
+    const int f = ((a % R) + R) % R;  // angle (pi / 4) * (8 f / R)
+    const int u = 8 * f, o = u / R, rem = u - o * R;
+    if ((o & 1) == 0) {
+        const double x = (kPi / 4.0) * rem / R;  // angle = (o / 2) pi / 2 + x
+        return quadrant(o / 2, cos_small(x), sin_small(x));
+    }
+    const double y = (kPi / 4.0) * (R - rem) / R;  // angle = (o / 2 + 1) pi / 2 - y
+    return quadrant(o / 2 + 1, cos_small(y), -sin_small(y));
+}
+
+template <int R>
+struct CisTable {
+    double c[R], s[R];
+    constexpr CisTable() : c(), s() {
+        for (int a = 0; a < R; ++a) {
+            const CS w = cis(a, R);
+            c[a] = w.c;
+            s[a] = w.s;
+        }
+    }
+};
+
+}  // namespace fftc
 
 __device__ __forceinline__ double2 mul_i(double2 a, int dir) {
     // dir * i * a
     return dir > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dft_small(double2 *v);
+// ---------------------------------------------------------------------------
+// Base DFTs (R = 2, 3, 4, 5), in place: v[k] <- sum_n v[n] e^{DIR 2 pi i n k / R}.
 
-template <>
-__device__ __forceinline__ void dft_small<2, -1>(double2 *v) {
-    double2 a = v[0];
+template <int DIR>
+__device__ __forceinline__ void dft2(double2 *v) {
+    const double2 a = v[0];
     v[0] = cadd(a, v[1]);
     v[1] = csub(a, v[1]);
-}
-template <>
-__device__ __forceinline__ void dft_small<2, 1>(double2 *v) {
-    dft_small<2, -1>(v);
 }
 
 template <int DIR>
@@ -46,10 +112,6 @@ __device__ __forceinline__ void dft4(double2 *v) {
     v[1] = cadd(d02, id13);
     v[3] = csub(d02, id13);
 }
-template <>
-__device__ __forceinline__ void dft_small<4, -1>(double2 *v) { dft4<-1>(v); }
-template <>
-__device__ __forceinline__ void dft_small<4, 1>(double2 *v) { dft4<1>(v); }
 
 template <int DIR>
 __device__ __forceinline__ void dft3(double2 *v) {
@@ -61,10 +123,6 @@ __device__ __forceinline__ void dft3(double2 *v) {
     v[1] = cadd(t2, t3);
     v[2] = csub(t2, t3);
 }
-template <>
-__device__ __forceinline__ void dft_small<3, -1>(double2 *v) { dft3<-1>(v); }
-template <>
-__device__ __forceinline__ void dft_small<3, 1>(double2 *v) { dft3<1>(v); }
 
 template <int DIR>
 __device__ __forceinline__ void dft5(double2 *v) {
@@ -85,28 +143,103 @@ __device__ __forceinline__ void dft5(double2 *v) {
     v[2] = cadd(b2, ie2);
     v[3] = csub(b2, ie2);
 }
-template <>
-__device__ __forceinline__ void dft_small<5, -1>(double2 *v) { dft5<-1>(v); }
-template <>
-__device__ __forceinline__ void dft_small<5, 1>(double2 *v) { dft5<1>(v); }
 
-template <int R, int DIR, int NT>
-__device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, const double2 *__restrict__ tw,
-                                               int tid, int nth) {
-    constexpr int B = (SC_FFT_MAXN_PER_THREAD * NT / R + NT - 1) / NT;
+template <int R, int DIR>
+__device__ __forceinline__ void dft_base(double2 *v) {
+    if constexpr (R == 2)
+        dft2<DIR>(v);
+    else if constexpr (R == 3)
+        dft3<DIR>(v);
+    else if constexpr (R == 4)
+        dft4<DIR>(v);
+    else
+        dft5<DIR>(v);
+}
+
+// x * e^{DIR 2 pi i e / R} for a twiddle exponent e that is a constant after unrolling;
+// the trivial angles cost no multiplications.
+template <int R, int DIR>
+__device__ __forceinline__ double2 twiddle_const(double2 x, int e) {
+    constexpr fftc::CisTable<R> T{};
+    e %= R;
+    if (e == 0) return x;
+    if (2 * e == R) return make_double2(-x.x, -x.y);
+    if (4 * e == R) return mul_i(x, DIR);
+    if (4 * e == 3 * R) return mul_i(x, -DIR);
+    return cmul(x, make_double2(T.c[e], DIR * T.s[e]));
+}
+
+// Composite DFT R = R1 R2 (Cooley-Tukey, all indices compile-time after unrolling):
+// X[k1 + R1 k2] = sum_{n2} e^{DIR 2 pi i n2 k2 / R2} e^{DIR 2 pi i n2 k1 / R}
+//                 sum_{n1} v[R2 n1 + n2] e^{DIR 2 pi i n1 k1 / R1}.
+template <int R1, int R2, int DIR>
+__device__ __forceinline__ void dft_ct(double2 *v) {
+    constexpr int R = R1 * R2;
+    double2 y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        double2 t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+        dft_base<R1, DIR>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = twiddle_const<R, DIR>(t[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        double2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2 * R1 + k1];
+        dft_base<R2, DIR>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_small(double2 *v) {
+    if constexpr (R <= 5)
+        dft_base<R, DIR>(v);
+    else if constexpr (R == 6)
+        dft_ct<2, 3, DIR>(v);
+    else if constexpr (R == 8)
+        dft_ct<4, 2, DIR>(v);
+    else if constexpr (R == 9)
+        dft_ct<3, 3, DIR>(v);
+    else if constexpr (R == 10)
+        dft_ct<2, 5, DIR>(v);
+    else if constexpr (R == 12)
+        dft_ct<4, 3, DIR>(v);
+    else if constexpr (R == 15)
+        dft_ct<3, 5, DIR>(v);
+    else
+        dft_ct<4, 4, DIR>(v);  // 16
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass of radix R.
+
+template <int R, int DIR, int NT, int PT>
+__device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, int twstep, unsigned mag,
+                                               const double2 *__restrict__ tw, int tid, int nth) {
+    constexpr int B = (PT + R - 1) / R;  // butterflies per thread: B NT >= N / R since N <= NT PT
     const int nb = N / R;
-    const int twstep = N / (Ns * R);
     double2 v[B][R];
+    int widx[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = tid + b * nth;
         if (j < nb) {
-            const int k = j % Ns;
+            // j = g Ns + k; the multiply-high is exact for j, Ns < 2^16
+            const int g = Ns > 1 ? (int)__umulhi((unsigned)j, mag) : j;
+            const int k = j - g * Ns;
+            widx[b] = g * Ns * R + k;
+            const int tk = k * twstep;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 x = buf[j + r * nb];
-                if (r > 0) {
-                    double2 w = tw[r * k * twstep];
+                if (r > 0 && Ns > 1) {
+                    double2 w = tw[r * tk];
                     if (DIR > 0) w.y = -w.y;
                     x = cmul(x, w);
                 }
@@ -120,30 +253,32 @@ __device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, cons
     for (int b = 0; b < B; ++b) {
         const int j = tid + b * nth;
         if (j < nb) {
-            const int k = j % Ns;
-            const int idx = (j / Ns) * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[idx + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[widx[b] + r * Ns] = v[b][r];
         }
     }
     __syncthreads();
 }
 
-// In-place transform of buf[0 .. P.n) (LDS) by NT threads; requires
-// P.n <= SC_FFT_MAXN_PER_THREAD * NT.  Starts and ends with a barrier-complete buffer.
-template <int DIR, int NT>
+// In-place transform of buf[0 .. P.n) (LDS) by NT threads; requires P.n <= NT PT.
+// Starts and ends with a barrier-complete buffer.
+template <int DIR, int NT, int PT>
 __device__ void fft_lds(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
-    int Ns = 1;
     for (int s = 0; s < P.nst; ++s) {
-        const int R = P.r[s];
-        if (R == 4)
-            stockham_stage<4, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
-        else if (R == 2)
-            stockham_stage<2, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
-        else if (R == 3)
-            stockham_stage<3, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
-        else
-            stockham_stage<5, DIR, NT>(buf, P.n, Ns, tw, tid, nth);
-        Ns *= R;
+        const int R = P.r[s], Ns = P.ns[s], ts = P.tws[s];
+        const unsigned mg = P.mag[s];
+        switch (R) {
+            case 2: stockham_stage<2, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 3: stockham_stage<3, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 4: stockham_stage<4, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 5: stockham_stage<5, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 6: stockham_stage<6, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 8: stockham_stage<8, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 9: stockham_stage<9, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 10: stockham_stage<10, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 12: stockham_stage<12, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 15: stockham_stage<15, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            default: stockham_stage<16, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+        }
     }
 }

@@ -21,7 +21,7 @@
 
 namespace {
 
-template <int NT>
+template <int NT, int PT>
 __global__ void __launch_bounds__(NT)
 k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
@@ -35,29 +35,45 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
-    double2 *A = sbuf;          // forward transform, length n2
-    double2 *B = sbuf + n2;     // inverse transform, length nos
+    double2 *B = sbuf;  // length nos; the forward transform runs in B[0 .. n2)
 
     const double sg = ((m - k) & 1) ? -1.0 : 1.0;
     const double2 *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
         double2 f = col[j];
-        A[j] = f;
-        A[n2 - 1 - j] = cscale(f, sg);
+        B[j] = f;
+        B[n2 - 1 - j] = cscale(f, sg);
     }
-    for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    fft_lds<-1, NT>(A, P2, tw2, tid, nth);
+    fft_lds<-1, NT, PT>(B, P2, tw2, tid, nth);
 
+    // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from
+    // n + n2 to n + nos (sources and targets are disjoint since nos >= n2 + lmax),
+    // everything in between becomes zero.  nm < n2 <= nos / 2 <= NT PT / 2, so
+    // each thread holds at most ceil(PT / 2) coefficients.
+    constexpr int MAXC = (PT + 1) / 2;
     const double dm = dphi[m < 0 ? -m : m];
-    for (int t = tid; t < nm; t += nth) {
-        const int n = t - lmax;
-        double2 x = A[n < 0 ? n + n2 : n];
-        x = cscale(cmul(x, phase[t]), dm);
-        B[n < 0 ? n + nos : n] = x;
+    double2 xs[MAXC];
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * nth;
+        if (t < nm) {
+            const int n = t - lmax;
+            xs[i] = cscale(cmul(B[n < 0 ? n + n2 : n], phase[t]), dm);
+        }
     }
     __syncthreads();
-    fft_lds<1, NT>(B, Pos, twos, tid, nth);
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * nth;
+        if (t < nm) {
+            const int n = t - lmax;
+            B[n < 0 ? n + nos : n] = xs[i];
+        }
+    }
+    for (int t = lmax + 1 + tid; t < nos - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    fft_lds<1, NT, PT>(B, Pos, twos, tid, nth);
 
     const int r0 = -W / 2 + 1;
     for (int row = tid; row < rows; row += nth) {
@@ -67,7 +83,7 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int PT>
 __global__ void __launch_bounds__(NT)
 k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
                 int W, FftPlan Pp, const double2 *__restrict__ twp) {
@@ -88,7 +104,7 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
         A[m < 0 ? m + np : m] = src[t];
     }
     __syncthreads();
-    fft_lds<1, NT>(A, Pp, twp, tid, nth);
+    fft_lds<1, NT, PT>(A, Pp, twp, tid, nth);
 
     const int q0 = -W / 2 + 1;
     T *dst = maps + (size_t)row * cols * ncp;
@@ -121,7 +137,7 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
 //    (forward FFT of the rows placed at r mod n2os), X_adj(n) =
 //    conj(p(n)) D_phi(m) Y(n), f_adj = inverse FFT_{n2}(X_adj) and
 //    F_adj(j) = f_adj(j) + (-1)^{m-k} f_adj(n2 - 1 - j).
-template <typename T, int NT>
+template <typename T, int NT, int PT>
 __global__ void __launch_bounds__(NT)
 k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, int rows, int cols, int ncp, int W,
               FftPlan Pp, const double2 *__restrict__ twp) {
@@ -157,7 +173,7 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
         }
     }
     __syncthreads();
-    fft_lds<-1, NT>(A, Pp, twp, tid, nth);
+    fft_lds<-1, NT, PT>(A, Pp, twp, tid, nth);
     double2 *dst = G + ((size_t)k * rows + row) * nm;
     for (int t = tid; t < nm; t += nth) {
         const int m = t - lmax;
@@ -165,7 +181,7 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
     }
 }
 
-template <int NT>
+template <int NT, int PT>
 __global__ void __launch_bounds__(NT)
 k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax, int nring, int rows, int W,
                 FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2, const double2 *__restrict__ twos,
@@ -178,10 +194,8 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
-    double2 *A = sbuf;       // length n2
-    double2 *B = sbuf + n2;  // length nos
+    double2 *B = sbuf;  // length nos; the length-n2 transform runs in B[0 .. n2)
     for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
-    for (int t = tid; t < n2; t += nth) A[t] = make_double2(0.0, 0.0);
     __syncthreads();
     const int r0 = -W / 2 + 1;
     for (int row = tid; row < rows; row += nth) {
@@ -190,15 +204,33 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
         B[r] = G[((size_t)k * rows + row) * nm + mi];  // rows land on distinct indices
     }
     __syncthreads();
-    fft_lds<-1, NT>(B, Pos, twos, tid, nth);
+    fft_lds<-1, NT, PT>(B, Pos, twos, tid, nth);
+    // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from n + nos to
+    // n + n2 (disjoint since nos >= n2 + lmax); the rest of [0, n2) becomes zero.
+    constexpr int MAXC = (PT + 1) / 2;
     const double dm = dphi[m < 0 ? -m : m];
-    for (int t = tid; t < nm; t += nth) {
-        const int n = t - lmax;
-        const double2 y = B[n < 0 ? n + nos : n];
-        A[n < 0 ? n + n2 : n] = cscale(cmul(cconj(phase[t]), y), dm);
+    double2 xs[MAXC];
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * nth;
+        if (t < nm) {
+            const int n = t - lmax;
+            xs[i] = cscale(cmul(cconj(phase[t]), B[n < 0 ? n + nos : n]), dm);
+        }
     }
     __syncthreads();
-    fft_lds<1, NT>(A, P2, tw2, tid, nth);
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * nth;
+        if (t < nm) {
+            const int n = t - lmax;
+            B[n < 0 ? n + n2 : n] = xs[i];
+        }
+    }
+    for (int t = lmax + 1 + tid; t < n2 - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    fft_lds<1, NT, PT>(B, P2, tw2, tid, nth);
+    double2 *A = B;
     const double sg = ((m - k) & 1) ? -1.0 : 1.0;
     double2 *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
@@ -209,27 +241,29 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
 
 }  // namespace
 
-// 256 threads up to 4096-point transforms, 512 above (lmax ~ 1024).
-static inline bool fft_big(const sc_plan *p) {
-    return p->n2os > SC_FFT_MAXN_PER_THREAD * SC_FFT_NT || p->nphi > SC_FFT_MAXN_PER_THREAD * SC_FFT_NT;
+// Size class of a transform of length n: 0 = (256 threads, 9 points each),
+// 1 = (512, 9), 2 = (1024, 8); the longest supported transform is 8192 points.
+static inline int fft_class(int n) {
+    return n <= SC_FFT_NT * SC_FFT_PT ? 0 : n <= SC_FFT_NT_BIG * SC_FFT_PT ? 1 : 2;
 }
 
-template <int NT>
+template <int NT, int PT>
 static hipError_t theta_up(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
-    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipError_t e = sc_set_lds_attr((const void *)k_theta_upsample<NT>, lds);
+    const size_t lds = sizeof(double2) * (size_t)p->n2os;
+    auto kern = k_theta_upsample<NT, PT>;
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_upsample<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring,
-                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring, p->rows, p->W,
+                       p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
     return hipGetLastError();
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int PT>
 static hipError_t phi_syn(sc_plan *p) {
     const int nblk = (p->kmax + 1) * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    auto kern = k_phi_synthesis<T, NT>;
+    auto kern = k_phi_synthesis<T, NT, PT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
@@ -237,11 +271,11 @@ static hipError_t phi_syn(sc_plan *p) {
     return hipGetLastError();
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int PT>
 static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
     const int nblk = (p->kmax + 1) * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    auto kern = k_phi_adjoint<T, NT>;
+    auto kern = k_phi_adjoint<T, NT, PT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const T *)gmaps, p->G, p->lmax,
@@ -249,32 +283,56 @@ static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
     return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int PT>
 static hipError_t theta_adj(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
-    const size_t lds = sizeof(double2) * (size_t)(p->n2 + p->n2os);
-    hipError_t e = sc_set_lds_attr((const void *)k_theta_adjoint<NT>, lds);
+    const size_t lds = sizeof(double2) * (size_t)p->n2os;
+    auto kern = k_theta_adjoint<NT, PT>;
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_adjoint<NT>, dim3(nblk), dim3(NT), lds, p->stream, p->G, p->F, p->lmax, p->nring,
-                       p->rows, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, p->F, p->lmax, p->nring, p->rows, p->W,
+                       p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
     return hipGetLastError();
 }
 
 hipError_t sc_launch_theta_upsample(sc_plan *p) {
-    return fft_big(p) ? theta_up<SC_FFT_NT_BIG>(p) : theta_up<SC_FFT_NT>(p);
+    switch (fft_class(p->n2os)) {
+        case 0: return theta_up<SC_FFT_NT, SC_FFT_PT>(p);
+        case 1: return theta_up<SC_FFT_NT_BIG, SC_FFT_PT>(p);
+        default: return theta_up<SC_FFT_NT_HUGE, SC_FFT_PT_HUGE>(p);
+    }
+}
+
+template <typename T>
+static hipError_t phi_syn_any(sc_plan *p) {
+    switch (fft_class(p->nphi)) {
+        case 0: return phi_syn<T, SC_FFT_NT, SC_FFT_PT>(p);
+        case 1: return phi_syn<T, SC_FFT_NT_BIG, SC_FFT_PT>(p);
+        default: return phi_syn<T, SC_FFT_NT_HUGE, SC_FFT_PT_HUGE>(p);
+    }
 }
 
 hipError_t sc_launch_phi_synthesis(sc_plan *p) {
-    if (p->prec == SC_FP64) return fft_big(p) ? phi_syn<double, SC_FFT_NT_BIG>(p) : phi_syn<double, SC_FFT_NT>(p);
-    return fft_big(p) ? phi_syn<float, SC_FFT_NT_BIG>(p) : phi_syn<float, SC_FFT_NT>(p);
+    return p->prec == SC_FP64 ? phi_syn_any<double>(p) : phi_syn_any<float>(p);
+}
+
+template <typename T>
+static hipError_t phi_adj_any(sc_plan *p, const void *gmaps) {
+    switch (fft_class(p->nphi)) {
+        case 0: return phi_adj<T, SC_FFT_NT, SC_FFT_PT>(p, gmaps);
+        case 1: return phi_adj<T, SC_FFT_NT_BIG, SC_FFT_PT>(p, gmaps);
+        default: return phi_adj<T, SC_FFT_NT_HUGE, SC_FFT_PT_HUGE>(p, gmaps);
+    }
 }
 
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {
-    if (p->prec == SC_FP64)
-        return fft_big(p) ? phi_adj<double, SC_FFT_NT_BIG>(p, gmaps) : phi_adj<double, SC_FFT_NT>(p, gmaps);
-    return fft_big(p) ? phi_adj<float, SC_FFT_NT_BIG>(p, gmaps) : phi_adj<float, SC_FFT_NT>(p, gmaps);
+    return p->prec == SC_FP64 ? phi_adj_any<double>(p, gmaps) : phi_adj_any<float>(p, gmaps);
 }
 
 hipError_t sc_launch_theta_adjoint(sc_plan *p) {
-    return fft_big(p) ? theta_adj<SC_FFT_NT_BIG>(p) : theta_adj<SC_FFT_NT>(p);
+    switch (fft_class(p->n2os)) {
+        case 0: return theta_adj<SC_FFT_NT, SC_FFT_PT>(p);
+        case 1: return theta_adj<SC_FFT_NT_BIG, SC_FFT_PT>(p);
+        default: return theta_adj<SC_FFT_NT_HUGE, SC_FFT_PT_HUGE>(p);
+    }
 }

@@ -272,61 +272,71 @@ hipError_t launch_binned_t(sc_plan *p, void *tod) {
 
 
 // ---------------------------------------------------------------------------
-// Binned gather on the matrix cores (FP32 maps).  Same work items, LDS staging
-// and weights as k_gather_binned; the per-chunk product
-//     X[s][c] = sum_{t < 64} w_s(t) P[t][c]     (64 samples x 16 CT comps x 64 taps)
-// runs as v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation): wave w
-// owns samples 16w .. 16w+15 and all CT component tiles.  Operand layout of
+// Binned gather on the matrix cores (FP32 maps).  Same work items and weights as
+// k_gather_binned; per chunk of up to 128 samples the product
+//     Y[c][s] = sum_{t < 64} P[t][c] w_s(t)     (16 CT comps x 128 samples x 64 taps)
+// runs as v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation) with the
+// map block P as the A operand and the tap weights w_s(t) = w_theta w_phi as B
+// (formed on the fly from the two 8-tap factors); wave w owns samples
+// 32w .. 32w+31 (two 16-sample tiles) and all component tiles.  Operand layout of
 // the 16x16x4 instruction: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
-// D[i][j] in lane j + 16(i/4), register i%4.
-// Lane (r = lane%16, grp = lane/16) therefore holds components c = 16 ct + r of
-// samples 16w + 4 grp + v (v < 4): its orders are k = 8 ct + (r+1)/2, so the
-// k-sum needs e^{i k0 psi} (k0 = (r+1)/2 <= 8, from a per-sample table) and one
-// FP64 rotation by e^{i 8 psi} per component tile.
-// LDS bytes of one work item with CT component tiles.
+// D[i][j] in lane j + 16(i/4), register i%4.  Lane (r = lane%16, grp = lane/16)
+// therefore holds components c = 16 ct + 4 grp + v (v < 4) of ONE sample
+// (32w + 16h + r): its orders are k0 = 8 ct + 2 grp (sin), k0 + 1 (cos, sin)
+// and k0 + 2 (cos), reached from e^{i 2 grp psi} by FP64 rotations with
+// e^{i psi} and e^{i 8 psi}; the sum over the lane's components is completed
+// across the four lanes of the sample.
+// Map rows in LDS are padded to a stride of NC + 16 floats when the tile count
+// is even, and the weight rows to 144 floats, so the four lane groups of an
+// operand read fall in distinct bank quarters.
+constexpr int GCH = 128;       // samples per chunk
+constexpr int GW1 = GCH + 16;  // weight row stride (floats)
+
 __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
-    return sizeof(float) * (64 * 16 * (size_t)CT + 64 * 64 + 64 * 16) +
-           64 * (sizeof(double2) + sizeof(double) + sizeof(int));
+    return sizeof(float) * (64 * (16 * (size_t)CT + 16) + 16 * GW1) + GCH * (sizeof(double) + sizeof(int));
 }
 
-// One work item: stage the anchor's map block, then contract its samples 64 at a
+// One work item: stage the anchor's map block, then contract its samples GCH at a
 // time.  CTMAX register tiles are reserved; the item uses its detector's ct <= CTMAX
 // (a wave-uniform bound, so the batch kernel serves detectors of any kmax with one
 // instantiation and work proportional to their own component count).
 template <int CTMAX>
 __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 item, double *smem_d, int ct_n) {
-    const int NC = 16 * ct_n;
-    float *Psh = (float *)smem_d;         // [64 taps][NC]
-    float *Wsh = Psh + 64 * NC;           // [64 taps][64 samples]; Z0 table after the product
-    double2 *Z0 = (double2 *)Wsh;         // [64 samples][9]: e^{i k psi}, k = 0..8
-    float *W1 = Wsh + 64 * 64;            // [16][64 samples]
-    double2 *E8 = (double2 *)(W1 + 64 * 16);  // [64] e^{i 8 psi}
-    double *Psi = (double *)(E8 + 64);        // [64]
-    int *Idx = (int *)(Psi + 64);             // [64]
+    const int NC = 16 * ct_n;                     // == D.ncp for the FP32 forms
+    const int NCS = NC + ((ct_n & 1) ? 0 : 16);   // LDS row stride
+    float *Psh = (float *)smem_d;                 // [64 taps][NCS]
+    float *W1 = Psh + 64 * NCS;                   // [16][GW1]: theta (0..7) and phi (8..15) factors
+    double *Psi = (double *)(W1 + 16 * GW1);      // [GCH]
+    int *Idx = (int *)(Psi + GCH);                // [GCH]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
     const int row0 = item.x / D.nkc, col0 = item.x - (item.x / D.nkc) * D.nkc;
-    for (int e = tid; e < 64 * NC; e += 256) {
-        const int t = e / NC, c = e - t * NC;
-        float v = 0.f;
-        if (c < D.ncp) v = D.maps[((size_t)(row0 + (t >> 3)) * D.cols + (col0 + (t & 7))) * D.ncp + c];
-        Psh[e] = v;
+    {
+        // tap t = 8 i + j is map row row0 + i, column col0 + j: NC contiguous floats
+        const float4 *src = (const float4 *)(D.maps + ((size_t)row0 * D.cols + col0) * NC);
+        const size_t rstride = (size_t)D.cols * NC / 4;
+        const int n4 = NC / 4;
+        for (int t = wv; t < 64; t += 4) {
+            const float4 *s4 = src + (t >> 3) * rstride + (t & 7) * n4;
+            float4 *d4 = (float4 *)(Psh + t * NCS);
+            for (int q = lane; q < n4; q += 64) d4[q] = s4[q];
+        }
     }
-    for (int ch = 0; ch < item.z; ch += 64) {
-        const int ns = item.z - ch < 64 ? item.z - ch : 64;
+    for (int ch = 0; ch < item.z; ch += GCH) {
+        const int ns = item.z - ch < GCH ? item.z - ch : GCH;
         const int pos0 = item.y + ch;
-        for (int e = tid; e < 64 * 16; e += 256) {
-            const int q = e >> 6, sl = e & 63;
+        for (int e = tid; e < 16 * GCH; e += 256) {
+            const int q = e / GCH, sl = e - q * GCH;
             float w = 0.f;
             if (sl < ns) {
                 const float f = (q < 8) ? (float)D.srt.fu[pos0 + sl] : (float)D.srt.fv[pos0 + sl];
                 w = es_weight<float>((f + (float)(3 - (q & 7))) * 0.25f, D.beta);
             }
-            W1[e] = w;
+            W1[q * GW1 + sl] = w;
         }
-        if (tid < 64) {
+        if (tid < GCH) {
             double ps = 0.0;
             int ix = -1;
             if (tid < ns) {
@@ -337,68 +347,65 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             Idx[tid] = ix;
         }
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int t = e >> 6, sl = e & 63;
-            Wsh[e] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
-        }
-        __syncthreads();
 
-        floatx4 acc[CTMAX];
+        floatx4 acc[2][CTMAX];
 #pragma unroll
-        for (int ct = 0; ct < CTMAX; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const float *wa = Wsh + grp * 64 + 16 * wv + r;  // A[i = r][k = grp] of sample tile wv
-        const float *pb = Psh + grp * NC + r;            // B[k = grp][j = r] of component tile 0
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int ct = 0; ct < CTMAX; ++ct) acc[h][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int s0 = 32 * wv + r;
+        const float *pa = Psh + grp * NCS + r;  // A[i = comp r][k = tap grp] of component tile 0
 #pragma unroll 2
         for (int ks = 0; ks < 16; ++ks) {
-            const float a = wa[ks * 4 * 64];
+            const int tap = 4 * ks + grp;
+            const float *wt = W1 + (tap >> 3) * GW1, *wp = W1 + (8 + (tap & 7)) * GW1;
+            const float b0 = wt[s0] * wp[s0];
+            const float b1 = wt[s0 + 16] * wp[s0 + 16];
 #pragma unroll
-            for (int ct = 0; ct < CTMAX; ++ct)
-                if (ct < ct_n)
-                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, pb[ks * 4 * NC + 16 * ct], acc[ct], 0, 0, 0);
-        }
-        __syncthreads();  // Wsh is dead: per-sample e^{i k psi} table in its place
-        if (tid < 64) {
-            double sn, cs;
-            sincos(Psi[tid], &sn, &cs);
-            const double2 e1 = make_double2(cs, sn);
-            double2 z = make_double2(1.0, 0.0);
-#pragma unroll
-            for (int k = 0; k <= 8; ++k) {
-                Z0[tid * 9 + k] = z;
-                if (k < 8) z = cmul(z, e1);
+            for (int ct = 0; ct < CTMAX; ++ct) {
+                if (ct < ct_n) {
+                    const float a = pa[ks * 4 * NCS + 16 * ct];
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][ct], 0, 0, 0);
+                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][ct], 0, 0, 0);
+                }
             }
-            E8[tid] = z;
         }
-        __syncthreads();
 
-        const int k0 = (r + 1) >> 1;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int sl = 16 * wv + 4 * grp + v;
-            double2 z = Z0[sl * 9 + k0];
-            const double2 e8 = E8[sl];
+        for (int h = 0; h < 2; ++h) {
+            const int sl = s0 + 16 * h;
+            double sn, cs;
+            sincos(Psi[sl], &sn, &cs);
+            const double2 e1 = make_double2(cs, sn);
+            const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
+            const double2 e8 = cmul(e4, e4);
+            double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
             float part = 0.f;
 #pragma unroll
             for (int ct = 0; ct < CTMAX; ++ct) {
                 if (ct < ct_n) {
-                    const int c = 16 * ct + r;
-                    const float x = acc[ct][v];
-                    if (c < D.ncomp) part = fmaf(c == 0 ? 1.f : (float)((c & 1) ? z.x : z.y), x, part);
-                    if (ct + 1 < ct_n) z = cmul(z, e8);
+                    const int c0 = 16 * ct + 4 * grp;
+                    const double2 z1 = cmul(z, e1);
+                    const double z2x = z1.x * e1.x - z1.y * e1.y;
+                    const floatx4 x = acc[h][ct];
+                    const float b0 = c0 == 0 ? 1.f : (float)z.y;
+                    if (c0 < D.ncomp) part = fmaf(b0, x[0], part);
+                    if (c0 + 1 < D.ncomp) part = fmaf((float)z1.x, x[1], part);
+                    if (c0 + 2 < D.ncomp) part = fmaf((float)z1.y, x[2], part);
+                    if (c0 + 3 < D.ncomp) part = fmaf((float)z2x, x[3], part);
+                    z = cmul(z, e8);
                 }
             }
-            part += __shfl_xor(part, 8);
-            part += __shfl_xor(part, 4);
-            part += __shfl_xor(part, 2);
-            part += __shfl_xor(part, 1);
-            if (r == 0 && sl < ns) D.tod[Idx[sl]] = part;
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (grp == 0 && sl < ns) D.tod[Idx[sl]] = part;
         }
-        __syncthreads();
+        __syncthreads();  // W1, Psi, Idx are rewritten by the next chunk
     }
 }
 
 template <int CT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
     extern __shared__ double smem_d[];
     __shared__ int item_sh;
@@ -408,7 +415,7 @@ k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
         __syncthreads();
         const int it = item_sh;
         if (it >= nitems) break;
-        gather_mfma_item<CT>(D, D.items[it], smem_d, CT);
+        gather_mfma_item<CT>(D, D.items[it], smem_d, (D.ncomp + 15) / 16);
     }
 }
 
@@ -416,7 +423,7 @@ k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
 // of every detector (detector d's items follow detector d-1's); each item uses
 // its detector's component-tile count (<= CTMAX).
 template <int CTMAX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ cursor) {
     extern __shared__ double smem_d[];
     __shared__ int start[SC_MAX_DET + 1];
@@ -459,7 +466,6 @@ int persistent_grid(const void *kern, size_t lds, int wgs_per_cu) {
 
 template <int CT>
 hipError_t launch_mfma(sc_plan *p, void *tod) {
-    static_assert(64 * 64 * sizeof(float) >= 64 * 9 * sizeof(double2), "Z0 table must fit the weight area");
     const size_t lds = mfma_lds_bytes(CT);
     auto kern = k_gather_mfma<CT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);

@@ -25,33 +25,67 @@
 // scaled value passes 2^600 it is rescaled and e incremented.  Once e = 0 the
 // true values are bounded by 1 and no further rescaling happens.
 //
+// The kernel runs the recursion on u^l = d^l / S_l with S_{l0} = S_{l0+1} = 1 and
+// S_{l+1} = gamma_l S_{l-1}, which turns it into
+//   u^{l+1} = (a_l cos(theta) - b_l) u^l - u^{l-1},  a_l = alpha_l S_l / S_{l+1},
+//   b_l = beta_l S_l / S_{l+1},
+// and folds S_l into the contraction weights: per d value one FMA forms
+// a_l cos(theta) - b_l, one FMA advances u and four FMAs contract it (both signs
+// of m, real and imaginary parts).  S_l is O(1) (gamma_l -> 1; the alternating
+// products of gamma telescope to about sqrt(l0 / l)), so u stays as well
+// conditioned as d.  While some ring of the wave still has e < 0 every step
+// also applies 2^{1200 e} and every 8 steps the rescaling is checked; once all
+// of the wave's rings have e = 0 (|d| <= 1, |u| = O(1) from then on) the loop
+// runs without either.
+//
 // Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
 // rings.  Recursion coefficients and weights for 64 consecutive l are built
-// cooperatively in LDS (one l per lane) and read as broadcasts.
+// cooperatively in LDS (one l per lane; S_l by a product scan over the lanes of
+// each parity) and read as broadcasts.
 #include "wigner_rec.h"
 
 namespace {
 
 using namespace wrec;
 
-// One recursion step for every ring of the lane: contract d^l (its true value
-// d * 2^{1200 e}; below 2^-600 while e < 0, i.e. nothing) and advance to d^{l+1}.
+// One step for every ring of the lane while some ring may be below range:
+// contract u^l (true value u S_l 2^{1200 e}, S_l folded into the weights) and
+// advance to u^{l+1}.
 template <int RPT>
-__device__ __forceinline__ void rec_step(int t, const double *cA, const double *cB, const double *cC,
-                                         const double2 *cWp, const double2 *cWm, const double *x, double *d,
-                                         double *dp, const int *e, double2 *fp, double2 *fm) {
-    const double A = cA[t], B = cB[t], C = cC[t];
+__device__ __forceinline__ void rec_step_scaled(int t, const double *cA, const double *cB, const double2 *cWp,
+                                                const double2 *cWm, const double *x, double *u, double *up,
+                                                const int *e, double2 *fp, double2 *fm) {
+    const double a = cA[t], b = cB[t];
     const double2 wp = cWp[t], wm = cWm[t];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const double dd = ldexp(d[r], REC_STEP * e[r]);
+        const double dd = ldexp(u[r], REC_STEP * e[r]);
         fp[r].x = fma(wp.x, dd, fp[r].x);
         fp[r].y = fma(wp.y, dd, fp[r].y);
         fm[r].x = fma(wm.x, dd, fm[r].x);
         fm[r].y = fma(wm.y, dd, fm[r].y);
-        const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
-        dp[r] = d[r];
-        d[r] = dn;
+        const double un = fma(fma(a, x[r], -b), u[r], -up[r]);
+        up[r] = u[r];
+        u[r] = un;
+    }
+}
+
+// The same step once every ring of the wave has e = 0.
+template <int RPT>
+__device__ __forceinline__ void rec_step(int t, const double *cA, const double *cB, const double2 *cWp,
+                                         const double2 *cWm, const double *x, double *u, double *up, double2 *fp,
+                                         double2 *fm) {
+    const double a = cA[t], b = cB[t];
+    const double2 wp = cWp[t], wm = cWm[t];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        fp[r].x = fma(wp.x, u[r], fp[r].x);
+        fp[r].y = fma(wp.y, u[r], fp[r].y);
+        fm[r].x = fma(wm.x, u[r], fm[r].x);
+        fm[r].y = fma(wm.y, u[r], fm[r].y);
+        const double un = fma(fma(a, x[r], -b), u[r], -up[r]);
+        up[r] = u[r];
+        u[r] = un;
     }
 }
 
@@ -60,7 +94,7 @@ __global__ void __launch_bounds__(64)
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
-    __shared__ double cA[64], cB[64], cC[64];
+    __shared__ double cA[64], cB[64];
     __shared__ double2 cWp[64], cWm[64];
 
     int b = blockIdx.x;
@@ -73,64 +107,95 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     const int mn = m < k ? m : k;
     const int nm = 2 * lmax + 1;
 
-    double x[RPT], d[RPT], dp[RPT];
+    double x[RPT], u[RPT], up[RPT];
     int e[RPT];
     double2 fp[RPT], fm[RPT];
 
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+    bool scaled = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int j = (g * RPT + r) * 64 + lane;
         fp[r] = make_double2(0.0, 0.0);
         fm[r] = make_double2(0.0, 0.0);
-        dp[r] = 0.0;
+        up[r] = 0.0;
         if (j < nring) {
-            start_value(j, nring, m, k, pref, x[r], d[r], e[r]);
+            start_value(j, nring, m, k, pref, x[r], u[r], e[r]);
         } else {
             x[r] = 0.0;
-            d[r] = 0.0;
+            u[r] = 0.0;
             e[r] = 0;
         }
+        scaled |= e[r] != 0;
     }
+    bool fast = !__any(scaled);
 
     const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
     const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
+    double s_prev = 1.0, s_cur = 1.0;  // S_{lc-1}, S_{lc} (S_{l0-1} := 1 only seeds the scan)
     for (int lc = l0; lc <= lmax; lc += 64) {
         const int l = lc + lane;
-        __syncthreads();
+        double A = 1.0, B = 0.0, C = 1.0;
+        double2 wp = make_double2(0.0, 0.0), wm = make_double2(0.0, 0.0);
         if (l <= lmax) {
-            double A, B, C;
             rec_coefs(l, mm, kk, mk, A, B, C);
             double2 a = alm[aoff + l];
             double2 bb = blm[boff + l];
             if (m == 0) a.y = 0.0;
             if (k == 0) bb.y = 0.0;
-            const double2 wp = cmul(a, cconj(bb));
+            wp = cmul(a, cconj(bb));
             const double s = ((l + k + m) & 1) ? -1.0 : 1.0;
-            const double2 wm = cscale(cmul(cconj(a), cconj(bb)), s);
-            cA[lane] = A;
-            cB[lane] = B;
-            cC[lane] = C;
-            cWp[lane] = wp;
-            cWm[lane] = wm;
+            wm = cscale(cmul(cconj(a), cconj(bb)), s);
         }
+        if (l == l0) C = 1.0;  // S_{l0+1} := 1 (gamma_{l0} = 0)
+        // T = S_{l+1} = gamma_l S_{l-1}: inclusive product over the lanes of this
+        // lane's parity, times the carried S_{lc-1} (even lanes) or S_{lc} (odd).
+        double T = C;
+#pragma unroll
+        for (int off = 2; off < 64; off <<= 1) {
+            const double v = __shfl_up(T, off);
+            if (lane >= off) T *= v;
+        }
+        T *= (lane & 1) ? s_cur : s_prev;
+        double Sl = __shfl_up(T, 1);  // S_l
+        if (lane == 0) Sl = s_cur;
+        s_prev = __shfl(T, 62);  // S_{lc+63} and S_{lc+64} for the next chunk
+        s_cur = __shfl(T, 63);
+        const double ratio = Sl / T;
+        __syncthreads();  // previous chunk's coefficients are consumed
+        cA[lane] = A * ratio;
+        cB[lane] = B * ratio;
+        cWp[lane] = cscale(wp, Sl);
+        cWm[lane] = cscale(wm, Sl);
         __syncthreads();
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
-        // Rescaling is checked once per 8 steps: one step grows |d| by at most
-        // ~2^10 (alpha_l <= l0 + 1), far inside the 2^424 left below overflow.
+        if (fast) {
+#pragma unroll 2
+            for (int t = 0; t < nl; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            continue;
+        }
+        // Rescaling is checked once per 8 steps: one step grows |u| by at most
+        // ~2^11, far inside the 2^424 left below overflow.
         for (int t0 = 0; t0 < nl; t0 += 8) {
             const int t1 = t0 + 8 < nl ? t0 + 8 : nl;
+            if (fast) {
+                for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
+                continue;
+            }
 #pragma unroll 2
-            for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cC, cWp, cWm, x, d, dp, e, fp, fm);
+            for (int t = t0; t < t1; ++t) rec_step_scaled<RPT>(t, cA, cB, cWp, cWm, x, u, up, e, fp, fm);
+            bool low = false;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                if (fabs(d[r]) > REC_BIG) {
-                    d[r] *= REC_DOWN;
-                    dp[r] *= REC_DOWN;
+                if (fabs(u[r]) > REC_BIG) {
+                    u[r] = rec_down(u[r]);
+                    up[r] = rec_down(up[r]);
                     e[r] += 1;
                 }
+                low |= e[r] != 0;
             }
+            fast = !__any(low);
         }
     }
 

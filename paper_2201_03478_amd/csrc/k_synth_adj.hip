@@ -110,8 +110,8 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 if (fabs(d[r]) > REC_BIG) {
-                    d[r] *= REC_DOWN;
-                    dp[r] *= REC_DOWN;
+                    d[r] = rec_down(d[r]);
+                    dp[r] = rec_down(dp[r]);
                     e[r] += 1;
                 }
             }
@@ -172,12 +172,19 @@ __global__ void k_reduce_over_k(const double2 *__restrict__ GA, double2 *__restr
 
 }  // namespace
 
-// Waves per (k, m) workgroup and rings per lane for the adjoint.
+// LDS bytes of an adjoint workgroup with nw waves.
+static size_t adj_lds_bytes(int nw) {
+    return sizeof(double) * (3 * 64 + (size_t)nw * 64 * 4 + (size_t)nw * 4 * ADJ_FLUSH * ADJ_ROW);
+}
+
+// Waves per (k, m) workgroup and rings per lane for the adjoint: the fewest idle
+// ring slots among layouts whose LDS fits one CU (at most 8 waves; 4 rings per
+// lane then cover nring <= 2048, i.e. transforms up to 8192 points).
 static void adj_layout(int nring, int *rpt, int *nw) {
     int best_r = 4, best_w = (nring + 255) / 256, best_waste = 1 << 30;
     for (int r = 4; r >= 1; --r) {
         const int waves = (nring + 64 * r - 1) / (64 * r);
-        if (waves > 16) continue;
+        if (adj_lds_bytes(waves) > 160 * 1024) continue;
         const int waste = waves * 64 * r - nring;
         if (waste < best_waste) {
             best_waste = waste;
@@ -202,7 +209,7 @@ hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *gr
     int rpt, nw;
     adj_layout(p->nring, &rpt, &nw);
     const int nblk = (p->lmax + 1) * (p->kmax + 1);
-    const size_t lds = sizeof(double) * (3 * 64 + (size_t)nw * 64 * 4 + (size_t)nw * 4 * ADJ_FLUSH * ADJ_ROW);
+    const size_t lds = adj_lds_bytes(nw);
     hipError_t e = hipSuccess;
     switch (rpt) {
         SC_ADJ_CASE(1)

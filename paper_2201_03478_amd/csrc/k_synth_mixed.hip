@@ -32,8 +32,7 @@ namespace {
 using namespace wrec;
 
 constexpr int MX_STEP = 128;          // FP32 rescaling exponent step
-constexpr float MX_BIG = 0x1p64f;
-constexpr float MX_DOWN = 0x1p-128f;
+constexpr float MX_BIG = 0x1p64f;  // rescaling divides by 2^128 through the exponent (ldexpf)
 
 template <int RPT>
 __global__ void __launch_bounds__(64)
@@ -131,8 +130,8 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 if (fabsf(d[r]) > MX_BIG) {
-                    d[r] *= MX_DOWN;
-                    dp[r] *= MX_DOWN;
+                    d[r] = ldexpf(d[r], -MX_STEP);
+                    dp[r] = ldexpf(dp[r], -MX_STEP);
                     e[r] += 1;
                 }
             }

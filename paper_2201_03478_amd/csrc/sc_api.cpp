@@ -55,15 +55,55 @@ int next_smooth(int n, bool even) {
     return n;
 }
 
+// Fewest passes of radix <= 16 (2^x 3^y 5^z) for 2^a 3^b 5^c, by exhaustive
+// search over the (small) exponent space; ties keep the first (largest) radix.
+static int radix_passes(int a, int b, int c, int *out) {
+    if (a == 0 && b == 0 && c == 0) return 0;
+    int best = 1 << 20, tmp[SC_MAX_RADICES];
+    for (int x = a; x >= 0; --x)
+        for (int y = b; y >= 0; --y)
+            for (int z = c; z >= 0; --z) {
+                int R = 1;
+                for (int i = 0; i < x; ++i) R *= 2;
+                for (int i = 0; i < y; ++i) R *= 3;
+                for (int i = 0; i < z; ++i) R *= 5;
+                if (R == 1 || R > 16 || R == 7 || R == 14) continue;
+                const int np = 1 + radix_passes(a - x, b - y, c - z, tmp + 1);
+                if (np < best && np <= SC_MAX_RADICES) {
+                    best = np;
+                    tmp[0] = R;
+                    for (int i = 0; i < np; ++i) out[i] = tmp[i];
+                }
+            }
+    return best;
+}
+
 bool factor_fft(int n, FftPlan *P) {
     P->n = n;
     P->nst = 0;
-    int m = n;
-    while (m % 4 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 4; m /= 4; }
-    while (m % 2 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 2; m /= 2; }
-    while (m % 3 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 3; m /= 3; }
-    while (m % 5 == 0 && P->nst < SC_MAX_RADICES) { P->r[P->nst++] = 5; m /= 5; }
-    return m == 1 && n <= 16 * 512;  // longest transform the LDS kernels handle
+    if (n < 2 || n > 16 * 512) return false;  // longest transform the LDS kernels handle
+    int m = n, a = 0, b = 0, c = 0;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    while (m % 5 == 0) { m /= 5; ++c; }
+    if (m != 1) return false;
+    int rad[SC_MAX_RADICES];
+    const int np = radix_passes(a, b, c, rad);
+    // Odd radices first: their strided writes (span 1, R1, ...) do not collide in
+    // LDS banks, and by the time the even radices run the span is large, where a
+    // pass reads and writes contiguous runs.
+    for (int i = 0; i < np; ++i)
+        if (rad[i] & 1) P->r[P->nst++] = rad[i];
+    for (int i = 0; i < np; ++i)
+        if (!(rad[i] & 1)) P->r[P->nst++] = rad[i];
+    int ns = 1;
+    for (int s = 0; s < P->nst; ++s) {
+        P->ns[s] = ns;
+        P->tws[s] = n / (ns * P->r[s]);
+        P->mag[s] = ns > 1 ? (unsigned)((0x100000000ull + (unsigned long long)ns - 1) / (unsigned long long)ns) : 0u;
+        ns *= P->r[s];
+    }
+    return true;
 }
 
 // Record the start event of a timed launch; returns the slot or -1.
@@ -269,7 +309,9 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->rows = p->n2os / 2 + W;
     p->cols = p->nphi + W - 1;
     p->ncomp = 2 * kmax + 1;
-    p->ncp = (p->ncomp + 3) & ~3;
+    // FP32 maps: components padded to the 16-wide tiles of the matrix-core gather,
+    // so an 8 x 8 block of the map is 8 contiguous runs; FP64 maps: to 4.
+    p->ncp = precision == SC_FP64 ? (p->ncomp + 3) & ~3 : (p->ncomp + 15) & ~15;
     p->nq = 128;
     p->alm_lmax = lmax;
     p->bin_chunk = BIN_CHUNK;

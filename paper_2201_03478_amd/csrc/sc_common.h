@@ -13,13 +13,19 @@
 
 #include "../../include/sidelobe.h"
 
-#define SC_MAX_RADICES 24
+#define SC_MAX_RADICES 16
 
-// Radix schedule of one mixed-radix (2, 3, 4, 5) Stockham transform.
+// Radix schedule of one mixed-radix (2, 3, 4, 5) Stockham transform.  Stage s
+// has radix r[s], span ns[s] = r[0] ... r[s-1] and twiddle stride
+// tws[s] = n / (ns[s] r[s]); mag[s] = ceil(2^32 / ns[s]) turns j / ns[s] into a
+// multiply-high (exact for j, ns < 2^16; unused when ns[s] = 1).
 struct FftPlan {
     int n;
     int nst;
     int r[SC_MAX_RADICES];
+    int ns[SC_MAX_RADICES];
+    int tws[SC_MAX_RADICES];
+    unsigned mag[SC_MAX_RADICES];
 };
 
 // Default samples per work item of the binned gather, and samples per binning pass.

@@ -31,7 +31,9 @@ __device__ XN xn_pow(double x, int n) {
 
 constexpr int REC_STEP = 1200;  // rescaling exponent step
 constexpr double REC_BIG = 0x1p600;
-constexpr double REC_DOWN = 0x1p-1200;
+// 2^-1200 is below the FP64 range, so rescaling divides by 2^1200 through the
+// exponent (ldexp), never through a multiplication by a constant.
+__device__ __forceinline__ double rec_down(double v) { return ldexp(v, -REC_STEP); }
 
 
 // Start value d^{l0}_{mk}(theta_j), l0 = max(m, k), theta_j = (j + 1/2) pi / nring,

@@ -37,6 +37,31 @@ def _rel(x, ref):
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-4)])
+def test_ring_sums_start_below_range_then_emerge(env, oracle_lib, prec, tol):
+    """lmax 1300: at rings near 22 and 158 degrees the start values of m ~ 430-460
+    lie below 2^-600 (e < 0) and the columns grow to ~1e-5 by lmax, so every
+    rescaling step is exercised; checked per (k, m) column against the oracle,
+    relative to the largest ring sum on the ring."""
+    torch, api, dev = env
+    L, K = 1300, 2
+    a = W.sky_alm(L, 6800)
+    b = W.beam_alm(L, K, 6801)
+    plan = api.Plan(L, K, prec)
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    F = plan.debug_stage(0)
+    nr = plan.info()["n_rings"]
+    js = np.array([nr // 8, nr // 2, 7 * nr // 8])
+    th = (js + 0.5) * math.pi / nr
+    Fs = F[:, :, torch.as_tensor(js, device=dev)].cpu().numpy()
+    ref = np.transpose(oracle_lib.ring_sums(a, b, L, K, th), (0, 2, 1))
+    for q in range(len(js)):
+        scale = np.max(np.abs(ref[:, :, q]))
+        err = np.max(np.abs(Fs[:, :, q] - ref[:, :, q])) / scale
+        print("%s ring %d/%d: max error / ring max %.3e" % (prec, js[q], nr, err))
+        assert err <= tol, js[q]
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 1e-4)])
 def test_ring_sums_lmax1024_near_poles(env, oracle_lib, prec, tol):
     torch, api, dev = env
