@@ -79,7 +79,10 @@ def tune_plan(plan, alm, blm, ptg, reps: int = 3, use_cache: bool = True) -> dic
         best = {}
         times = {}
         for r in RING_RPT[plan.precision]:
-            plan.set_param("ring_rpt", r)
+            try:
+                plan.set_param("ring_rpt", r)
+            except N.ScError:
+                continue  # layout not available for this ring count
             times[r] = _time(lambda: plan.set_sky_beam(alm, blm), reps)
         best["ring_rpt"] = min(times, key=times.get)
         plan.set_param("ring_rpt", best["ring_rpt"])

@@ -33,10 +33,13 @@
 // a_l cos(theta) - b_l, one FMA advances u and four FMAs contract it (both signs
 // of m, real and imaginary parts).  S_l is O(1) (gamma_l -> 1; the alternating
 // products of gamma telescope to about sqrt(l0 / l)), so u stays as well
-// conditioned as d.  While some ring of the wave still has e < 0 every step
-// also applies 2^{1200 e} and every 8 steps the rescaling is checked; once all
-// of the wave's rings have e = 0 (|d| <= 1, |u| = O(1) from then on) the loop
-// runs without either.
+// conditioned as d.  Every ring accumulates its scaled u unconditionally: while
+// e < 0 the sums are meaningless, so they are cleared at the check where e
+// reaches 0 (what the ring added before that is below 2^-600 of its true size,
+// i.e. nothing), and a ring that ends with e < 0 writes zero.  The check runs
+// every 8 steps while some ring of the wave has e < 0; once all have e = 0
+// (|d| <= 1, |u| = O(1) from then on) the loop runs without it.  Both loops
+// cost the same six FMAs per d value.
 //
 // Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
 // rings.  Recursion coefficients and weights for 64 consecutive l are built
@@ -48,29 +51,8 @@ namespace {
 
 using namespace wrec;
 
-// One step for every ring of the lane while some ring may be below range:
-// contract u^l (true value u S_l 2^{1200 e}, S_l folded into the weights) and
-// advance to u^{l+1}.
-template <int RPT>
-__device__ __forceinline__ void rec_step_scaled(int t, const double *cA, const double *cB, const double2 *cWp,
-                                                const double2 *cWm, const double *x, double *u, double *up,
-                                                const int *e, double2 *fp, double2 *fm) {
-    const double a = cA[t], b = cB[t];
-    const double2 wp = cWp[t], wm = cWm[t];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const double dd = ldexp(u[r], REC_STEP * e[r]);
-        fp[r].x = fma(wp.x, dd, fp[r].x);
-        fp[r].y = fma(wp.y, dd, fp[r].y);
-        fm[r].x = fma(wm.x, dd, fm[r].x);
-        fm[r].y = fma(wm.y, dd, fm[r].y);
-        const double un = fma(fma(a, x[r], -b), u[r], -up[r]);
-        up[r] = u[r];
-        u[r] = un;
-    }
-}
-
-// The same step once every ring of the wave has e = 0.
+// One recursion step for every ring of the lane: contract u^l (true value
+// u S_l 2^{1200 e}, S_l folded into the weights) and advance to u^{l+1}.
 template <int RPT>
 __device__ __forceinline__ void rec_step(int t, const double *cA, const double *cB, const double2 *cWp,
                                          const double2 *cWm, const double *x, double *u, double *up, double2 *fp,
@@ -179,12 +161,9 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         // ~2^11, far inside the 2^424 left below overflow.
         for (int t0 = 0; t0 < nl; t0 += 8) {
             const int t1 = t0 + 8 < nl ? t0 + 8 : nl;
-            if (fast) {
-                for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
-                continue;
-            }
 #pragma unroll 2
-            for (int t = t0; t < t1; ++t) rec_step_scaled<RPT>(t, cA, cB, cWp, cWm, x, u, up, e, fp, fm);
+            for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            if (fast) continue;
             bool low = false;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -192,6 +171,10 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
                     u[r] = rec_down(u[r]);
                     up[r] = rec_down(up[r]);
                     e[r] += 1;
+                    if (e[r] == 0) {  // in range from here on: drop the sums of the scaled values
+                        fp[r] = make_double2(0.0, 0.0);
+                        fm[r] = make_double2(0.0, 0.0);
+                    }
                 }
                 low |= e[r] != 0;
             }
@@ -202,6 +185,10 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int j = (g * RPT + r) * 64 + lane;
+        if (e[r] != 0) {  // never in range: the true sums are below 2^-600
+            fp[r] = make_double2(0.0, 0.0);
+            fm[r] = make_double2(0.0, 0.0);
+        }
         if (j < nring) {
             F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
             if (m > 0) F[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)] = fm[r];
