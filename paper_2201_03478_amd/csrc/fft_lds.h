@@ -282,3 +282,77 @@ __device__ void fft_lds(double2 *buf, const FftPlan &P, const double2 *__restric
         }
     }
 }
+
+// ---------------------------------------------------------------------------
+// Transforms whose length and radix sequence are compile-time constants: the
+// same Stockham passes with every span, stride and twiddle step folded, one code
+// path per pass (no runtime radix switch), so a kernel holds only its own passes.
+// FftSpec<N, R0, R1, ...> lists the radices in pass order; FftGeneric selects the
+// runtime-planned fft_lds.
+
+template <int N, int... Rs>
+struct FftSpec {};
+struct FftGeneric {};
+
+template <int R, int DIR, int NT, int N, int NS>
+__device__ __forceinline__ void stockham_stage_c(double2 *buf, const double2 *__restrict__ tw, int tid) {
+    constexpr int nb = N / R;
+    constexpr int B = (nb + NT - 1) / NT;
+    constexpr int TWS = N / (NS * R);
+    double2 v[B][R];
+    int widx[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = tid + b * NT;
+        if ((b + 1) * NT <= nb || j < nb) {
+            const int g = j / NS, k = j - g * NS;
+            widx[b] = g * NS * R + k;
+            const int tk = k * TWS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = buf[j + r * nb];
+                if (NS > 1 && r > 0) {
+                    double2 w = tw[r * tk];
+                    if (DIR > 0) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[b][r] = x;
+            }
+            dft_small<R, DIR>(v[b]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = tid + b * NT;
+        if ((b + 1) * NT <= nb || j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[widx[b] + r * NS] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int NT, int N, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_passes_c(double2 *buf, const double2 *__restrict__ tw, int tid) {
+    stockham_stage_c<R, DIR, NT, N, NS>(buf, tw, tid);
+    if constexpr (sizeof...(Rest) > 0) fft_passes_c<DIR, NT, N, NS * R, Rest...>(buf, tw, tid);
+}
+
+template <int DIR, int NT, int PT, typename S>
+struct FftRun;
+
+template <int DIR, int NT, int PT>
+struct FftRun<DIR, NT, PT, FftGeneric> {
+    __device__ static void run(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
+        fft_lds<DIR, NT, PT>(buf, P, tw, tid, nth);
+    }
+};
+
+template <int DIR, int NT, int PT, int N, int... Rs>
+struct FftRun<DIR, NT, PT, FftSpec<N, Rs...>> {
+    static_assert(N <= NT * PT, "size class too small for the transform");
+    __device__ static void run(double2 *buf, const FftPlan &, const double2 *__restrict__ tw, int tid, int) {
+        fft_passes_c<DIR, NT, N, 1, Rs...>(buf, tw, tid);
+    }
+};

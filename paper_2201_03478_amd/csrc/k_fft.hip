@@ -21,8 +21,8 @@
 
 namespace {
 
-template <int NT, int PT>
-__global__ void __launch_bounds__(NT)
+template <int NT, int PT, typename S2, typename SOS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
                  const double2 *__restrict__ twos, const double2 *__restrict__ phase,
@@ -45,7 +45,7 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
         B[n2 - 1 - j] = cscale(f, sg);
     }
     __syncthreads();
-    fft_lds<-1, NT, PT>(B, P2, tw2, tid, nth);
+    FftRun<-1, NT, PT, S2>::run(B, P2, tw2, tid, nth);
 
     // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from
     // n + n2 to n + nos (sources and targets are disjoint since nos >= n2 + lmax),
@@ -73,7 +73,7 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
     for (int t = lmax + 1 + tid; t < nos - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    fft_lds<1, NT, PT>(B, Pos, twos, tid, nth);
+    FftRun<1, NT, PT, SOS>::run(B, Pos, twos, tid, nth);
 
     const int r0 = -W / 2 + 1;
     for (int row = tid; row < rows; row += nth) {
@@ -83,8 +83,8 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
 }
 
-template <typename T, int NT, int PT>
-__global__ void __launch_bounds__(NT)
+template <typename T, int NT, int PT, typename SP>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
                 int W, FftPlan Pp, const double2 *__restrict__ twp) {
     extern __shared__ double2 sbuf[];
@@ -104,7 +104,7 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
         A[m < 0 ? m + np : m] = src[t];
     }
     __syncthreads();
-    fft_lds<1, NT, PT>(A, Pp, twp, tid, nth);
+    FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
 
     const int q0 = -W / 2 + 1;
     T *dst = maps + (size_t)row * cols * ncp;
@@ -247,11 +247,11 @@ static inline int fft_class(int n) {
     return n <= SC_FFT_NT * SC_FFT_PT ? 0 : n <= SC_FFT_NT_BIG * SC_FFT_PT ? 1 : 2;
 }
 
-template <int NT, int PT>
+template <int NT, int PT, typename S2 = FftGeneric, typename SOS = FftGeneric>
 static hipError_t theta_up(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
     const size_t lds = sizeof(double2) * (size_t)p->n2os;
-    auto kern = k_theta_upsample<NT, PT>;
+    auto kern = k_theta_upsample<NT, PT, S2, SOS>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring, p->rows, p->W,
@@ -259,11 +259,11 @@ static hipError_t theta_up(sc_plan *p) {
     return hipGetLastError();
 }
 
-template <typename T, int NT, int PT>
+template <typename T, int NT, int PT, typename SP = FftGeneric>
 static hipError_t phi_syn(sc_plan *p) {
     const int nblk = (p->kmax + 1) * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    auto kern = k_phi_synthesis<T, NT, PT>;
+    auto kern = k_phi_synthesis<T, NT, PT, SP>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
@@ -295,7 +295,17 @@ static hipError_t theta_adj(sc_plan *p) {
     return hipGetLastError();
 }
 
+// Compile-time plans for the transform lengths of lmax 256, 512 and 1024 (radices
+// chosen so each pass keeps most lanes of its waves busy, an odd radix first).
+using F540 = FftSpec<540, 9, 5, 12>;
+using F1080 = FftSpec<1080, 9, 12, 10>;
+using F2160 = FftSpec<2160, 15, 12, 12>;
+using F4320 = FftSpec<4320, 9, 5, 6, 16>;
+
 hipError_t sc_launch_theta_upsample(sc_plan *p) {
+    if (p->n2 == 540 && p->n2os == 1080) return theta_up<128, 9, F540, F1080>(p);
+    if (p->n2 == 1080 && p->n2os == 2160) return theta_up<SC_FFT_NT, SC_FFT_PT, F1080, F2160>(p);
+    if (p->n2 == 2160 && p->n2os == 4320) return theta_up<SC_FFT_NT_BIG, SC_FFT_PT, F2160, F4320>(p);
     switch (fft_class(p->n2os)) {
         case 0: return theta_up<SC_FFT_NT, SC_FFT_PT>(p);
         case 1: return theta_up<SC_FFT_NT_BIG, SC_FFT_PT>(p);
@@ -305,6 +315,9 @@ hipError_t sc_launch_theta_upsample(sc_plan *p) {
 
 template <typename T>
 static hipError_t phi_syn_any(sc_plan *p) {
+    if (p->nphi == 1080) return phi_syn<T, 128, 9, F1080>(p);
+    if (p->nphi == 2160) return phi_syn<T, SC_FFT_NT, SC_FFT_PT, F2160>(p);
+    if (p->nphi == 4320) return phi_syn<T, SC_FFT_NT_BIG, SC_FFT_PT, F4320>(p);
     switch (fft_class(p->nphi)) {
         case 0: return phi_syn<T, SC_FFT_NT, SC_FFT_PT>(p);
         case 1: return phi_syn<T, SC_FFT_NT_BIG, SC_FFT_PT>(p);

@@ -4,7 +4,8 @@ The band limits below give theta, upsampled-theta and phi transform lengths
 whose radix plans together use every pass radix (2, 3, 4, 5, 6, 8, 9, 10, 12,
 15, 16), in the forward (theta analysis) and inverse (upsampling, phi
 synthesis) directions, and lmax 1800 needs 7290- and 7500-point transforms
-(the 1024-thread class).  The FP64 form (W = 14) reaches the convolution of
+(the 1024-thread class); lmax 256, 512 and 1024 run the compile-time plans of
+540/1080, 1080/2160 and 2160/4320 points.  The FP64 form (W = 14) reaches the convolution of
 Eq. 2 (Galloway et al. 2022, Sec. 2.1) to ~1e-13, so any wrong twiddle, index
 or pass order shows as an O(1) error against the oracle.  The adjoint at the
 largest lengths is checked by the dot-product test against its own forward.
@@ -31,7 +32,7 @@ def _to(torch, dev, x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
 
 
-@pytest.mark.parametrize("L", [6, 10, 13, 15, 24, 32, 40, 64, 100, 1800])
+@pytest.mark.parametrize("L", [6, 10, 13, 15, 24, 32, 40, 64, 100, 256, 512, 1024, 1800])
 def test_fp64_form_across_transform_lengths(env, oracle_lib, L):
     torch, api, dev = env
     K = min(2, L)
