@@ -313,6 +313,23 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
     const int row0 = item.x / D.nkc, col0 = item.x - (item.x / D.nkc) * D.nkc;
+    // Sample records of the next chunk are loaded into registers one chunk
+    // ahead (thread t stages the weights of sample t % GCH; threads < GCH also
+    // carry psi and the output index), so their latency overlaps the products.
+    const int sw = tid & (GCH - 1);
+    double pf_u = 0.0, pf_v = 0.0, pf_psi = 0.0;
+    int pf_idx = -1;
+    {
+        const int ns0 = item.z < GCH ? item.z : GCH;
+        if (sw < ns0) {
+            pf_u = D.srt.fu[item.y + sw];
+            pf_v = D.srt.fv[item.y + sw];
+        }
+        if (tid < ns0) {
+            pf_psi = D.srt.psi[item.y + tid];
+            pf_idx = D.srt.idx[item.y + tid];
+        }
+    }
     {
         // tap t = 8 i + j is map row row0 + i, column col0 + j: NC contiguous floats
         const float4 *src = (const float4 *)(D.maps + ((size_t)row0 * D.cols + col0) * NC);
@@ -326,27 +343,33 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
     }
     for (int ch = 0; ch < item.z; ch += GCH) {
         const int ns = item.z - ch < GCH ? item.z - ch : GCH;
-        const int pos0 = item.y + ch;
-        for (int e = tid; e < 16 * GCH; e += 256) {
-            const int q = e / GCH, sl = e - q * GCH;
-            float w = 0.f;
-            if (sl < ns) {
-                const float f = (q < 8) ? (float)D.srt.fu[pos0 + sl] : (float)D.srt.fv[pos0 + sl];
-                w = es_weight<float>((f + (float)(3 - (q & 7))) * 0.25f, D.beta);
+        {
+            const float fu = (float)pf_u, fv = (float)pf_v;
+#pragma unroll
+            for (int i = 0; i < 16 * GCH / 256; ++i) {
+                const int q = (tid >> 7) + 2 * i;  // 256 threads cover 2 weight rows per step
+                float w = 0.f;
+                if (sw < ns) w = es_weight<float>(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, D.beta);
+                W1[q * GW1 + sw] = w;
             }
-            W1[q * GW1 + sl] = w;
         }
         if (tid < GCH) {
-            double ps = 0.0;
-            int ix = -1;
-            if (tid < ns) {
-                ps = D.srt.psi[pos0 + tid];
-                ix = D.srt.idx[pos0 + tid];
-            }
-            Psi[tid] = ps;
-            Idx[tid] = ix;
+            Psi[tid] = tid < ns ? pf_psi : 0.0;
+            Idx[tid] = tid < ns ? pf_idx : -1;
         }
         __syncthreads();
+        {
+            const int nxt = ch + GCH;
+            const int nns = item.z - nxt < GCH ? item.z - nxt : GCH;  // <= 0 past the last chunk
+            if (sw < nns) {
+                pf_u = D.srt.fu[item.y + nxt + sw];
+                pf_v = D.srt.fv[item.y + nxt + sw];
+            }
+            if (tid < nns) {
+                pf_psi = D.srt.psi[item.y + nxt + tid];
+                pf_idx = D.srt.idx[item.y + nxt + tid];
+            }
+        }
 
         floatx4 acc[2][CTMAX];
 #pragma unroll
@@ -410,12 +433,16 @@ k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
     extern __shared__ double smem_d[];
     __shared__ int item_sh;
     const int nitems = D.totals[1];
-    for (;;) {
-        if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    __syncthreads();
+    int it = item_sh;
+    while (it < nitems) {
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
+        gather_mfma_item<CT>(D, D.items[it], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
+        if (threadIdx.x == 0) item_sh = nxt;
         __syncthreads();
-        const int it = item_sh;
-        if (it >= nitems) break;
-        gather_mfma_item<CT>(D, D.items[it], smem_d, (D.ncomp + 15) / 16);
+        it = item_sh;
     }
 }
 
@@ -438,15 +465,19 @@ k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ c
     }
     __syncthreads();
     const int total = start[ndet];
-    for (;;) {
-        if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
-        __syncthreads();
-        const int it = item_sh;
-        if (it >= total) break;
+    if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    __syncthreads();
+    int it = item_sh;
+    while (it < total) {
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
         int d = 0;
         while (d + 1 < ndet && it >= start[d + 1]) ++d;
         const GatherDet D = dets[d];
-        gather_mfma_item<CTMAX>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);
+        gather_mfma_item<CTMAX>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
+        if (threadIdx.x == 0) item_sh = nxt;
+        __syncthreads();
+        it = item_sh;
     }
 }
 
