@@ -186,12 +186,15 @@ int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage
  *   SC_PARAM_RING_RPT           rings per lane of the ring-sum kernel, 1..4 (1..8 for SC_MIXED)
  *   SC_PARAM_SKY_LMAX           band limit of the layout of the alm array given to
  *                               sc_set_sky_beam (>= lmax; a shared sky may have a larger one)
+ *   SC_PARAM_GATHER_WAVES       waves per matrix-core gather workgroup, 4 or 8 (default 4);
+ *                               the same 128-sample chunk split over more waves
  */
 enum sc_param {
     SC_PARAM_BIN_CHUNK = 1,
     SC_PARAM_GATHER_WGS_PER_CU = 2,
     SC_PARAM_RING_RPT = 3,
-    SC_PARAM_SKY_LMAX = 4
+    SC_PARAM_SKY_LMAX = 4,
+    SC_PARAM_GATHER_WAVES = 5
 };
 int sc_plan_set_param(sc_plan *plan, int param, int64_t value);
 int sc_plan_get_param(const sc_plan *plan, int param, int64_t *value);

@@ -4,7 +4,8 @@ For one (lmax, kmax, precision) it times, with HIP events on the current
 stream, the candidates of
   * ring_rpt           rings per lane of the ring-sum kernel (ring-sum stage time),
   * bin_chunk          samples per gather work item, and
-  * gather_wgs_per_cu  persistent gather workgroups per CU (binning + gather time),
+  * gather_wgs_per_cu  persistent gather workgroups per CU and
+  * gather_waves       waves per gather workgroup (binning + gather time),
 keeps the fastest, and caches the choice in a JSON file keyed by
 "arch|L<lmax>|K<kmax>|P<precision>" ($SC_AUTOTUNE_CACHE, default
 ~/.cache/paper_2201_03478_amd/autotune.json).  Only launch shapes change: every
@@ -22,6 +23,7 @@ from . import _native as N
 RING_RPT = {N.SC_FP64: (1, 2, 3, 4), N.SC_F64MAPS_F32GATHER: (1, 2, 3, 4), N.SC_MIXED: (1, 2, 3, 4, 6, 8)}
 BIN_CHUNK = (128, 256, 512, 1024)
 WGS_PER_CU = (0, 1)
+GATHER_WAVES = (4, 8)
 
 
 def cache_path() -> str:
@@ -91,10 +93,12 @@ def tune_plan(plan, alm, blm, ptg, reps: int = 3, use_cache: bool = True) -> dic
         times = {}
         for c in BIN_CHUNK:
             for w in WGS_PER_CU:
-                plan.set_param("bin_chunk", c)
-                plan.set_param("gather_wgs_per_cu", w)
-                times[(c, w)] = _time(lambda: plan.interpolate(ptg, out=out), reps)
-        best["bin_chunk"], best["gather_wgs_per_cu"] = min(times, key=times.get)
+                for nw in GATHER_WAVES:
+                    plan.set_param("bin_chunk", c)
+                    plan.set_param("gather_wgs_per_cu", w)
+                    plan.set_param("gather_waves", nw)
+                    times[(c, w, nw)] = _time(lambda: plan.interpolate(ptg, out=out), reps)
+        best["bin_chunk"], best["gather_wgs_per_cu"], best["gather_waves"] = min(times, key=times.get)
         if use_cache:
             cache = load_cache()
             cache[key] = best
@@ -112,11 +116,15 @@ def tune_batch(batch, alm_sky, reps: int = 2, use_cache: bool = True) -> list:
         if key not in chosen:
             p = batch.plan(i)
             chosen[key] = tune_plan(p, alm_sky, d["blm"], d["ptg"], reps=reps, use_cache=use_cache)
-    wgs = {}
+    wgs, waves = {}, {}
     for i, d in enumerate(batch.dets):
         best = chosen[(d["lmax"], d["kmax"])]
         batch.set_param("ring_rpt", best["ring_rpt"], det=i)
         batch.set_param("bin_chunk", best["bin_chunk"], det=i)
-        wgs[best["gather_wgs_per_cu"]] = wgs.get(best["gather_wgs_per_cu"], 0) + d["ptg"].shape[0]
-    batch.set_param("gather_wgs_per_cu", max(wgs, key=wgs.get))  # the choice covering most samples
+        n = d["ptg"].shape[0]
+        wgs[best["gather_wgs_per_cu"]] = wgs.get(best["gather_wgs_per_cu"], 0) + n
+        waves[best["gather_waves"]] = waves.get(best["gather_waves"], 0) + n
+    # one gather launch serves all detectors: the choices covering most samples
+    batch.set_param("gather_wgs_per_cu", max(wgs, key=wgs.get))
+    batch.set_param("gather_waves", max(waves, key=waves.get))
     return [chosen[(d["lmax"], d["kmax"])] for d in batch.dets]

@@ -277,12 +277,13 @@ hipError_t launch_binned_t(sc_plan *p, void *tod) {
 //     Y[c][s] = sum_{t < 64} P[t][c] w_s(t)     (16 CT comps x 128 samples x 64 taps)
 // runs as v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation) with the
 // map block P as the A operand and the tap weights w_s(t) = w_theta w_phi as B
-// (formed on the fly from the two 8-tap factors); wave w owns samples
-// 32w .. 32w+31 (two 16-sample tiles) and all component tiles.  Operand layout of
+// (formed on the fly from the two 8-tap factors); a workgroup of NWV = 4 or 8
+// waves takes 128 samples, wave w owning 8/NWV 16-sample tiles and all component
+// tiles (8 waves hold half the accumulators each and double the waves per CU).  Operand layout of
 // the 16x16x4 instruction: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16(i/4), register i%4.  Lane (r = lane%16, grp = lane/16)
 // therefore holds components c = 16 ct + 4 grp + v (v < 4) of ONE sample
-// (32w + 16h + r): its orders are k0 = 8 ct + 2 grp (sin), k0 + 1 (cos, sin)
+// (16 (TPW w + h) + r): its orders are k0 = 8 ct + 2 grp (sin), k0 + 1 (cos, sin)
 // and k0 + 2 (cos), reached from e^{i 2 grp psi} by FP64 rotations with
 // e^{i psi} and e^{i 8 psi}; the sum over the lane's components is completed
 // across the four lanes of the sample.
@@ -297,13 +298,15 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
 }
 
 // One work item: stage the anchor's map block, then contract its samples GCH at a
-// time.  CTMAX register tiles are reserved; the item uses its detector's ct <= CTMAX
-// (a wave-uniform bound, so the batch kernel serves detectors of any kmax with one
-// instantiation and work proportional to their own component count).
-template <int CTMAX>
-__device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 item, double *smem_d, int ct_n) {
-    const int NC = 16 * ct_n;                     // == D.ncp for the FP32 forms
-    const int NCS = NC + ((ct_n & 1) ? 0 : 16);   // LDS row stride
+// time.  CT is the item's exact component-tile count (a compile-time constant,
+// so the product loop has no per-tile branches and its LDS loads run ahead of
+// the matrix instructions).
+template <int CT, int NWV>
+__device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 item, double *smem_d) {
+    constexpr int NT = 64 * NWV;    // threads
+    constexpr int TPW = 8 / NWV;    // 16-sample tiles per wave
+    constexpr int NC = 16 * CT;                   // == D.ncp for the FP32 forms
+    constexpr int NCS = NC + ((CT & 1) ? 0 : 16); // LDS row stride
     float *Psh = (float *)smem_d;                 // [64 taps][NCS]
     float *W1 = Psh + 64 * NCS;                   // [16][GW1]: theta (0..7) and phi (8..15) factors
     double *Psi = (double *)(W1 + 16 * GW1);      // [GCH]
@@ -335,7 +338,7 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
         const float4 *src = (const float4 *)(D.maps + ((size_t)row0 * D.cols + col0) * NC);
         const size_t rstride = (size_t)D.cols * NC / 4;
         const int n4 = NC / 4;
-        for (int t = wv; t < 64; t += 4) {
+        for (int t = wv; t < 64; t += NWV) {
             const float4 *s4 = src + (t >> 3) * rstride + (t & 7) * n4;
             float4 *d4 = (float4 *)(Psh + t * NCS);
             for (int q = lane; q < n4; q += 64) d4[q] = s4[q];
@@ -346,8 +349,8 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
         {
             const float fu = (float)pf_u, fv = (float)pf_v;
 #pragma unroll
-            for (int i = 0; i < 16 * GCH / 256; ++i) {
-                const int q = (tid >> 7) + 2 * i;  // 256 threads cover 2 weight rows per step
+            for (int i = 0; i < 16 * GCH / NT; ++i) {
+                const int q = (tid >> 7) + (NT / GCH) * i;  // NT threads cover NT / GCH weight rows per step
                 float w = 0.f;
                 if (sw < ns) w = es_weight<float>(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, D.beta);
                 W1[q * GW1 + sw] = w;
@@ -371,31 +374,57 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             }
         }
 
-        floatx4 acc[2][CTMAX];
+        floatx4 acc[TPW][CT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < TPW; ++h)
 #pragma unroll
-            for (int ct = 0; ct < CTMAX; ++ct) acc[h][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const int s0 = 32 * wv + r;
+            for (int ct = 0; ct < CT; ++ct) acc[h][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int s0 = 16 * TPW * wv + r;
         const float *pa = Psh + grp * NCS + r;  // A[i = comp r][k = tap grp] of component tile 0
+        // Software pipeline: the operands of tap group ks + 1 (map values and the
+        // two weight factors) are read from LDS before the matrix instructions of
+        // group ks are issued, and multiplied only after them.
+        float a[CT], ft[TPW], fp[TPW];
+        {
+            const float *wt = W1 + (grp >> 3) * GW1, *wp = W1 + (8 + (grp & 7)) * GW1;
+#pragma unroll
+            for (int h = 0; h < TPW; ++h) {
+                ft[h] = wt[s0 + 16 * h];
+                fp[h] = wp[s0 + 16 * h];
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) a[ct] = pa[16 * ct];
+        }
 #pragma unroll 2
         for (int ks = 0; ks < 16; ++ks) {
-            const int tap = 4 * ks + grp;
-            const float *wt = W1 + (tap >> 3) * GW1, *wp = W1 + (8 + (tap & 7)) * GW1;
-            const float b0 = wt[s0] * wp[s0];
-            const float b1 = wt[s0 + 16] * wp[s0 + 16];
+            float bw[TPW];
 #pragma unroll
-            for (int ct = 0; ct < CTMAX; ++ct) {
-                if (ct < ct_n) {
-                    const float a = pa[ks * 4 * NCS + 16 * ct];
-                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[0][ct], 0, 0, 0);
-                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[1][ct], 0, 0, 0);
+            for (int h = 0; h < TPW; ++h) bw[h] = ft[h] * fp[h];
+            float an[CT];
+            const int ksn = ks + 1 < 16 ? ks + 1 : ks;  // last group: harmless re-read
+            {
+                const int tap = 4 * ksn + grp;
+                const float *wt = W1 + (tap >> 3) * GW1, *wp = W1 + (8 + (tap & 7)) * GW1;
+#pragma unroll
+                for (int h = 0; h < TPW; ++h) {
+                    ft[h] = wt[s0 + 16 * h];
+                    fp[h] = wp[s0 + 16 * h];
                 }
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) an[ct] = pa[ksn * 4 * NCS + 16 * ct];
             }
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ct], bw[h], acc[h][ct], 0, 0, 0);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) a[ct] = an[ct];
         }
 
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < TPW; ++h) {
             const int sl = s0 + 16 * h;
             double sn, cs;
             sincos(Psi[sl], &sn, &cs);
@@ -405,8 +434,8 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
             float part = 0.f;
 #pragma unroll
-            for (int ct = 0; ct < CTMAX; ++ct) {
-                if (ct < ct_n) {
+            for (int ct = 0; ct < CT; ++ct) {
+                {
                     const int c0 = 16 * ct + 4 * grp;
                     const double2 z1 = cmul(z, e1);
                     const double z2x = z1.x * e1.x - z1.y * e1.y;
@@ -427,8 +456,8 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
     }
 }
 
-template <int CT>
-__global__ void __launch_bounds__(256, 2)
+template <int CT, int NWV>
+__global__ void __launch_bounds__(64 * NWV, NWV / 2)
 k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
     extern __shared__ double smem_d[];
     __shared__ int item_sh;
@@ -439,18 +468,28 @@ k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
     while (it < nitems) {
         int nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
-        gather_mfma_item<CT>(D, D.items[it], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
+        gather_mfma_item<CT, NWV>(D, D.items[it], smem_d);  // ends with a barrier
         if (threadIdx.x == 0) item_sh = nxt;
         __syncthreads();
         it = item_sh;
     }
 }
 
+// Item routine for a runtime tile count ct in [1, CTMAX]: one instantiation per count.
+template <int CT, int CTMAX, int NWV>
+__device__ __forceinline__ void gather_item_ct(const GatherDet &D, const int4 item, double *smem_d, int ct) {
+    if (ct == CT || CT == CTMAX) {
+        gather_mfma_item<CT, NWV>(D, item, smem_d);
+        return;
+    }
+    if constexpr (CT < CTMAX) gather_item_ct<CT + 1, CTMAX, NWV>(D, item, smem_d, ct);
+}
+
 // All detectors of a batch in one persistent launch: one queue over the items
-// of every detector (detector d's items follow detector d-1's); each item uses
-// its detector's component-tile count (<= CTMAX).
-template <int CTMAX>
-__global__ void __launch_bounds__(256, 2)
+// of every detector (detector d's items follow detector d-1's); each item runs
+// with its detector's component-tile count (<= CTMAX).
+template <int CTMAX, int NWV>
+__global__ void __launch_bounds__(64 * NWV, NWV / 2)
 k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ cursor) {
     extern __shared__ double smem_d[];
     __shared__ int start[SC_MAX_DET + 1];
@@ -474,7 +513,7 @@ k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ c
         int d = 0;
         while (d + 1 < ndet && it >= start[d + 1]) ++d;
         const GatherDet D = dets[d];
-        gather_mfma_item<CTMAX>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
+        gather_item_ct<1, CTMAX, NWV>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
         if (threadIdx.x == 0) item_sh = nxt;
         __syncthreads();
         it = item_sh;
@@ -491,31 +530,31 @@ int ct_class(int ncomp) {
     return 16;
 }
 
-int persistent_grid(const void *kern, size_t lds, int wgs_per_cu) {
-    return sc_persistent_grid(kern, 256, lds, wgs_per_cu);
-}
-
-template <int CT>
+template <int CT, int NWV>
 hipError_t launch_mfma(sc_plan *p, void *tod) {
     const size_t lds = mfma_lds_bytes(CT);
-    auto kern = k_gather_mfma<CT>;
+    auto kern = k_gather_mfma<CT, NWV>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    const int grid = persistent_grid((const void *)kern, lds, p->gather_wgs_per_cu);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, sc_gather_det(p, tod), p->bw.totals + 2);
+    const int grid = sc_persistent_grid((const void *)kern, 64 * NWV, lds, p->gather_wgs_per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWV), lds, p->stream, sc_gather_det(p, tod), p->bw.totals + 2);
     return hipGetLastError();
 }
 
+template <int CT, int NWV>
+hipError_t launch_mfma_ct(sc_plan *p, void *tod, int ct) {
+    if (ct == CT || CT == 16) return launch_mfma<CT, NWV>(p, tod);
+    if constexpr (CT < 16) return launch_mfma_ct<CT + 1, NWV>(p, tod, ct);
+    return hipErrorInvalidValue;
+}
+
+template <int NWV>
+hipError_t launch_mfma_w(sc_plan *p, void *tod) {
+    return launch_mfma_ct<1, NWV>(p, tod, (p->ncomp + 15) / 16);  // exact tile count, 1 .. 16
+}
+
 hipError_t launch_mfma_any(sc_plan *p, void *tod) {
-    switch (ct_class(p->ncomp)) {
-        case 1: return launch_mfma<1>(p, tod);
-        case 2: return launch_mfma<2>(p, tod);
-        case 3: return launch_mfma<3>(p, tod);
-        case 5: return launch_mfma<5>(p, tod);
-        case 9: return launch_mfma<9>(p, tod);
-        case 13: return launch_mfma<13>(p, tod);
-        default: return launch_mfma<16>(p, tod);
-    }
+    return p->gather_waves == 8 ? launch_mfma_w<8>(p, tod) : launch_mfma_w<4>(p, tod);
 }
 }  // namespace
 
@@ -546,25 +585,32 @@ GatherDet sc_gather_det(const sc_plan *p, void *tod) {
     return D;
 }
 
-template <int CTMAX>
+template <int CTMAX, int NWV>
 static hipError_t gather_batch(const GatherDet *dets_dev, int ndet, int *cursor, int wgs_per_cu, hipStream_t stream) {
     const size_t lds = mfma_lds_bytes(CTMAX);
-    auto kern = k_gather_batch<CTMAX>;
+    auto kern = k_gather_batch<CTMAX, NWV>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    const int grid = persistent_grid((const void *)kern, lds, wgs_per_cu);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, stream, dets_dev, ndet, cursor);
+    const int grid = sc_persistent_grid((const void *)kern, 64 * NWV, lds, wgs_per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWV), lds, stream, dets_dev, ndet, cursor);
     return hipGetLastError();
 }
 
+template <int NWV>
+static hipError_t gather_batch_w(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
+                                 hipStream_t stream) {
+    if (max_ct <= 2) return gather_batch<2, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 5) return gather_batch<5, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 13) return gather_batch<13, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    return gather_batch<16, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+}
+
 // One persistent launch over the binned items of several FP32 plans; max_ct is
-// the largest component-tile count among them.
+// the largest component-tile count among them, waves the workgroup shape (4 or 8).
 hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
-                                  hipStream_t stream) {
-    if (max_ct <= 2) return gather_batch<2>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    if (max_ct <= 5) return gather_batch<5>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    if (max_ct <= 13) return gather_batch<13>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    return gather_batch<16>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+                                  int waves, hipStream_t stream) {
+    return waves == 8 ? gather_batch_w<8>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream)
+                      : gather_batch_w<4>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream);
 }
 
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod) {

@@ -316,6 +316,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->alm_lmax = lmax;
     p->bin_chunk = BIN_CHUNK;
     p->gather_wgs_per_cu = 0;
+    p->gather_waves = 4;
     {
         const char *g = std::getenv("SC_GATHER_PATH");
         p->gather_direct = (g && std::strcmp(g, "direct") == 0) ? 1 : 0;
@@ -549,6 +550,10 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
             if (v < 0 || v > 16) return fail(SC_EINVAL, "workgroups per CU %lld outside [0, 16]", (long long)v);
             p->gather_wgs_per_cu = (int)v;
             return SC_OK;
+        case SC_PARAM_GATHER_WAVES:
+            if (v != 4 && v != 8) return fail(SC_EINVAL, "gather waves %lld is not 4 or 8", (long long)v);
+            p->gather_waves = (int)v;
+            return SC_OK;
         case SC_PARAM_RING_RPT: {
             const int vmax = p->prec == SC_MIXED ? 8 : 4;
             if (v < 1 || v > vmax) return fail(SC_EINVAL, "rings per lane %lld outside [1, %d]", (long long)v, vmax);
@@ -576,6 +581,7 @@ int sc_plan_get_param(const sc_plan *p, int param, int64_t *v) {
     switch (param) {
         case SC_PARAM_BIN_CHUNK: *v = p->bin_chunk; return SC_OK;
         case SC_PARAM_GATHER_WGS_PER_CU: *v = p->gather_wgs_per_cu; return SC_OK;
+        case SC_PARAM_GATHER_WAVES: *v = p->gather_waves; return SC_OK;
         case SC_PARAM_RING_RPT: *v = p->prec == SC_MIXED ? p->rpt_mx : p->rpt; return SC_OK;
         case SC_PARAM_SKY_LMAX: *v = p->alm_lmax; return SC_OK;
         default: return fail(SC_EINVAL, "unknown parameter %d", param);
@@ -648,6 +654,7 @@ struct sc_batch {
     int *cursor;
     int max_ct;
     int wgs_per_cu;
+    int waves;  // gather workgroup shape
     int warmed;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -679,7 +686,7 @@ hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s) {
             e = D.n > 0 ? sc_launch_binning(p, D.ptg, D.n) : sc_launch_zero(p->bw.totals, 4 * sizeof(int), s);
     }
     if (e == hipSuccess) e = sc_launch_zero(b->cursor, sizeof(int), s);
-    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, s);
+    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, b->waves, s);
     for (sc_plan *p : b->plans) p->stream = b->stream;
     return e;
 }
@@ -722,6 +729,7 @@ int sc_batch_create(sc_batch **out, const sc_det_desc *dets, int ndet, int lmax_
     b->ndet = ndet;
     b->lmax_sky = lmax_sky;
     b->prec = precision;
+    b->waves = 4;
     b->stream = (hipStream_t)stream;
     b->dets.assign(dets, dets + ndet);
     std::vector<GatherDet> gd(ndet);
@@ -767,6 +775,12 @@ int sc_batch_set_param(sc_batch *b, int det, int param, int64_t value) {
         batch_drop_graph(b);
         return SC_OK;
     }
+    if (param == SC_PARAM_GATHER_WAVES) {
+        if (value != 4 && value != 8) return fail(SC_EINVAL, "gather waves %lld is not 4 or 8", (long long)value);
+        b->waves = (int)value;
+        batch_drop_graph(b);
+        return SC_OK;
+    }
     if (param == SC_PARAM_SKY_LMAX) return fail(SC_EINVAL, "the sky lmax of a batch is fixed at creation");
     if (det < -1 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [-1, %d)", det, b->ndet);
     for (int d = 0; d < b->ndet; ++d) {
@@ -782,6 +796,10 @@ int sc_batch_get_param(const sc_batch *b, int det, int param, int64_t *value) {
     if (!b || !value) return fail(SC_EINVAL, "NULL batch or output");
     if (param == SC_PARAM_GATHER_WGS_PER_CU) {
         *value = b->wgs_per_cu;
+        return SC_OK;
+    }
+    if (param == SC_PARAM_GATHER_WAVES) {
+        *value = b->waves;
         return SC_OK;
     }
     if (det < 0 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [0, %d)", det, b->ndet);

@@ -201,3 +201,24 @@ def test_binned_gather_edge_cases(torch_dev, api, oracle_lib, prec):
     assert np.max(np.abs(valu - direct)) <= tol_same * np.max(np.abs(ref))
     for got in (binned, direct, valu):
         assert _rel_l2(got, ref) <= (1e-6 if prec != "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("L,K", [(64, 20), (128, 100)])
+def test_gather_workgroup_shapes_agree(torch_dev, api, oracle_lib, L, K):
+    """4- and 8-wave gather workgroups run the same products in the same order: equal outputs."""
+    torch, dev = torch_dev
+    a, b = _inputs(L, K, 1300 + L)
+    p = W.scan_pointings(30000, device=dev)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    out = {}
+    for waves in (4, 8):
+        plan.set_param("gather_waves", waves)
+        assert plan.get_param("gather_waves") == waves
+        out[waves] = plan.interpolate(p).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(out[4], out[8])
+    idx = torch.arange(0, 30000, 3001, device=dev)
+    ref = oracle_lib.convolve(a, b, L, K, p[idx].cpu().numpy())
+    got = out[8][idx].double().cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
