@@ -51,24 +51,60 @@ namespace {
 
 using namespace wrec;
 
+// Coefficients and weights of one step (l -> l+1), read from LDS.
+struct RecCoef {
+    double a, b;
+    double2 wp, wm;
+};
+
+__device__ __forceinline__ RecCoef rec_load(int t, const double *cA, const double *cB, const double2 *cWp,
+                                            const double2 *cWm) {
+    return RecCoef{cA[t], cB[t], cWp[t], cWm[t]};
+}
+
 // One recursion step for every ring of the lane: contract u^l (true value
 // u S_l 2^{1200 e}, S_l folded into the weights) and advance to u^{l+1}.
 template <int RPT>
-__device__ __forceinline__ void rec_step(int t, const double *cA, const double *cB, const double2 *cWp,
-                                         const double2 *cWm, const double *x, double *u, double *up, double2 *fp,
+__device__ __forceinline__ void rec_step(const RecCoef &c, const double *x, double *u, double *up, double2 *fp,
                                          double2 *fm) {
-    const double a = cA[t], b = cB[t];
-    const double2 wp = cWp[t], wm = cWm[t];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        fp[r].x = fma(wp.x, u[r], fp[r].x);
-        fp[r].y = fma(wp.y, u[r], fp[r].y);
-        fm[r].x = fma(wm.x, u[r], fm[r].x);
-        fm[r].y = fma(wm.y, u[r], fm[r].y);
-        const double un = fma(fma(a, x[r], -b), u[r], -up[r]);
+        fp[r].x = fma(c.wp.x, u[r], fp[r].x);
+        fp[r].y = fma(c.wp.y, u[r], fp[r].y);
+        fm[r].x = fma(c.wm.x, u[r], fm[r].x);
+        fm[r].y = fma(c.wm.y, u[r], fm[r].y);
+        const double un = fma(fma(c.a, x[r], -c.b), u[r], -up[r]);
         up[r] = u[r];
         u[r] = un;
     }
+}
+
+// Steps t0 .. t1-1.  Four steps per iteration with two coefficient sets in
+// turn: the LDS reads of the next two steps are issued before the current two
+// steps' arithmetic (a scheduling barrier keeps them there), and an even step
+// count per iteration returns u / u_prev to the same registers, so neither the
+// loads nor the recursion need register moves.
+template <int RPT>
+__device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, const double *cB, const double2 *cWp,
+                                          const double2 *cWm, const double *x, double *u, double *up, double2 *fp,
+                                          double2 *fm) {
+    const int te = t0 + ((t1 - t0) & ~3);
+    if (te > t0) {
+        RecCoef a0 = rec_load(t0, cA, cB, cWp, cWm), a1 = rec_load(t0 + 1, cA, cB, cWp, cWm);
+        for (int t = t0; t < te; t += 4) {
+            const RecCoef b0 = rec_load(t + 2, cA, cB, cWp, cWm), b1 = rec_load(t + 3, cA, cB, cWp, cWm);
+            __builtin_amdgcn_sched_barrier(0);
+            rec_step<RPT>(a0, x, u, up, fp, fm);
+            rec_step<RPT>(a1, x, u, up, fp, fm);
+            const int tn = t + 4 < te ? t + 4 : t;  // last iteration: harmless re-read
+            a0 = rec_load(tn, cA, cB, cWp, cWm);
+            a1 = rec_load(tn + 1, cA, cB, cWp, cWm);
+            __builtin_amdgcn_sched_barrier(0);
+            rec_step<RPT>(b0, x, u, up, fp, fm);
+            rec_step<RPT>(b1, x, u, up, fp, fm);
+        }
+    }
+    for (int t = te; t < t1; ++t) rec_step<RPT>(rec_load(t, cA, cB, cWp, cWm), x, u, up, fp, fm);
 }
 
 template <int RPT>
@@ -153,16 +189,14 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         __syncthreads();
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
         if (fast) {
-#pragma unroll 2
-            for (int t = 0; t < nl; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            rec_steps<RPT>(0, nl, cA, cB, cWp, cWm, x, u, up, fp, fm);
             continue;
         }
         // Rescaling is checked once per 8 steps: one step grows |u| by at most
         // ~2^11, far inside the 2^424 left below overflow.
         for (int t0 = 0; t0 < nl; t0 += 8) {
             const int t1 = t0 + 8 < nl ? t0 + 8 : nl;
-#pragma unroll 2
-            for (int t = t0; t < t1; ++t) rec_step<RPT>(t, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            rec_steps<RPT>(t0, t1, cA, cB, cWp, cWm, x, u, up, fp, fm);
             if (fast) continue;
             bool low = false;
 #pragma unroll
