@@ -46,7 +46,8 @@ def stage_model(info: dict, n: int, prec: int):
     """Algorithmic work per launch of each kernel: (bound, units, unit_name, peak)."""
     L, K = info["lmax"], info["kmax"]
     nm = 2 * L + 1
-    nr, rows, cols, nc, Wd = info["n_rings"], info["map_rows"], info["map_cols"], info["n_comp"], info["W"]
+    nr, rows, cols, Wd = info["n_rings"], info["map_rows"], info["map_cols"], info["W"]
+    nc = 2 * K + 1  # algorithmic component count (the stored zero sin 0 psi map is not counted)
     esz = 8 if prec == 0 else 4
     dv = ring_dvalues(L, K, nr)
     return {

@@ -107,7 +107,8 @@ int sc_plan_set_stream(sc_plan *plan, void *stream);
  *   0 lmax, 1 kmax, 2 precision, 3 W, 4 n_rings (theta rings of the
  *   recursion), 5 n_fft_theta (2 n_rings), 6 n_theta_fine (oversampled
  *   full-circle theta grid), 7 n_phi (oversampled phi grid), 8 map_rows,
- *   9 map_cols, 10 n_comp (2 kmax + 1), 11 n_comp_padded,
+ *   9 map_cols, 10 n_comp (2 kmax + 2: a cos k psi, sin k psi
+ *   pair per k, the sin 0 psi slot zero), 11 n_comp_padded,
  *   12 workspace bytes.
  * Returns the number of values available (13).
  */

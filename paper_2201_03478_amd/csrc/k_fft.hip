@@ -15,11 +15,24 @@
 //    rows r in [-W/2 + 1, n2os/2 + W/2] (ghost rows past the poles included).
 //  phi: per (k, row) the deconvolved m-spectrum is inverse-transformed onto
 //    phi_q = q 2 pi / nphi, q in [-W/2 + 1, nphi + W/2 - 1] (wrap copies), and
-//    stored as the real components M_0 = T_0, M_{2k-1} = 2 Re T_k,
-//    M_{2k} = -2 Im T_k so that c = sum_c basis_c(psi) M_c (Eq. 8).
+//    stored as the real components M_0 = T_0, M_1 = 0, M_{2k} = 2 Re T_k,
+//    M_{2k+1} = -2 Im T_k, so that c = sum_c basis_c(psi) M_c (Eq. 8) with
+//    basis_{2k} = cos k psi and basis_{2k+1} = sin k psi.
 #include "fft_lds.h"
 
 namespace {
+
+// one aligned store of a component pair (the padded row length is even)
+template <typename T>
+__device__ inline void store_pair(T *o, double a, double b);
+template <>
+__device__ inline void store_pair<double>(double *o, double a, double b) {
+    *(double2 *)o = make_double2(a, b);
+}
+template <>
+__device__ inline void store_pair<float>(float *o, double a, double b) {
+    *(float2 *)o = make_float2((float)a, (float)b);
+}
 
 template <int NT, int PT, typename S2, typename SOS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
@@ -112,13 +125,9 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
         int q = col + q0;
         q = q < 0 ? q + np : (q >= np ? q - np : q);
         const double2 v = A[q];
-        T *o = dst + (size_t)col * ncp;
-        if (k == 0) {
-            o[0] = (T)v.x;
-        } else {
-            o[2 * k - 1] = (T)(2.0 * v.x);
-            o[2 * k] = (T)(-2.0 * v.y);
-        }
+        // one aligned pair store per column: (M_{2k}, M_{2k+1}) = (2 Re T_k, -2 Im T_k), (Re T_0, 0)
+        const double s = k == 0 ? 1.0 : 2.0;
+        store_pair<T>(dst + (size_t)col * ncp + 2 * k, s * v.x, k == 0 ? 0.0 : -s * v.y);
     }
 }
 
@@ -128,8 +137,8 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
 // sky coefficients).  With <u, v> = Re sum conj(u) v on complex arrays:
 //
 //  phi: T_k(row, q) = sum_m G(row, m) e^{i m q h_phi} and the stored real maps
-//    M_0 = Re T_0, M_{2k-1} = 2 Re T_k, M_{2k} = -2 Im T_k (wrap columns are
-//    copies).  Given map gradients GM, U_k = 2 (GM_{2k-1} - i GM_{2k})
+//    M_0 = Re T_0, M_1 = 0, M_{2k} = 2 Re T_k, M_{2k+1} = -2 Im T_k (wrap
+//    columns are copies).  Given map gradients GM, U_k = 2 (GM_{2k} - i GM_{2k+1})
 //    (U_0 = GM_0), wrap columns folded onto q mod nphi; then
 //    Gadj(row, m) = sum_q e^{-i m q h_phi} U(q)  (forward FFT).
 //  theta: G(r) = sum_n e^{i n r h} D_phi(m) p(n) X(n), X = FFT_{n2}(f),
@@ -156,7 +165,7 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
     for (int q = tid; q < np; q += nth) {
         const T *o = src + (size_t)(q - q0) * ncp;
         A[q] = k == 0 ? make_double2((double)o[0], 0.0)
-                      : make_double2(2.0 * (double)o[2 * k - 1], -2.0 * (double)o[2 * k]);
+                      : make_double2(2.0 * (double)o[2 * k], -2.0 * (double)o[2 * k + 1]);
     }
     __syncthreads();
     if (tid < W - 1) {
@@ -168,8 +177,8 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
         if (k == 0) {
             A[qq].x += (double)o[0];
         } else {
-            A[qq].x += 2.0 * (double)o[2 * k - 1];
-            A[qq].y -= 2.0 * (double)o[2 * k];
+            A[qq].x += 2.0 * (double)o[2 * k];
+            A[qq].y -= 2.0 * (double)o[2 * k + 1];
         }
     }
     __syncthreads();

@@ -4,7 +4,8 @@
 // Sec. 2.1, Eq. 8 with the finite-resolution maps and interpolation described
 // after the two-step algorithm)
 //     c = sum_{i,j < W} w_theta(i) w_phi(j) sum_c basis_c(psi) M_c[r0 + i][q0 + j],
-//     basis = (1, cos psi, sin psi, cos 2 psi, sin 2 psi, ...),
+//     basis = (1, 0, cos psi, sin psi, cos 2 psi, sin 2 psi, ...)
+//     (basis_{2k} = cos k psi, basis_{2k+1} = sin k psi; the stored sin 0 psi map is zero),
 // with exponential-of-semicircle weights w(z) = exp(beta (sqrt(1 - z^2) - 1)),
 // z = (x - x_node) / (W/2) in grid units.  The grid indices and the fractional
 // offsets are formed in FP64 (a float phi near 2 pi would misplace the stencil
@@ -69,14 +70,9 @@ k_gather_v1(const double *__restrict__ ptg, int64_t n, const T *__restrict__ map
         for (int t = 0; t < 4; ++t) {
             const int c = lane + 64 * t;
             if (c < ncomp) {
-                T bas = (T)1;
-                if (c > 0) {
-                    const int kk = (c + 1) >> 1;
-                    double sn, cs;
-                    sincos((double)kk * psr, &sn, &cs);
-                    bas = (T)((c & 1) ? cs : sn);
-                }
-                part += bas * acc[t];
+                double sn, cs;
+                sincos((double)(c >> 1) * psr, &sn, &cs);
+                part += (T)((c & 1) ? sn : cs) * acc[t];
             }
         }
         for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off);
@@ -195,11 +191,11 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
             {
                 const int sl = tid >> 2, q = tid & 3;  // 4 lanes per sample, 4 groups each
                 const double2 e1 = E1[sl];
-                int kc = ((4 * q) * CPT + 1) >> 1;
+                int kc = ((4 * q) * CPT) >> 1;
                 double2 z = cpowi(e1, kc);
 #pragma unroll
                 for (int g = 4 * q; g < 4 * q + 4; ++g) {
-                    const int k0 = (g * CPT + 1) >> 1;
+                    const int k0 = (g * CPT) >> 1;
                     if (k0 > kc) {
                         z = cmul(z, cpowi(e1, k0 - kc));
                         kc = k0;
@@ -215,21 +211,17 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 const int sl = 4 * sg + q;
                 const double2 e1 = E1[sl];
                 double2 z = Eg[sl * 16 + cg];
-                int k = (c0 + 1) >> 1;
+                int k = c0 >> 1;
                 T part = (T)0;
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) {
                     const int c = c0 + j;
                     if (c < ncomp) {
-                        if (c == 0) {
-                            part += acc[q][j];
-                        } else {
-                            if (((c + 1) >> 1) > k) {
-                                z = cmul(z, e1);
-                                ++k;
-                            }
-                            part = fma((T)((c & 1) ? z.x : z.y), acc[q][j], part);
+                        if ((c >> 1) > k) {
+                            z = cmul(z, e1);
+                            ++k;
                         }
+                        part = fma((T)((c & 1) ? z.y : z.x), acc[q][j], part);
                     }
                 }
                 part += __shfl_xor(part, 8);
@@ -283,9 +275,9 @@ hipError_t launch_binned_t(sc_plan *p, void *tod) {
 // the 16x16x4 instruction: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16(i/4), register i%4.  Lane (r = lane%16, grp = lane/16)
 // therefore holds components c = 16 ct + 4 grp + v (v < 4) of ONE sample
-// (16 (TPW w + h) + r): its orders are k0 = 8 ct + 2 grp (sin), k0 + 1 (cos, sin)
-// and k0 + 2 (cos), reached from e^{i 2 grp psi} by FP64 rotations with
-// e^{i psi} and e^{i 8 psi}; the sum over the lane's components is completed
+// (16 (TPW w + h) + r): the cos/sin pairs of orders k0 = 8 ct + 2 grp and k0 + 1,
+// reached from e^{i 2 grp psi} by FP64 rotations with e^{i psi} and
+// e^{i 8 psi}; the sum over the lane's components is completed
 // across the four lanes of the sample.
 // Map rows in LDS are padded to a stride of NC + 16 floats when the tile count
 // is even, and the weight rows to 144 floats, so the four lane groups of an
@@ -436,15 +428,18 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 {
+                    // components c0 .. c0 + 3 are the pairs k0 = c0 / 2 and k0 + 1; z = e^{i k0 psi}
                     const int c0 = 16 * ct + 4 * grp;
                     const double2 z1 = cmul(z, e1);
-                    const double z2x = z1.x * e1.x - z1.y * e1.y;
                     const floatx4 x = acc[h][ct];
-                    const float b0 = c0 == 0 ? 1.f : (float)z.y;
-                    if (c0 < D.ncomp) part = fmaf(b0, x[0], part);
-                    if (c0 + 1 < D.ncomp) part = fmaf((float)z1.x, x[1], part);
-                    if (c0 + 2 < D.ncomp) part = fmaf((float)z1.y, x[2], part);
-                    if (c0 + 3 < D.ncomp) part = fmaf((float)z2x, x[3], part);
+                    if (c0 < D.ncomp) {
+                        part = fmaf((float)z.x, x[0], part);
+                        part = fmaf((float)z.y, x[1], part);
+                    }
+                    if (c0 + 2 < D.ncomp) {
+                        part = fmaf((float)z1.x, x[2], part);
+                        part = fmaf((float)z1.y, x[3], part);
+                    }
                     z = cmul(z, e8);
                 }
             }

@@ -69,12 +69,9 @@ k_scatter_direct(const double *__restrict__ ptg, int64_t n, const T *__restrict_
             const int c = lane + 64 * t;
             T bas = (T)0;
             if (c < ncomp) {
-                bas = (T)1;
-                if (c > 0) {
-                    double sn, cs;
-                    sincos((double)((c + 1) >> 1) * psr, &sn, &cs);
-                    bas = (T)((c & 1) ? cs : sn);
-                }
+                double sn, cs;
+                sincos((double)(c >> 1) * psr, &sn, &cs);
+                bas = (T)((c & 1) ? sn : cs);
             }
             val[t] = ys * bas;
         }
@@ -87,7 +84,7 @@ k_scatter_direct(const double *__restrict__ ptg, int64_t n, const T *__restrict_
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int c = lane + 64 * t;
-                    if (c < ncomp) atomic_add(base + c, wij * val[t]);
+                    if (c < ncomp && c != 1) atomic_add(base + c, wij * val[t]);  // basis_1 = sin 0 = 0
                 }
             }
         }
@@ -160,22 +157,18 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
                 const int c0 = qq * PER;
                 const double2 e1 = E1[sl];
                 const float yy = Ys[sl];
-                int kc = (c0 + 1) >> 1;
+                int kc = c0 >> 1;  // PER is even: the range starts on a cos/sin pair
                 double2 z = cpow_int(e1, kc);
                 float *vrow = Vsh + sl * NC;
                 for (int j = 0; j < PER; ++j) {
                     const int c = c0 + j;
                     float vv = 0.f;
                     if (c < ncomp) {
-                        if (c == 0) {
-                            vv = yy;
-                        } else {
-                            if (((c + 1) >> 1) > kc) {
-                                z = cmul(z, e1);
-                                ++kc;
-                            }
-                            vv = yy * (float)((c & 1) ? z.x : z.y);
+                        if ((c >> 1) > kc) {
+                            z = cmul(z, e1);
+                            ++kc;
                         }
+                        vv = yy * (float)((c & 1) ? z.y : z.x);
                     }
                     vrow[c] = vv;
                 }
@@ -201,7 +194,7 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int c = 16 * ct + r;
-                if (c < ncomp) atomic_add(base + c, acc[ct][v]);
+                if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
             }
         }
     }

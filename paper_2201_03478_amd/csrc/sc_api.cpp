@@ -308,7 +308,9 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     if (p->nphi < 2 * W) p->nphi = next_smooth(2 * W, false);
     p->rows = p->n2os / 2 + W;
     p->cols = p->nphi + W - 1;
-    p->ncomp = 2 * kmax + 1;
+    // component pairs: (2k, 2k + 1) hold the cos k psi and sin k psi maps; the
+    // sin 0 psi slot (component 1) is zero, so each phi column stores one pair.
+    p->ncomp = 2 * kmax + 2;
     // FP32 maps: components padded to the 16-wide tiles of the matrix-core gather,
     // so an 8 x 8 block of the map is 8 contiguous runs; FP64 maps: to 4.
     p->ncp = precision == SC_FP64 ? (p->ncomp + 3) & ~3 : (p->ncomp + 15) & ~15;

@@ -81,7 +81,7 @@ struct sc_plan {
     int n2os;          // oversampled full-circle theta grid, spacing 2 pi / n2os
     int nphi;          // oversampled phi grid, spacing 2 pi / nphi
     int rows, cols;    // stored map rows (theta nodes incl. ghost rows) and columns (incl. wrap)
-    int ncomp, ncp;    // 2 kmax + 1 components, padded count
+    int ncomp, ncp;    // 2 kmax + 2 stored components (cos/sin pairs), padded count
     int rpt, ngroups;  // recursion layout: rings per lane, ring groups per (k, m)
     int rpt_mx, ngroups_mx;  // the same for the FP32 (mixed-precision) recursion
     hipStream_t stream;
