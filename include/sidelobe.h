@@ -187,16 +187,32 @@ int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage
  *   SC_PARAM_RING_RPT           rings per lane of the ring-sum kernel, 1..4 (1..8 for SC_MIXED)
  *   SC_PARAM_SKY_LMAX           band limit of the layout of the alm array given to
  *                               sc_set_sky_beam (>= lmax; a shared sky may have a larger one)
- *   SC_PARAM_GATHER_WAVES       waves per matrix-core gather workgroup, 4 or 8 (default 4);
- *                               the same 128-sample chunk split over more waves
+ *   SC_PARAM_GATHER_WAVES       waves per workgroup of the SC_MMA_FP32 gather, 4 or 8 (default 4);
+ *                               the same 128-sample chunk split over more waves (the split
+ *                               form always runs 4)
+ *   SC_PARAM_GATHER_MMA         product form of the FP32 matrix-core gather (sc_gather_mma):
+ *                               SC_MMA_SPLIT16 (default) or SC_MMA_FP32
  */
 enum sc_param {
     SC_PARAM_BIN_CHUNK = 1,
     SC_PARAM_GATHER_WGS_PER_CU = 2,
     SC_PARAM_RING_RPT = 3,
     SC_PARAM_SKY_LMAX = 4,
-    SC_PARAM_GATHER_WAVES = 5
+    SC_PARAM_GATHER_WAVES = 5,
+    SC_PARAM_GATHER_MMA = 6
 };
+
+/*
+ * Product forms of the interpolation contraction (FP32 maps, W = 8), both with
+ * FP32 accumulation:
+ *   SC_MMA_FP32     FP32 x FP32 matrix products.
+ *   SC_MMA_SPLIT16  every FP32 operand split into two FP16 parts (x ~ x_hi + x_lo,
+ *                   about 2^-24 relative) and each product taken as
+ *                   a_hi b_hi + a_hi b_lo + a_lo b_hi on the FP16 matrix cores,
+ *                   with exact power-of-two range scalings; about 3/16 of the
+ *                   matrix time of SC_MMA_FP32 at a similar rounding level.
+ */
+enum sc_gather_mma { SC_MMA_FP32 = 0, SC_MMA_SPLIT16 = 1 };
 int sc_plan_set_param(sc_plan *plan, int param, int64_t value);
 int sc_plan_get_param(const sc_plan *plan, int param, int64_t *value);
 

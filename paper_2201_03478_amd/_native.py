@@ -17,6 +17,8 @@ SC_OK, SC_EINVAL, SC_ENOMEM, SC_EHIP, SC_ESTATE = 0, -1, -2, -3, -4
 SC_FP64, SC_F64MAPS_F32GATHER, SC_MIXED = 0, 1, 2
 
 SC_PARAM_BIN_CHUNK, SC_PARAM_GATHER_WGS_PER_CU, SC_PARAM_RING_RPT, SC_PARAM_SKY_LMAX, SC_PARAM_GATHER_WAVES = 1, 2, 3, 4, 5
+SC_PARAM_GATHER_MMA = 6
+SC_MMA_FP32, SC_MMA_SPLIT16 = 0, 1
 
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",

@@ -5,7 +5,7 @@ stream, the candidates of
   * ring_rpt           rings per lane of the ring-sum kernel (ring-sum stage time),
   * bin_chunk          samples per gather work item, and
   * gather_wgs_per_cu  persistent gather workgroups per CU and
-  * gather_waves       waves per gather workgroup (binning + gather time),
+  * gather_waves       waves per workgroup of the FP32-product gather (binning + gather time),
 keeps the fastest, and caches the choice in a JSON file keyed by
 "arch|L<lmax>|K<kmax>|P<precision>" ($SC_AUTOTUNE_CACHE, default
 ~/.cache/paper_2201_03478_amd/autotune.json).  Only launch shapes change: every
@@ -91,9 +91,11 @@ def tune_plan(plan, alm, blm, ptg, reps: int = 3, use_cache: bool = True) -> dic
         plan.set_sky_beam(alm, blm)
         out = torch.empty(ptg.shape[0], dtype=plan.tod_dtype, device=ptg.device)
         times = {}
+        # the workgroup shape is a choice of the FP32 product form only
+        shapes = GATHER_WAVES if plan.get_param("gather_mma") == N.SC_MMA_FP32 else (4,)
         for c in BIN_CHUNK:
             for w in WGS_PER_CU:
-                for nw in GATHER_WAVES:
+                for nw in shapes:
                     plan.set_param("bin_chunk", c)
                     plan.set_param("gather_wgs_per_cu", w)
                     plan.set_param("gather_waves", nw)

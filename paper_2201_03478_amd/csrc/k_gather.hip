@@ -110,7 +110,7 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 const T *__restrict__ maps, T *__restrict__ tod, int cols, int ncp, int ncomp, int nkc,
                 double beta) {
     constexpr int NC = 16 * CPT;  // staged components (zero-padded)
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     T *Psh = (T *)smem_d;         // [64 taps][NC]
     T *Wsh = Psh + 64 * NC;       // [64 taps][64 samples]; reused for Eg after the product
     double2 *Eg = (double2 *)Wsh; // [64 samples][16 groups] e^{i k0(g) psi}
@@ -289,6 +289,45 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
     return sizeof(float) * (64 * (16 * (size_t)CT + 16) + 16 * GW1) + GCH * (sizeof(double) + sizeof(int));
 }
 
+// The k-sum of one chunk: lane (r, grp) of wave w holds, for each of its TPW
+// sample tiles h, components 16 ct + 4 grp + v of sample s0 + 16 h (s0 =
+// 16 TPW w + r); it forms sum_c basis_c(psi) X[c] over them, the four lanes of
+// the sample add their parts, and the sum (times oscale) is the sample's value.
+template <int CT, int TPW>
+__device__ __forceinline__ void ksum_store(const GatherDet &D, const floatx4 (&acc)[TPW][CT], const double *Psi,
+                                           const int *Idx, int s0, int grp, int ns, float oscale) {
+#pragma unroll
+    for (int h = 0; h < TPW; ++h) {
+        const int sl = s0 + 16 * h;
+        double sn, cs;
+        sincos(Psi[sl], &sn, &cs);
+        const double2 e1 = make_double2(cs, sn);
+        const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
+        const double2 e8 = cmul(e4, e4);
+        double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
+        float part = 0.f;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            // components c0 .. c0 + 3 are the pairs k0 = c0 / 2 and k0 + 1; z = e^{i k0 psi}
+            const int c0 = 16 * ct + 4 * grp;
+            const double2 z1 = cmul(z, e1);
+            const floatx4 x = acc[h][ct];
+            if (c0 < D.ncomp) {
+                part = fmaf((float)z.x, x[0], part);
+                part = fmaf((float)z.y, x[1], part);
+            }
+            if (c0 + 2 < D.ncomp) {
+                part = fmaf((float)z1.x, x[2], part);
+                part = fmaf((float)z1.y, x[3], part);
+            }
+            z = cmul(z, e8);
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (grp == 0 && sl < ns) D.tod[Idx[sl]] = part * oscale;
+    }
+}
+
 // One work item: stage the anchor's map block, then contract its samples GCH at a
 // time.  CT is the item's exact component-tile count (a compile-time constant,
 // so the product loop has no per-tile branches and its LDS loads run ahead of
@@ -415,81 +454,328 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             for (int ct = 0; ct < CT; ++ct) a[ct] = an[ct];
         }
 
-#pragma unroll
-        for (int h = 0; h < TPW; ++h) {
-            const int sl = s0 + 16 * h;
-            double sn, cs;
-            sincos(Psi[sl], &sn, &cs);
-            const double2 e1 = make_double2(cs, sn);
-            const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
-            const double2 e8 = cmul(e4, e4);
-            double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
-            float part = 0.f;
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                {
-                    // components c0 .. c0 + 3 are the pairs k0 = c0 / 2 and k0 + 1; z = e^{i k0 psi}
-                    const int c0 = 16 * ct + 4 * grp;
-                    const double2 z1 = cmul(z, e1);
-                    const floatx4 x = acc[h][ct];
-                    if (c0 < D.ncomp) {
-                        part = fmaf((float)z.x, x[0], part);
-                        part = fmaf((float)z.y, x[1], part);
-                    }
-                    if (c0 + 2 < D.ncomp) {
-                        part = fmaf((float)z1.x, x[2], part);
-                        part = fmaf((float)z1.y, x[3], part);
-                    }
-                    z = cmul(z, e8);
-                }
-            }
-            part += __shfl_xor(part, 16);
-            part += __shfl_xor(part, 32);
-            if (grp == 0 && sl < ns) D.tod[Idx[sl]] = part;
-        }
+        ksum_store<CT, TPW>(D, acc, Psi, Idx, s0, grp, ns, 1.f);
         __syncthreads();  // W1, Psi, Idx are rewritten by the next chunk
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split products on the FP16/FP8 matrix cores, to FP32 accuracy.  A map value
+// x (FP32, 24 significant bits) is written exactly as x = a1 + a2 + a3 with
+// a1 = fp16(x), a2 = fp16(x - a1) (round to nearest; 11 + 11 bits) and the
+// remainder a3 = x - a1 - a2, which has at most 2 significant bits and is held
+// exactly in FP8 (e4m3).  A tap weight w is written as b1 + b2 (two FP16 parts,
+// |w - b1 - b2| <= 2^-22 w) and as fp8(w).  The product is
+//     x w ~ a1 b1 + a1 b2 + a2 b1 + a2 b2 + a3 fp8(w)
+// (the omitted terms are below 2^-26 |x w|): four v_mfma_f32_16x16x32_f16 and
+// one v_mfma_f32_16x16x32_fp8_fp8, FP32 accumulation, i.e. 9/32 of the matrix
+// time of the FP32 form.  The map values carry all 24 bits because their
+// rounding errors are amplified by the cancellation in the k-sum; the weight's
+// 2^-22 is not (a weight multiplies every component of its tap alike).
+// Ranges are handled by exact power-of-two scalings: the map block of an item
+// by 2^(15 - e) with 2^e above its largest magnitude (a workgroup max taken
+// while the block is staged), the weights by 2^14 (FP16 parts) and the
+// remainders a3 by 2^14 (FP8); the k-sum undoes them.  Values far below the
+// block maximum lose relative, not absolute, precision in the subnormal
+// ranges: an absolute error below 2^-37 of the block maximum.
+//
+// Operand layout of the 16x16x32 instructions: A[i][k] in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D as for the
+// FP32 form.  Taps are grouped in two halves of 32 (map rows 0-3 and 4-7);
+// within a half, lane group g holds map row 4 half + g and element q the map
+// column q, for A (component r of tile ct) and B (sample r of tile h) alike.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+constexpr float SPLIT_WSCALE = 16384.f;  // 2^14
+constexpr float SPLIT_RSCALE = 16384.f;  // 2^14
+
+__host__ __device__ constexpr size_t split_lds_bytes(int CT) {
+    return 2 * (2 * (size_t)CT * 64 * sizeof(half8)) + 2 * (size_t)CT * 64 * sizeof(long) + sizeof(float) * 16 * GW1 +
+           GCH * (sizeof(double) + sizeof(int));
+}
+
+// An empty use of a register value (keeps it allocated up to this point).
+template <typename V>
+__device__ __forceinline__ void keep_live(const V &v) {
+    asm volatile("" ::"v"(v));
+}
+
+// The value as computed (rounded to FP32 and held in a register): the compiler
+// cannot fold the operation that produced it into a later conversion.
+__device__ __forceinline__ float as_is(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// eight floats to eight FP8 (e4m3) bytes, element q in byte q
+__device__ __forceinline__ long pack_fp8x8(const float (&f)[8]) {
+    int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], 0, false);
+    w0 = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], w0, true);
+    int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], 0, false);
+    w1 = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], w1, true);
+    return (long)(((unsigned long)(unsigned)w1 << 32) | (unsigned)w0);
+}
+
 template <int CT, int NWV>
+__device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax) {
+    constexpr int NT = 64 * NWV;
+    constexpr int TPW = 8 / NWV;
+    constexpr int NC = 16 * CT;
+    constexpr int NC4 = NC / 4;
+    constexpr int NU = 8 * NC4;                // staging units: (map row, 4 components) x 8 columns
+    constexpr int UPT = (NU + NT - 1) / NT;
+    half8 *Ahi = (half8 *)smem_d;              // [2 tap halves][CT][64 lanes]: a1
+    half8 *Alo = Ahi + 2 * CT * 64;            // a2
+    long *Arm = (long *)(Alo + 2 * CT * 64);   // a3 (FP8 x 8)
+    float *W1 = (float *)(Arm + 2 * CT * 64);  // [16][GW1]: theta (0..7) and phi (8..15) factors
+    double *Psi = (double *)(W1 + 16 * GW1);   // [GCH]
+    int *Idx = (int *)(Psi + GCH);             // [GCH]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, grp = lane >> 4;
+    const int row0 = item.x / D.nkc, col0 = item.x - (item.x / D.nkc) * D.nkc;
+    const int sw = tid & (GCH - 1);
+    double pf_u = 0.0, pf_v = 0.0, pf_psi = 0.0;
+    int pf_idx = -1;
+    {
+        const int ns0 = item.z < GCH ? item.z : GCH;
+        if (sw < ns0) {
+            pf_u = D.srt.fu[item.y + sw];
+            pf_v = D.srt.fv[item.y + sw];
+        }
+        if (tid < ns0) {
+            pf_psi = D.srt.psi[item.y + tid];
+            pf_idx = D.srt.idx[item.y + tid];
+        }
+    }
+    float oscale;
+    {
+        floatx4 v[UPT][8];
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < UPT; ++k) {
+            const int u = tid + k * NT;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[k][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (u < NU) {
+                const int i = u / NC4, c4 = u - i * NC4;
+                const floatx4 *s4 = (const floatx4 *)(D.maps + ((size_t)(row0 + i) * D.cols + col0) * NC) + c4;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[k][j] = s4[j * NC4];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(v[k][j][0]), fabsf(v[k][j][1])), fmaxf(fabsf(v[k][j][2]), fabsf(v[k][j][3]))));
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if (lane == 0) atomicMax(smax, __float_as_uint(m));  // non-negative floats order as their bits
+        __syncthreads();
+        int e;
+        (void)frexpf(__uint_as_float(*smax), &e);  // block maximum < 2^e
+        const float ms = ldexpf(1.f, 15 - e);
+        oscale = ldexpf(1.f, e - 15) * (1.f / SPLIT_WSCALE);
+#pragma unroll
+        for (int k = 0; k < UPT; ++k) {
+            const int u = tid + k * NT;
+            if (u < NU) {
+                const int i = u / NC4, c4 = u - i * NC4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = 4 * c4 + q;
+                    half8 hi, lo;
+                    float rm[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float x = as_is(v[k][j][q] * ms);  // exact (power of two)
+                        hi[j] = (_Float16)x;
+                        const float r1 = as_is(x - (float)hi[j]);  // exact
+                        lo[j] = (_Float16)r1;
+                        rm[j] = (r1 - (float)lo[j]) * SPLIT_RSCALE;  // exact; <= 2 significant bits
+                    }
+                    const int o = ((i >> 2) * CT + (c >> 4)) * 64 + (i & 3) * 16 + (c & 15);
+                    Ahi[o] = hi;
+                    Alo[o] = lo;
+                    Arm[o] = pack_fp8x8(rm);
+                }
+            }
+        }
+    }
+    for (int ch = 0; ch < item.z; ch += GCH) {
+        const int ns = item.z - ch < GCH ? item.z - ch : GCH;
+        {
+            const float fu = (float)pf_u, fv = (float)pf_v;
+#pragma unroll
+            for (int i = 0; i < 16 * GCH / NT; ++i) {
+                const int q = (tid >> 7) + (NT / GCH) * i;
+                float w = 0.f;
+                if (sw < ns) w = es_weight<float>(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, D.beta);
+                W1[q * GW1 + sw] = w;
+            }
+        }
+        if (tid < GCH) {
+            Psi[tid] = tid < ns ? pf_psi : 0.0;
+            Idx[tid] = tid < ns ? pf_idx : -1;
+        }
+        __syncthreads();
+        {
+            const int nxt = ch + GCH;
+            const int nns = item.z - nxt < GCH ? item.z - nxt : GCH;
+            if (sw < nns) {
+                pf_u = D.srt.fu[item.y + nxt + sw];
+                pf_v = D.srt.fv[item.y + nxt + sw];
+            }
+            if (tid < nns) {
+                pf_psi = D.srt.psi[item.y + nxt + tid];
+                pf_idx = D.srt.idx[item.y + nxt + tid];
+            }
+        }
+
+        floatx4 acc[TPW][CT];
+#pragma unroll
+        for (int h = 0; h < TPW; ++h)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[h][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int s0 = 16 * TPW * wv + r;
+        float wph[TPW][8];
+#pragma unroll
+        for (int h = 0; h < TPW; ++h)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) wph[h][j] = W1[(8 + j) * GW1 + s0 + 16 * h] * SPLIT_WSCALE;
+        // Software pipeline over the 2 CT (tap half, component tile) steps: the map
+        // operands of step q + 1 are read from LDS before the products of step q.
+        const half8 *ph = Ahi + lane, *pl = Alo + lane;  // step q = kh CT + ct at 64 q
+        const long *pr = Arm + lane;
+        half8 ah = ph[0], al = pl[0];
+        long ar = pr[0];
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh) {
+            half8 bh[TPW], bl[TPW];
+            long b8[TPW];
+#pragma unroll
+            for (int h = 0; h < TPW; ++h) {
+                const float wt = W1[(4 * kh + grp) * GW1 + s0 + 16 * h];
+                float w8[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    // one rounding of the product, and both parts split from that value
+                    // (fusing the product into either conversion would pair the two
+                    // parts with differently rounded products)
+                    const float x = as_is(wt * wph[h][j]);
+                    bh[h][j] = (_Float16)x;
+                    bl[h][j] = (_Float16)(x - (float)bh[h][j]);
+                    w8[j] = x * (1.f / SPLIT_RSCALE);
+                }
+                b8[h] = pack_fp8x8(w8);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int q = kh * CT + ct;
+                const int qn = q + 1 < 2 * CT ? q + 1 : q;
+                const half8 ahn = ph[64 * qn], aln = pl[64 * qn];
+                const long arn = pr[64 * qn];
+                __builtin_amdgcn_sched_barrier(0);
+                // smallest terms first
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ar, b8[h], acc[h][ct], 0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bl[h], acc[h][ct], 0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[h], acc[h][ct], 0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[h], acc[h][ct], 0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < TPW; ++h)
+                    acc[h][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[h], acc[h][ct], 0, 0, 0);
+                // The operands stay live past their products (the barrier keeps the
+                // products above these uses), so that no product's destination is
+                // allocated over its own A or B registers.
+                __builtin_amdgcn_sched_barrier(0);
+                keep_live(ah);
+                keep_live(al);
+                keep_live(ar);
+#pragma unroll
+                for (int h = 0; h < TPW; ++h) {
+                    keep_live(bh[h]);
+                    keep_live(bl[h]);
+                    keep_live(b8[h]);
+                }
+                ah = ahn;
+                al = aln;
+                ar = arn;
+            }
+        }
+        ksum_store<CT, TPW>(D, acc, Psi, Idx, s0, grp, ns, oscale);
+        __syncthreads();  // W1, Psi, Idx are rewritten by the next chunk
+    }
+}
+
+template <int CT, int NWV, int MM>
+__device__ __forceinline__ void gather_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax) {
+    if constexpr (MM == SC_MMA_SPLIT16)
+        gather_split_item<CT, NWV>(D, item, smem_d, smax);
+    else
+        gather_mfma_item<CT, NWV>(D, item, smem_d);
+}
+
+__host__ __device__ constexpr size_t gather_lds_bytes(int MM, int CT) {
+    return MM == SC_MMA_SPLIT16 ? split_lds_bytes(CT) : mfma_lds_bytes(CT);
+}
+
+template <int CT, int NWV, int MM>
 __global__ void __launch_bounds__(64 * NWV, NWV / 2)
 k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     __shared__ int item_sh;
+    __shared__ unsigned smax;  // block maximum of the split form, cleared before every item
     const int nitems = D.totals[1];
-    if (threadIdx.x == 0) item_sh = atomicAdd(cursor, 1);
+    if (threadIdx.x == 0) {
+        item_sh = atomicAdd(cursor, 1);
+        smax = 0u;
+    }
     __syncthreads();
     int it = item_sh;
     while (it < nitems) {
         int nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
-        gather_mfma_item<CT, NWV>(D, D.items[it], smem_d);  // ends with a barrier
-        if (threadIdx.x == 0) item_sh = nxt;
+        gather_item<CT, NWV, MM>(D, D.items[it], smem_d, &smax);  // ends with a barrier
+        if (threadIdx.x == 0) {
+            item_sh = nxt;
+            smax = 0u;
+        }
         __syncthreads();
         it = item_sh;
     }
 }
 
 // Item routine for a runtime tile count ct in [1, CTMAX]: one instantiation per count.
-template <int CT, int CTMAX, int NWV>
-__device__ __forceinline__ void gather_item_ct(const GatherDet &D, const int4 item, double *smem_d, int ct) {
+template <int CT, int CTMAX, int NWV, int MM>
+__device__ __forceinline__ void gather_item_ct(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax,
+                                               int ct) {
     if (ct == CT || CT == CTMAX) {
-        gather_mfma_item<CT, NWV>(D, item, smem_d);
+        gather_item<CT, NWV, MM>(D, item, smem_d, smax);
         return;
     }
-    if constexpr (CT < CTMAX) gather_item_ct<CT + 1, CTMAX, NWV>(D, item, smem_d, ct);
+    if constexpr (CT < CTMAX) gather_item_ct<CT + 1, CTMAX, NWV, MM>(D, item, smem_d, smax, ct);
 }
 
 // All detectors of a batch in one persistent launch: one queue over the items
 // of every detector (detector d's items follow detector d-1's); each item runs
 // with its detector's component-tile count (<= CTMAX).
-template <int CTMAX, int NWV>
+template <int CTMAX, int NWV, int MM>
 __global__ void __launch_bounds__(64 * NWV, NWV / 2)
 k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ cursor) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     __shared__ int start[SC_MAX_DET + 1];
     __shared__ int item_sh;
+    __shared__ unsigned smax;
     if (threadIdx.x == 0) {
+        smax = 0u;
         int s = 0;
         for (int d = 0; d < ndet; ++d) {
             start[d] = s;
@@ -508,8 +794,11 @@ k_gather_batch(const GatherDet *__restrict__ dets, int ndet, int *__restrict__ c
         int d = 0;
         while (d + 1 < ndet && it >= start[d + 1]) ++d;
         const GatherDet D = dets[d];
-        gather_item_ct<1, CTMAX, NWV>(D, D.items[it - start[d]], smem_d, (D.ncomp + 15) / 16);  // ends with a barrier
-        if (threadIdx.x == 0) item_sh = nxt;
+        gather_item_ct<1, CTMAX, NWV, MM>(D, D.items[it - start[d]], smem_d, &smax, (D.ncomp + 15) / 16);  // ends with a barrier
+        if (threadIdx.x == 0) {
+            item_sh = nxt;
+            smax = 0u;
+        }
         __syncthreads();
         it = item_sh;
     }
@@ -525,10 +814,10 @@ int ct_class(int ncomp) {
     return 16;
 }
 
-template <int CT, int NWV>
+template <int CT, int NWV, int MM>
 hipError_t launch_mfma(sc_plan *p, void *tod) {
-    const size_t lds = mfma_lds_bytes(CT);
-    auto kern = k_gather_mfma<CT, NWV>;
+    const size_t lds = gather_lds_bytes(MM, CT);
+    auto kern = k_gather_mfma<CT, NWV, MM>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int grid = sc_persistent_grid((const void *)kern, 64 * NWV, lds, p->gather_wgs_per_cu);
@@ -536,20 +825,23 @@ hipError_t launch_mfma(sc_plan *p, void *tod) {
     return hipGetLastError();
 }
 
-template <int CT, int NWV>
+template <int CT, int NWV, int MM>
 hipError_t launch_mfma_ct(sc_plan *p, void *tod, int ct) {
-    if (ct == CT || CT == 16) return launch_mfma<CT, NWV>(p, tod);
-    if constexpr (CT < 16) return launch_mfma_ct<CT + 1, NWV>(p, tod, ct);
+    if (ct == CT || CT == 16) return launch_mfma<CT, NWV, MM>(p, tod);
+    if constexpr (CT < 16) return launch_mfma_ct<CT + 1, NWV, MM>(p, tod, ct);
     return hipErrorInvalidValue;
 }
 
-template <int NWV>
+template <int NWV, int MM>
 hipError_t launch_mfma_w(sc_plan *p, void *tod) {
-    return launch_mfma_ct<1, NWV>(p, tod, (p->ncomp + 15) / 16);  // exact tile count, 1 .. 16
+    return launch_mfma_ct<1, NWV, MM>(p, tod, (p->ncomp + 15) / 16);  // exact tile count, 1 .. 16
 }
 
+// The split form always runs 4-wave workgroups (its 8-wave build, limited to 128
+// registers per lane, spills heavily and is not used).
 hipError_t launch_mfma_any(sc_plan *p, void *tod) {
-    return p->gather_waves == 8 ? launch_mfma_w<8>(p, tod) : launch_mfma_w<4>(p, tod);
+    if (p->gather_mma == SC_MMA_SPLIT16) return launch_mfma_w<4, SC_MMA_SPLIT16>(p, tod);
+    return p->gather_waves == 8 ? launch_mfma_w<8, SC_MMA_FP32>(p, tod) : launch_mfma_w<4, SC_MMA_FP32>(p, tod);
 }
 }  // namespace
 
@@ -580,10 +872,10 @@ GatherDet sc_gather_det(const sc_plan *p, void *tod) {
     return D;
 }
 
-template <int CTMAX, int NWV>
+template <int CTMAX, int NWV, int MM>
 static hipError_t gather_batch(const GatherDet *dets_dev, int ndet, int *cursor, int wgs_per_cu, hipStream_t stream) {
-    const size_t lds = mfma_lds_bytes(CTMAX);
-    auto kern = k_gather_batch<CTMAX, NWV>;
+    const size_t lds = gather_lds_bytes(MM, CTMAX);
+    auto kern = k_gather_batch<CTMAX, NWV, MM>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int grid = sc_persistent_grid((const void *)kern, 64 * NWV, lds, wgs_per_cu);
@@ -591,21 +883,23 @@ static hipError_t gather_batch(const GatherDet *dets_dev, int ndet, int *cursor,
     return hipGetLastError();
 }
 
-template <int NWV>
+template <int NWV, int MM>
 static hipError_t gather_batch_w(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
                                  hipStream_t stream) {
-    if (max_ct <= 2) return gather_batch<2, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    if (max_ct <= 5) return gather_batch<5, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    if (max_ct <= 13) return gather_batch<13, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
-    return gather_batch<16, NWV>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 2) return gather_batch<2, NWV, MM>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 5) return gather_batch<5, NWV, MM>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    if (max_ct <= 13) return gather_batch<13, NWV, MM>(dets_dev, ndet, cursor, wgs_per_cu, stream);
+    return gather_batch<16, NWV, MM>(dets_dev, ndet, cursor, wgs_per_cu, stream);
 }
 
 // One persistent launch over the binned items of several FP32 plans; max_ct is
-// the largest component-tile count among them, waves the workgroup shape (4 or 8).
+// the largest component-tile count among them, waves the workgroup shape of the
+// FP32 form (4 or 8; the split form runs 4), mma the product form.
 hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu,
-                                  int waves, hipStream_t stream) {
-    return waves == 8 ? gather_batch_w<8>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream)
-                      : gather_batch_w<4>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream);
+                                  int waves, int mma, hipStream_t stream) {
+    if (mma == SC_MMA_SPLIT16) return gather_batch_w<4, SC_MMA_SPLIT16>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream);
+    return waves == 8 ? gather_batch_w<8, SC_MMA_FP32>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream)
+                      : gather_batch_w<4, SC_MMA_FP32>(dets_dev, ndet, max_ct, cursor, wgs_per_cu, stream);
 }
 
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod) {

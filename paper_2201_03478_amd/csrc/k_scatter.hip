@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256)
 k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt, const float *__restrict__ y,
                float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
     constexpr int NC = 16 * CT;
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     float *Vsh = (float *)smem_d;     // [64 samples][NC]
     float *Wsh = Vsh + 64 * NC;       // [64 taps][WROW]: 64 samples + pad (conflict-free A reads)
     float *W1 = Wsh + 64 * WROW;      // [16][64 samples]

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(1024)
 k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ blm, double2 *__restrict__ GA,
                     const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax,
                     int nring) {
-    extern __shared__ double adj_smem[];
+    extern __shared__ __attribute__((aligned(16))) double adj_smem[];
     const int nw = blockDim.x >> 6;
     double *cA = adj_smem, *cB = cA + 64, *cC = cB + 64;                   // [64]
     double *Qw = cC + 64;                                                  // [nw][64][4]

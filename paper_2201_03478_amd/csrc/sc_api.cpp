@@ -319,6 +319,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->bin_chunk = BIN_CHUNK;
     p->gather_wgs_per_cu = 0;
     p->gather_waves = 4;
+    p->gather_mma = SC_MMA_SPLIT16;
     {
         const char *g = std::getenv("SC_GATHER_PATH");
         p->gather_direct = (g && std::strcmp(g, "direct") == 0) ? 1 : 0;
@@ -556,6 +557,10 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
             if (v != 4 && v != 8) return fail(SC_EINVAL, "gather waves %lld is not 4 or 8", (long long)v);
             p->gather_waves = (int)v;
             return SC_OK;
+        case SC_PARAM_GATHER_MMA:
+            if (v != SC_MMA_FP32 && v != SC_MMA_SPLIT16) return fail(SC_EINVAL, "gather product form %lld unknown", (long long)v);
+            p->gather_mma = (int)v;
+            return SC_OK;
         case SC_PARAM_RING_RPT: {
             const int vmax = p->prec == SC_MIXED ? 8 : 4;
             if (v < 1 || v > vmax) return fail(SC_EINVAL, "rings per lane %lld outside [1, %d]", (long long)v, vmax);
@@ -584,6 +589,7 @@ int sc_plan_get_param(const sc_plan *p, int param, int64_t *v) {
         case SC_PARAM_BIN_CHUNK: *v = p->bin_chunk; return SC_OK;
         case SC_PARAM_GATHER_WGS_PER_CU: *v = p->gather_wgs_per_cu; return SC_OK;
         case SC_PARAM_GATHER_WAVES: *v = p->gather_waves; return SC_OK;
+        case SC_PARAM_GATHER_MMA: *v = p->gather_mma; return SC_OK;
         case SC_PARAM_RING_RPT: *v = p->prec == SC_MIXED ? p->rpt_mx : p->rpt; return SC_OK;
         case SC_PARAM_SKY_LMAX: *v = p->alm_lmax; return SC_OK;
         default: return fail(SC_EINVAL, "unknown parameter %d", param);
@@ -657,6 +663,7 @@ struct sc_batch {
     int max_ct;
     int wgs_per_cu;
     int waves;  // gather workgroup shape
+    int mma;    // gather product form
     int warmed;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -688,7 +695,7 @@ hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s) {
             e = D.n > 0 ? sc_launch_binning(p, D.ptg, D.n) : sc_launch_zero(p->bw.totals, 4 * sizeof(int), s);
     }
     if (e == hipSuccess) e = sc_launch_zero(b->cursor, sizeof(int), s);
-    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, b->waves, s);
+    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, b->waves, b->mma, s);
     for (sc_plan *p : b->plans) p->stream = b->stream;
     return e;
 }
@@ -732,6 +739,7 @@ int sc_batch_create(sc_batch **out, const sc_det_desc *dets, int ndet, int lmax_
     b->lmax_sky = lmax_sky;
     b->prec = precision;
     b->waves = 4;
+    b->mma = SC_MMA_SPLIT16;
     b->stream = (hipStream_t)stream;
     b->dets.assign(dets, dets + ndet);
     std::vector<GatherDet> gd(ndet);
@@ -783,6 +791,13 @@ int sc_batch_set_param(sc_batch *b, int det, int param, int64_t value) {
         batch_drop_graph(b);
         return SC_OK;
     }
+    if (param == SC_PARAM_GATHER_MMA) {
+        if (value != SC_MMA_FP32 && value != SC_MMA_SPLIT16)
+            return fail(SC_EINVAL, "gather product form %lld unknown", (long long)value);
+        b->mma = (int)value;
+        batch_drop_graph(b);
+        return SC_OK;
+    }
     if (param == SC_PARAM_SKY_LMAX) return fail(SC_EINVAL, "the sky lmax of a batch is fixed at creation");
     if (det < -1 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [-1, %d)", det, b->ndet);
     for (int d = 0; d < b->ndet; ++d) {
@@ -802,6 +817,10 @@ int sc_batch_get_param(const sc_batch *b, int det, int param, int64_t *value) {
     }
     if (param == SC_PARAM_GATHER_WAVES) {
         *value = b->waves;
+        return SC_OK;
+    }
+    if (param == SC_PARAM_GATHER_MMA) {
+        *value = b->mma;
         return SC_OK;
     }
     if (det < 0 || det >= b->ndet) return fail(SC_EINVAL, "detector %d outside [0, %d)", det, b->ndet);

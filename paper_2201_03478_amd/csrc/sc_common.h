@@ -111,6 +111,7 @@ struct sc_plan {
     int bin_chunk;         // samples per gather work item (tunable)
     int gather_wgs_per_cu; // persistent gather workgroups per CU (0: as many as fit; tunable)
     int gather_waves;      // waves per matrix-core gather workgroup, 4 or 8 (tunable)
+    int gather_mma;        // matrix-core product form, SC_MMA_FP32 or SC_MMA_SPLIT16
     int gather_direct;     // force the per-sample gather (env SC_GATHER_PATH=direct)
     int gather_valu;       // FP32 binned gather on the VALU instead of MFMA (env SC_GATHER_PATH=valu)
     int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
@@ -151,7 +152,7 @@ hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
 GatherDet sc_gather_det(const sc_plan *p, void *tod);
 hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu, int waves,
-                                  hipStream_t stream);
+                                  int mma, hipStream_t stream);
 bool sc_gather_binned_supported(const sc_plan *p);
 
 static inline BinGeom sc_bin_geom(const sc_plan *p) {

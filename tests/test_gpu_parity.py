@@ -205,12 +205,13 @@ def test_binned_gather_edge_cases(torch_dev, api, oracle_lib, prec):
 
 @pytest.mark.parametrize("L,K", [(64, 20), (128, 100)])
 def test_gather_workgroup_shapes_agree(torch_dev, api, oracle_lib, L, K):
-    """4- and 8-wave gather workgroups run the same products in the same order: equal outputs."""
+    """4- and 8-wave workgroups of the FP32 product form run the same products in the same order."""
     torch, dev = torch_dev
     a, b = _inputs(L, K, 1300 + L)
     p = W.scan_pointings(30000, device=dev)
     plan = api.Plan(L, K, "f64maps_f32gather")
     plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    plan.set_param("gather_mma", api.N.SC_MMA_FP32)
     out = {}
     for waves in (4, 8):
         plan.set_param("gather_waves", waves)
@@ -222,3 +223,51 @@ def test_gather_workgroup_shapes_agree(torch_dev, api, oracle_lib, L, K):
     ref = oracle_lib.convolve(a, b, L, K, p[idx].cpu().numpy())
     got = out[8][idx].double().cpu().numpy()
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+@pytest.mark.parametrize("L,K,n", [(64, 20, 30000), (512, 100, 300000)])
+def test_gather_product_forms_agree(torch_dev, api, oracle_lib, L, K, n):
+    """The split FP16/FP8 products (the default) reach the FP32 products' accuracy.
+
+    Both forms contract the same FP32 map block with the same FP32 weights; the
+    split form carries every map value exactly and the weights to 2^-22, so the
+    two agree to the FP32 rounding level and both meet the 1e-6 parity bound
+    against the direct sum of Eq. 2 (Galloway et al. 2022, Sec. 2.1)."""
+    torch, dev = torch_dev
+    a, b = _inputs(L, K, 1400 + L)
+    p = W.scan_pointings(n, device=dev)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    assert plan.get_param("gather_mma") == api.N.SC_MMA_SPLIT16
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    out = {}
+    for mma in (api.N.SC_MMA_FP32, api.N.SC_MMA_SPLIT16):
+        plan.set_param("gather_mma", mma)
+        out[mma] = plan.interpolate(p).double()
+    torch.cuda.synchronize()
+    d = out[api.N.SC_MMA_SPLIT16] - out[api.N.SC_MMA_FP32]
+    rel = float(torch.linalg.norm(d) / torch.linalg.norm(out[api.N.SC_MMA_FP32]))
+    mx = float(d.abs().max() / out[api.N.SC_MMA_FP32].abs().max())
+    print("L=%d K=%d split vs fp32 products: rel-L2 %.3e max %.3e" % (L, K, rel, mx))
+    assert rel <= 5e-7 and mx <= 5e-6
+    idx = torch.arange(0, n, n // 40, device=dev)
+    ref = oracle_lib.convolve(a, b, L, K, p[idx].cpu().numpy())
+    for mma, o in out.items():
+        got = o[idx].cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6, mma
+
+
+@pytest.mark.parametrize("e", [-80, 80])
+def test_split_form_power_of_two_scaling(torch_dev, api, e):
+    """The split form's range scalings are exact powers of two: scaling the sky by
+    2^e scales every output by exactly 2^e (no FP16/FP8 range effects)."""
+    torch, dev = torch_dev
+    L, K = 48, 10
+    a, b = _inputs(L, K, 1500)
+    p = W.scan_pointings(20000, device=dev)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    base = plan.interpolate(p).clone()
+    plan.set_sky_beam(_to(torch, dev, a * 2.0 ** e), _to(torch, dev, b))
+    scaled = plan.interpolate(p).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(scaled, base * 2.0 ** e)
