@@ -30,7 +30,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "conv TOD samples/s, lmax512 kmax100, mixed vs FP64 at 1e-6 rel err"
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}  # MI355X published peaks
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "fp16": 2.5e15, "hbm": 8.0e12}  # MI355X published (dense) peaks
+# The split gather forms one FP32-accurate product block from four FP16 matrix
+# products and one FP8 product (half the FP16 time): 4.5 FP16 blocks.
+PEAK["split"] = PEAK["fp16"] / 4.5
+
+# Sources each stage's kernels are built from (their traffic records are tied to these).
+STAGE_SOURCES = {
+    "ring_sums": ["k_synth.hip", "wigner_rec.h"],
+    "theta_upsample": ["k_fft.hip", "fft_lds.h"],
+    "phi_synthesis": ["k_fft.hip", "fft_lds.h"],
+    "gather": ["k_gather.hip"],
+    "binning": ["k_bin.hip"],
+}
 
 
 def ring_dvalues(L: int, K: int, nring: int) -> int:
@@ -42,8 +54,10 @@ def ring_dvalues(L: int, K: int, nring: int) -> int:
     return tot * nring
 
 
-def stage_model(info: dict, n: int, prec: int):
-    """Algorithmic work per launch of each kernel: (bound, units, unit_name, peak)."""
+def stage_model(info: dict, n: int, prec: int, mma: int = 1):
+    """Algorithmic work per launch of each kernel: (bound, units, unit_name, peak).
+
+    mma is the gather's product form (0: FP32 matrix products, 1: split FP16/FP8)."""
     L, K = info["lmax"], info["kmax"]
     nm = 2 * L + 1
     nr, rows, cols, Wd = info["n_rings"], info["map_rows"], info["map_cols"], info["W"]
@@ -57,18 +71,21 @@ def stage_model(info: dict, n: int, prec: int):
         "theta_upsample": ("hbm", 16.0 * (K + 1) * nm * (nr + rows), "GB/s", PEAK["hbm"]),
         # read the spectra, write the real components of the maps
         "phi_synthesis": ("hbm", 16.0 * (K + 1) * rows * nm + esz * rows * cols * nc, "GB/s", PEAK["hbm"]),
-        # one FMA per (tap, component) per sample
-        "gather": ("alu", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"] if prec == 0 else PEAK["fp32"]),
+        # one FMA per (tap, component) per sample: FP64 VALU, FP32 or split matrix products
+        "gather": (("alu", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"]) if prec == 0 else
+                   ("mfma", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["split"] if mma == 1 else PEAK["fp32"])),
         # pointings read twice (keys, scatter), key + rank written and read, sorted record written
         "binning": ("hbm", n * (2 * 24.0 + 2 * 8.0 + 28.0), "GB/s", PEAK["hbm"]),
     }
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(stage: str) -> str:
+    """Hash of the sources a stage's kernels are compiled from (with the shared headers)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2201_03478_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in STAGE_SOURCES[stage] + ["sc_common.h"]:
         h.update(open(os.path.join(d, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "sidelobe.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -80,7 +97,7 @@ def measured_traffic(stage: str, workload: str):
     try:
         rec = json.load(open(path))
         ent = rec.get(workload, {}).get(stage)
-        if ent and ent.get("source_hash") == kernel_source_hash():
+        if ent and ent.get("source_hash") == kernel_source_hash(stage):
             return ent["bytes_per_launch"]
     except Exception:
         return None
@@ -169,7 +186,7 @@ def main():
     prec = info["precision"]
     print("bench: main form %.3f ms/step" % ms, file=sys.stderr, flush=True)
 
-    model = stage_model(info, n, prec)
+    model = stage_model(info, n, prec, plan.get_param("gather_mma"))
     per_launch = {s: (t / c if c else 0.0) for s, (t, c) in stages.items()}
     dom = max(per_launch, key=per_launch.get)
     bound, units, unit, peak = model[dom]
@@ -187,6 +204,16 @@ def main():
         "avg_launch_ms": per_launch[dom],
         "algorithmic_per_launch": units,
     }
+
+    stage_roofline = {}
+    for s_, t_ in per_launch.items():
+        if not t_ or s_ not in model:
+            continue
+        b_, u_, un_, pk_ = model[s_]
+        a_ = u_ / (t_ * 1e-3)
+        sc_ = 1e12 if un_ == "TFLOP/s" else 1e9
+        stage_roofline[s_] = {"bound": b_, "achieved": a_ / sc_, "peak": pk_ / sc_, "unit": un_, "frac": a_ / pk_,
+                              "avg_launch_ms": t_}
 
     result = {
         "metric": METRIC,
@@ -209,6 +236,7 @@ def main():
         },
         "stages_ms_per_step": {s: t / args.steps for s, (t, c) in stages.items()},
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
     }
 
     # steady state with the maps already built (binning + gather only)
