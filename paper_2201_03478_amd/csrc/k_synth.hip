@@ -110,7 +110,8 @@ __device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, cons
 template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
-            const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
+            const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
+            const double *__restrict__ rtab, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
     __shared__ double cA[64], cB[64];
     __shared__ double2 cWp[64], cWm[64];
@@ -130,6 +131,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     double2 fp[RPT], fm[RPT];
 
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+    const double pfe = (double)pref.e, pfm = log2(pref.m);  // log2 of the start prefactor
     bool scaled = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -138,7 +140,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         fm[r] = make_double2(0.0, 0.0);
         up[r] = 0.0;
         if (j < nring) {
-            start_value(j, nring, m, k, pref, x[r], u[r], e[r]);
+            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], u[r], e[r]);
         } else {
             x[r] = 0.0;
             u[r] = 0.0;
@@ -235,7 +237,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 #define SC_RING_CASE(R)                                                                                      \
     case R:                                                                                                  \
         hipLaunchKernelGGL(k_ring_sums<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,         \
-                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,      \
+                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring,      \
                            p->ngroups, p->alm_lmax);                                                         \
         break;
 

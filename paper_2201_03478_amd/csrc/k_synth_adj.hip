@@ -30,7 +30,8 @@ constexpr int ADJ_ROW = 65;    // padded row length (doubles) of the partial buf
 template <int RPT>
 __global__ void __launch_bounds__(1024)
 k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ blm, double2 *__restrict__ GA,
-                    const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax,
+                    const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
+            const double *__restrict__ rtab, int lmax, int kmax,
                     int nring) {
     extern __shared__ __attribute__((aligned(16))) double adj_smem[];
     const int nw = blockDim.x >> 6;
@@ -55,6 +56,7 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     int e[RPT];
     double2 fap[RPT], fam[RPT];
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+    const double pfe = (double)pref.e, pfm = log2(pref.m);  // log2 of the start prefactor
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int j = (w * RPT + r) * 64 + lane;
@@ -62,7 +64,7 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
         fap[r] = make_double2(0.0, 0.0);
         fam[r] = make_double2(0.0, 0.0);
         if (j < nring) {
-            start_value(j, nring, m, k, pref, x[r], d[r], e[r]);
+            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], d[r], e[r]);
             fap[r] = FA[((size_t)k * nm + (m + lmax)) * nring + j];
             if (m > 0) fam[r] = FA[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)];
         } else {
@@ -202,7 +204,7 @@ static void adj_layout(int nring, int *rpt, int *nw) {
         e = sc_set_lds_attr((const void *)kern, lds);   \
         if (e != hipSuccess) return e;                                                                       \
         hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)blm,      \
-                           p->GA, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring);                          \
+                           p->GA, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring);                          \
     } break;
 
 hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad) {

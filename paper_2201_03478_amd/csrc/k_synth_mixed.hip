@@ -37,7 +37,8 @@ constexpr float MX_BIG = 0x1p64f;  // rescaling divides by 2^128 through the exp
 template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
-                  const double *__restrict__ sbin_m, const int *__restrict__ sbin_e, int lmax, int kmax, int nring,
+                  const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
+            const double *__restrict__ rtab, int lmax, int kmax, int nring,
                   int ngroups, int alm_lmax) {
     __shared__ float cA[64], cB[64], cC[64];
     __shared__ float cW[64][4];
@@ -57,6 +58,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
     int e[RPT];
     floatx4 acc[RPT];
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
+    const double pfe = (double)pref.e, pfm = log2(pref.m);  // log2 of the start prefactor
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int j = (g * RPT + r) * 64 + lane;
@@ -68,7 +70,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
         if (j < nring) {
             double xd, dd;
             int ed;
-            start_value(j, nring, m, k, pref, xd, dd, ed);
+            start_value(rtab + 5 * j, m, k, pfe, pfm, xd, dd, ed);
             // true value dd 2^{1200 ed}: re-express as an FP32 value with a 2^{128 e} step
             int E;
             const double mant = frexp(dd, &E);
@@ -161,7 +163,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
 #define SC_MIXED_CASE(R)                                                                                     \
     case R:                                                                                                  \
         hipLaunchKernelGGL(k_ring_sums_mixed<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,   \
-                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->lmax, p->kmax, p->nring,      \
+                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring,      \
                            p->ngroups_mx, p->alm_lmax);                                                     \
         break;
 

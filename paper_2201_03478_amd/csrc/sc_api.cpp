@@ -192,7 +192,7 @@ void free_plan_buffers(sc_plan *p) {
     std::free(p->tl);
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
-    void *bufs[] = {p->F, p->G, p->maps, p->sbin_m, p->sbin_e, p->tw2, p->tw2os, p->twphi,
+    void *bufs[] = {p->F, p->G, p->maps, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
                     p->phase, p->dphi, p->glx, p->glw};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -343,6 +343,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     rc = rc ? rc : alloc(&p->maps, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_m, sizeof(double) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_e, sizeof(int) * (lmax + 1) * (kmax + 1), &tot);
+    rc = rc ? rc : alloc((void **)&p->rtab, sizeof(double) * 5 * p->nring, &tot);
     rc = rc ? rc : alloc((void **)&p->tw2, sizeof(double2) * p->n2, &tot);
     rc = rc ? rc : alloc((void **)&p->tw2os, sizeof(double2) * p->n2os, &tot);
     rc = rc ? rc : alloc((void **)&p->twphi, sizeof(double2) * p->nphi, &tot);
@@ -359,6 +360,22 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     // padding components stay zero for the plan's lifetime
     hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, p->stream);
     if (e == hipSuccess) e = sc_launch_tables(p);
+    if (e == hipSuccess) {
+        // ring table in extended host precision: theta_j = (j + 1/2) pi / nring
+        std::vector<double> rt(5 * (size_t)p->nring);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int j = 0; j < p->nring; ++j) {
+            const long double th = ((long double)j + 0.5L) * pi / (long double)p->nring;
+            const long double lc = log2l(cosl(0.5L * th)), ls = log2l(sinl(0.5L * th));
+            rt[5 * j] = (double)cosl(th);
+            rt[5 * j + 1] = (double)lc;
+            rt[5 * j + 2] = (double)(lc - (long double)(double)lc);
+            rt[5 * j + 3] = (double)ls;
+            rt[5 * j + 4] = (double)(ls - (long double)(double)ls);
+        }
+        e = hipMemcpyAsync(p->rtab, rt.data(), sizeof(double) * rt.size(), hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // rt is a local buffer
+    }
     if (e != hipSuccess) {
         free_plan_buffers(p);
         delete p;

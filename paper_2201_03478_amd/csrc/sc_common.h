@@ -94,6 +94,7 @@ struct sc_plan {
     void *maps;        // [rows][cols][ncp] float or double
     double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
     int *sbin_e;       // [lmax+1][kmax+1] binary exponent
+    double *rtab;      // [nring][5] cos(theta_j); log2 cos(theta_j / 2), log2 sin(theta_j / 2) as (hi, lo) pairs
     double2 *tw2, *tw2os, *twphi;  // e^{-2 pi i t / N}
     double2 *phase;    // [2 lmax+1] e^{-i n pi / n2} / (n2 hhat_theta(n))
     double *dphi;      // [lmax+1] 1 / hhat_phi(m)

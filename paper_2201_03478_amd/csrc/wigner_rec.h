@@ -18,17 +18,6 @@ __device__ __forceinline__ XN xn_norm(double v, int e) {
     return {mm, e + ee};
 }
 __device__ __forceinline__ XN xn_mul(XN a, XN b) { return xn_norm(a.m * b.m, a.e + b.e); }
-__device__ XN xn_pow(double x, int n) {
-    XN r = {0.5, 1};
-    XN b = xn_norm(x, 0);
-    while (n) {
-        if (n & 1) r = xn_mul(r, b);
-        b = xn_mul(b, b);
-        n >>= 1;
-    }
-    return r;
-}
-
 constexpr int REC_STEP = 1200;  // rescaling exponent step
 constexpr double REC_BIG = 0x1p600;
 // 2^-1200 is below the FP64 range, so rescaling divides by 2^1200 through the
@@ -40,18 +29,38 @@ __device__ __forceinline__ double rec_down(double v) { return ldexp(v, -REC_STEP
 // as a scaled FP64 value d and exponent step e <= 0 (true value d 2^{1200 e}):
 //   d^l_{l k} = (-1)^{l-k} sqrt(C(2l, l+k)) c^{l+k} s^{l-k}   (m >= k)
 //   d^l_{m l} =            sqrt(C(2l, l+m)) c^{l+m} s^{l-m}   (m <  k)
-// c = cos(theta/2), s = sin(theta/2); pref = sqrt(C(2 l0, l0 + min(m, k))).
-__device__ __forceinline__ void start_value(int j, int nring, int m, int k, XN pref, double &x, double &d, int &e) {
+// c = cos(theta/2), s = sin(theta/2).  It is formed in the log domain:
+//   log2 |d| = pe + pm + P log2 c + Q log2 s,   P = l0 + min(m, k), Q = l0 - min(m, k),
+// with sqrt(C(2 l0, l0 + min(m, k))) = 2^pe 2^pm (pe an integer, pm = log2 of its
+// mantissa), log2 c and log2 s given per ring as double-double pairs (rt[1..4]),
+// every product and sum carried with its rounding error (|log2 d| reaches 10^4
+// at lmax 1800), then one exp2 of the fractional part: relative error ~1e-15.
+// rt[0] = cos(theta_j).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void start_value(const double *__restrict__ rt, int m, int k, double pe, double pm,
+                                            double &x, double &d, int &e) {
     const int l0 = m > k ? m : k, mn = m < k ? m : k;
     const double sgn = (m >= k && ((m - k) & 1)) ? -1.0 : 1.0;
-    const double t = ((double)j + 0.5) / (double)nring;  // theta / pi
-    x = cospi(t);
-    const double ch = cospi(0.5 * t), sh = sinpi(0.5 * t);
-    XN v = xn_mul(xn_mul(xn_pow(ch, l0 + mn), xn_pow(sh, l0 - mn)), pref);
-    const int E = v.e;
+    x = rt[0];
+    const double P = (double)(l0 + mn), Q = (double)(l0 - mn);
+    const double p1 = P * rt[1], q1 = Q * rt[3];
+    const double p1e = fma(P, rt[1], -p1) + P * rt[2];
+    const double q1e = fma(Q, rt[3], -q1) + Q * rt[4];
+    double s, se, t, te;
+    two_sum(p1, q1, s, se);
+    two_sum(s, pe, t, te);
+    const double fl = floor(t);
+    const double f = (t - fl) + (((se + te) + (p1e + q1e)) + pm);  // t - fl is exact; |f| < 3
+    int de;
+    const double mant = frexp(exp2(f), &de);  // |d| = mant 2^E, mant in [0.5, 1)
+    const int E = (int)fl + de;
     const int es = (E + REC_STEP / 2 >= 0) ? 0 : -((-(E + REC_STEP / 2) + REC_STEP - 1) / REC_STEP);
     e = es;
-    d = sgn * ldexp(v.m, E - REC_STEP * es);
+    d = sgn * ldexp(mant, E - REC_STEP * es);
 }
 
 // Recursion coefficients for the step l -> l+1:
