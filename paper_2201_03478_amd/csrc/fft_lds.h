@@ -344,7 +344,7 @@ struct FftRun;
 
 template <int DIR, int NT, int PT>
 struct FftRun<DIR, NT, PT, FftGeneric> {
-    __device__ static void run(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
+    __device__ __forceinline__ static void run(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
         fft_lds<DIR, NT, PT>(buf, P, tw, tid, nth);
     }
 };
@@ -352,7 +352,7 @@ struct FftRun<DIR, NT, PT, FftGeneric> {
 template <int DIR, int NT, int PT, int N, int... Rs>
 struct FftRun<DIR, NT, PT, FftSpec<N, Rs...>> {
     static_assert(N <= NT * PT, "size class too small for the transform");
-    __device__ static void run(double2 *buf, const FftPlan &, const double2 *__restrict__ tw, int tid, int) {
+    __device__ __forceinline__ static void run(double2 *buf, const FftPlan &, const double2 *__restrict__ tw, int tid, int) {
         fft_passes_c<DIR, NT, N, 1, Rs...>(buf, tw, tid);
     }
 };
