@@ -40,16 +40,36 @@ __device__ __forceinline__ void anchor_of(const double *ptg, int64_t s, const Bi
     if (!(psi >= 0.0 && psi < two_pi)) psi = 0.0;
 }
 
+// Anchor key and rank within the key.  Consecutive samples of a scan mostly
+// share an anchor, so the ranks are reserved per run of equal keys in a wave
+// (one atomic add of the run length by the run's first lane) rather than per
+// sample; a key that appears in several runs gets disjoint ranges.  (Blocks are
+// whole waves; the valid lanes of the last wave are a prefix.)
 __global__ void k_bin_keys(const double *__restrict__ ptg, int64_t n, BinGeom g, int *__restrict__ key,
                            int *__restrict__ rank, int *__restrict__ count) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int r0, c0;
-    double fu, fv, psi;
-    anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
-    const int k = r0 * g.nkc + c0;
-    key[s] = k;
-    rank[s] = atomicAdd(&count[k], 1);
+    const bool valid = s < n;
+    int k = -1;
+    if (valid) {
+        int r0, c0;
+        double fu, fv, psi;
+        anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
+        k = r0 * g.nkc + c0;
+        key[s] = k;
+    }
+    const int lane = threadIdx.x & 63;
+    const int kprev = __shfl_up(k, 1);
+    const bool head = valid && (lane == 0 || kprev != k);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all ones at lane 63)
+    const int leader = 63 - __clzll(heads & upto);          // first lane of this lane's run
+    const unsigned long long above = heads & ~upto;
+    const int vend = 64 - __clzll(__ballot(valid));         // one past the last valid lane
+    const int next = above ? __ffsll((long long)above) - 1 : vend;
+    int base = 0;
+    if (head) base = atomicAdd(&count[k], next - lane);
+    base = __shfl(base, leader);
+    if (valid) rank[s] = base + (lane - leader);
 }
 
 // --- exclusive scan of int2 (x: samples per key, y: items per key) ------------
