@@ -11,8 +11,10 @@
 // length R1, constant twiddles e^{DIR 2 pi i n2 k1 / R}, R1 DFTs of length R2),
 // so the data crosses LDS once per pass, not once per prime factor.
 // DIR = -1 is the forward transform sum_j x_j e^{-2 pi i n j / N}, DIR = +1 the
-// unnormalised inverse.  Pass twiddles come from a table tw[t] = e^{-2 pi i t / N};
-// the first pass (Ns = 1) has unit twiddles and loads none.
+// unnormalised inverse.  Pass twiddles come from a pass-major table: the pass
+// with span Ns and twiddle step ts = N / (Ns R) finds e^{-2 pi i r k ts / N} at
+// (Ns - 1) + (r - 1) Ns + k, so a wave's lanes (consecutive k) read one
+// contiguous run; the first pass (Ns = 1) has unit twiddles and loads none.
 //
 // Size classes: NT threads per workgroup and at most PT points per thread
 // (N <= NT PT); a radix-R pass holds ceil(PT / R) butterflies per thread.
@@ -220,7 +222,7 @@ __device__ __forceinline__ void dft_small(double2 *v) {
 // One Stockham pass of radix R.
 
 template <int R, int DIR, int NT, int PT>
-__device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, int twstep, unsigned mag,
+__device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, unsigned mag,
                                                const double2 *__restrict__ tw, int tid, int nth) {
     constexpr int B = (PT + R - 1) / R;  // butterflies per thread: B NT >= N / R since N <= NT PT
     const int nb = N / R;
@@ -234,12 +236,12 @@ __device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, int 
             const int g = Ns > 1 ? (int)__umulhi((unsigned)j, mag) : j;
             const int k = j - g * Ns;
             widx[b] = g * Ns * R + k;
-            const int tk = k * twstep;
+            const double2 *twk = tw + (Ns - 1) + k;  // pass-major table: entry (r - 1) Ns
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 x = buf[j + r * nb];
                 if (r > 0 && Ns > 1) {
-                    double2 w = tw[r * tk];
+                    double2 w = twk[(r - 1) * Ns];
                     if (DIR > 0) w.y = -w.y;
                     x = cmul(x, w);
                 }
@@ -265,20 +267,20 @@ __device__ __forceinline__ void stockham_stage(double2 *buf, int N, int Ns, int 
 template <int DIR, int NT, int PT>
 __device__ void fft_lds(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
     for (int s = 0; s < P.nst; ++s) {
-        const int R = P.r[s], Ns = P.ns[s], ts = P.tws[s];
+        const int R = P.r[s], Ns = P.ns[s];
         const unsigned mg = P.mag[s];
         switch (R) {
-            case 2: stockham_stage<2, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 3: stockham_stage<3, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 4: stockham_stage<4, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 5: stockham_stage<5, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 6: stockham_stage<6, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 8: stockham_stage<8, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 9: stockham_stage<9, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 10: stockham_stage<10, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 12: stockham_stage<12, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            case 15: stockham_stage<15, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
-            default: stockham_stage<16, DIR, NT, PT>(buf, P.n, Ns, ts, mg, tw, tid, nth); break;
+            case 2: stockham_stage<2, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 3: stockham_stage<3, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 4: stockham_stage<4, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 5: stockham_stage<5, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 6: stockham_stage<6, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 8: stockham_stage<8, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 9: stockham_stage<9, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 10: stockham_stage<10, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 12: stockham_stage<12, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            case 15: stockham_stage<15, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
+            default: stockham_stage<16, DIR, NT, PT>(buf, P.n, Ns, mg, tw, tid, nth); break;
         }
     }
 }
@@ -298,7 +300,6 @@ template <int R, int DIR, int NT, int N, int NS>
 __device__ __forceinline__ void stockham_stage_c(double2 *buf, const double2 *__restrict__ tw, int tid) {
     constexpr int nb = N / R;
     constexpr int B = (nb + NT - 1) / NT;
-    constexpr int TWS = N / (NS * R);
     double2 v[B][R];
     int widx[B];
 #pragma unroll
@@ -307,12 +308,11 @@ __device__ __forceinline__ void stockham_stage_c(double2 *buf, const double2 *__
         if ((b + 1) * NT <= nb || j < nb) {
             const int g = j / NS, k = j - g * NS;
             widx[b] = g * NS * R + k;
-            const int tk = k * TWS;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 x = buf[j + r * nb];
                 if (NS > 1 && r > 0) {
-                    double2 w = tw[r * tk];
+                    double2 w = tw[(NS - 1) + (r - 1) * NS + k];  // pass-major table
                     if (DIR > 0) w.y = -w.y;
                     x = cmul(x, w);
                 }

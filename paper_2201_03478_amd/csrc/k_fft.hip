@@ -306,10 +306,10 @@ static hipError_t theta_adj(sc_plan *p) {
 
 // Compile-time plans for the transform lengths of lmax 256, 512 and 1024 (radices
 // chosen so each pass keeps most lanes of its waves busy, an odd radix first).
-using F540 = FftSpec<540, 9, 5, 12>;
-using F1080 = FftSpec<1080, 9, 12, 10>;
-using F2160 = FftSpec<2160, 15, 12, 12>;
-using F4320 = FftSpec<4320, 9, 5, 6, 16>;
+using F540 = FftSpec<540, SC_PLAN_540>;
+using F1080 = FftSpec<1080, SC_PLAN_1080>;
+using F2160 = FftSpec<2160, SC_PLAN_2160>;
+using F4320 = FftSpec<4320, SC_PLAN_4320>;
 
 hipError_t sc_launch_theta_upsample(sc_plan *p) {
     if (p->n2 == 540 && p->n2os == 1080) return theta_up<128, 9, F540, F1080>(p);

@@ -16,13 +16,27 @@
 
 namespace {
 
-__global__ void k_twiddles(double2 *tw, int n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) {
-        double s, c;
-        sincospi(-2.0 * (double)t / (double)n, &s, &c);
-        tw[t] = make_double2(c, s);
+// Pass-major twiddles of a plan: pass s (span NS = ns[s], radix R, twiddle step
+// tws[s]) holds e^{-2 pi i r k tws / N} for r = 1 .. R-1, k = 0 .. NS-1 at
+// (NS - 1) + (r - 1) NS + k, so the lanes of a pass (consecutive k) read
+// consecutive entries.  The passes' blocks fill [0, N - 1) exactly (their sizes
+// (R - 1) NS telescope to N - 1).
+__global__ void k_pass_twiddles(double2 *tw, FftPlan P) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.n) return;
+    double2 v = make_double2(1.0, 0.0);
+    for (int s = 0; s < P.nst; ++s) {
+        const int NS = P.ns[s], R = P.r[s];
+        const int local = e - (NS - 1);
+        if (local >= 0 && local < (R - 1) * NS) {
+            const int r = 1 + local / NS, k = local - (r - 1) * NS;
+            const long long t = (long long)r * k * P.tws[s];
+            double sn, cs;
+            sincospi(-2.0 * (double)t / (double)P.n, &sn, &cs);
+            v = make_double2(cs, sn);
+        }
     }
+    tw[e] = v;
 }
 
 __global__ void k_gauss_legendre(double *x, double *w, int nq) {
@@ -117,9 +131,9 @@ __global__ void k_sqrt_binom(double *sm, int *se, int lmax, int kmax) {
 
 hipError_t sc_launch_tables(sc_plan *p) {
     const int bs = 256;
-    hipLaunchKernelGGL(k_twiddles, dim3((p->n2 + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2, p->n2);
-    hipLaunchKernelGGL(k_twiddles, dim3((p->n2os + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2os, p->n2os);
-    hipLaunchKernelGGL(k_twiddles, dim3((p->nphi + bs - 1) / bs), dim3(bs), 0, p->stream, p->twphi, p->nphi);
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->n2 + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2, p->p2);
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->n2os + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2os, p->p2os);
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->nphi + bs - 1) / bs), dim3(bs), 0, p->stream, p->twphi, p->pphi);
     hipLaunchKernelGGL(k_gauss_legendre, dim3((p->nq + 63) / 64), dim3(64), 0, p->stream, p->glx, p->glw, p->nq);
     const int nt = 2 * p->lmax + 1;
     hipLaunchKernelGGL(k_deconv, dim3((nt + 63) / 64), dim3(64), 0, p->stream, p->phase, p->dphi, p->lmax, p->n2,

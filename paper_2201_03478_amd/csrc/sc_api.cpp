@@ -87,15 +87,23 @@ bool factor_fft(int n, FftPlan *P) {
     while (m % 3 == 0) { m /= 3; ++b; }
     while (m % 5 == 0) { m /= 5; ++c; }
     if (m != 1) return false;
-    int rad[SC_MAX_RADICES];
-    const int np = radix_passes(a, b, c, rad);
-    // Odd radices first: their strided writes (span 1, R1, ...) do not collide in
-    // LDS banks, and by the time the even radices run the span is large, where a
-    // pass reads and writes contiguous runs.
-    for (int i = 0; i < np; ++i)
-        if (rad[i] & 1) P->r[P->nst++] = rad[i];
-    for (int i = 0; i < np; ++i)
-        if (!(rad[i] & 1)) P->r[P->nst++] = rad[i];
+    static const int p540[] = {SC_PLAN_540}, p1080[] = {SC_PLAN_1080}, p2160[] = {SC_PLAN_2160},
+                     p4320[] = {SC_PLAN_4320};
+    const int *fixed = n == 540 ? p540 : n == 1080 ? p1080 : n == 2160 ? p2160 : n == 4320 ? p4320 : nullptr;
+    if (fixed) {
+        // the compile-time kernels' order
+        for (int prod = 1; prod < n; prod *= fixed[P->nst], ++P->nst) P->r[P->nst] = fixed[P->nst];
+    } else {
+        int rad[SC_MAX_RADICES];
+        const int np = radix_passes(a, b, c, rad);
+        // Odd radices first: their strided writes (span 1, R1, ...) do not collide in
+        // LDS banks, and by the time the even radices run the span is large, where a
+        // pass reads and writes contiguous runs.
+        for (int i = 0; i < np; ++i)
+            if (rad[i] & 1) P->r[P->nst++] = rad[i];
+        for (int i = 0; i < np; ++i)
+            if (!(rad[i] & 1)) P->r[P->nst++] = rad[i];
+    }
     int ns = 1;
     for (int s = 0; s < P->nst; ++s) {
         P->ns[s] = ns;

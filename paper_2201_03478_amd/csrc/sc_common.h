@@ -19,6 +19,13 @@
 // has radix r[s], span ns[s] = r[0] ... r[s-1] and twiddle stride
 // tws[s] = n / (ns[s] r[s]); mag[s] = ceil(2^32 / ns[s]) turns j / ns[s] into a
 // multiply-high (exact for j, ns < 2^16; unused when ns[s] = 1).
+// Radix orders of the transform lengths that have compile-time kernels; the host
+// plans use the same orders, so one pass-major twiddle table serves both.
+#define SC_PLAN_540 9, 5, 12
+#define SC_PLAN_1080 9, 12, 10
+#define SC_PLAN_2160 15, 12, 12
+#define SC_PLAN_4320 9, 5, 6, 16
+
 struct FftPlan {
     int n;
     int nst;
