@@ -34,6 +34,18 @@ __device__ inline void store_pair<float>(float *o, double a, double b) {
     *(float2 *)o = make_float2((float)a, (float)b);
 }
 
+// Two columns per workgroup.  Columns mi and mi + 1 (same k) have opposite
+// parities s1 = (-1)^{m-k} and s2 = -s1, and for an extended column with
+// f(n2 - 1 - j) = s f(j) the transform obeys X(-n) = s w^n X(n), w = e^{-2 pi i / n2}.
+// So one transform of h = f1 + i f2 gives both: with H = FFT(h),
+// X1 = (H(n) + s1 w^{-n} H(-n)) / 2 and X2 = (H(n) - s1 w^{-n} H(-n)) / (2 i).
+// The deconvolution factor is p(n) d(m), p(n) = e^{-i pi n / n2} q(|n|) with q real,
+// so p(n) w^{-n} = conj(p(n)), and the combined spectrum Y1 + i Y2 is
+//     Z(n) = a p(n) H(n) + b conj(p(n)) H(-n),  a = (d1 + d2) / 2,  b = s1 (d1 - d2) / 2.
+// The upsampled columns keep the parities, G_c(-r) = s_c G_c(r), so the inverse
+// transform of Z, O = G1 + i G2, separates as G1 = (O(r) + s1 O(-r)) / 2 and
+// G2 = (O(r) - s1 O(-r)) / (2 i) (the halves are folded into a and b).  For odd
+// nm the last column is alone (f2 = 0, d2 = d1 makes Z = d1 p H).
 template <int NT, int PT, typename S2, typename SOS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
@@ -42,20 +54,23 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
                  const double *__restrict__ dphi) {
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive m share an XCD
-    const int k = blk / nm;
-    const int mi = blk - k * nm;
+    const int npair = lmax + 1;  // ceil(nm / 2)
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive column pairs share an XCD
+    const int k = blk / npair;
+    const int mi = 2 * (blk - k * npair);
+    const bool two = mi + 1 < nm;
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
     double2 *B = sbuf;  // length nos; the forward transform runs in B[0 .. n2)
 
-    const double sg = ((m - k) & 1) ? -1.0 : 1.0;
+    const double s1 = ((m - k) & 1) ? -1.0 : 1.0;
     const double2 *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
-        double2 f = col[j];
-        B[j] = f;
-        B[n2 - 1 - j] = cscale(f, sg);
+        const double2 a = col[j];
+        const double2 b = two ? col[nring + j] : make_double2(0.0, 0.0);
+        B[j] = make_double2(a.x - b.y, a.y + b.x);                   // a + i b
+        B[n2 - 1 - j] = make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x));  // s1 (a - i b)
     }
     __syncthreads();
     FftRun<-1, NT, PT, S2>::run(B, P2, tw2, tid, nth);
@@ -65,14 +80,19 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     // everything in between becomes zero.  nm < n2 <= nos / 2 <= NT PT / 2, so
     // each thread holds at most ceil(PT / 2) coefficients.
     constexpr int MAXC = (PT + 1) / 2;
-    const double dm = dphi[m < 0 ? -m : m];
+    const double d1 = dphi[m < 0 ? -m : m];
+    const double d2 = two ? dphi[m + 1 < 0 ? -(m + 1) : m + 1] : d1;
+    const double ca = 0.25 * (d1 + d2), cb = 0.25 * s1 * (d1 - d2);
     double2 xs[MAXC];
 #pragma unroll
     for (int i = 0; i < MAXC; ++i) {
         const int t = tid + i * nth;
         if (t < nm) {
             const int n = t - lmax;
-            xs[i] = cscale(cmul(B[n < 0 ? n + n2 : n], phase[t]), dm);
+            const double2 p = phase[t];
+            const double2 hp = B[n < 0 ? n + n2 : n], hm = B[n > 0 ? n2 - n : -n];
+            const double2 u = cmul(p, hp), v = cmul(cconj(p), hm);
+            xs[i] = make_double2(ca * u.x + cb * v.x, ca * u.y + cb * v.y);
         }
     }
     __syncthreads();
@@ -88,11 +108,19 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     __syncthreads();
     FftRun<1, NT, PT, SOS>::run(B, Pos, twos, tid, nth);
 
+    // Lane pairs write the two columns of a row side by side (one 32-byte run).
     const int r0 = -W / 2 + 1;
-    for (int row = tid; row < rows; row += nth) {
+    double2 *gk = G + (size_t)k * rows * nm + mi;
+    for (int q = tid; q < 2 * rows; q += nth) {
+        const int row = q >> 1, c = q & 1;
+        if (c && !two) continue;
         int r = row + r0;
         r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
-        G[((size_t)k * rows + row) * nm + mi] = B[r];
+        const int rm = r == 0 ? 0 : nos - r;
+        const double2 o = B[r], om = B[rm];
+        const double2 g = c == 0 ? make_double2(o.x + s1 * om.x, o.y + s1 * om.y)
+                                 : make_double2(o.y - s1 * om.y, s1 * om.x - o.x);  // -i (o - s1 om)
+        gk[(size_t)row * nm + c] = g;
     }
 }
 
@@ -190,41 +218,71 @@ k_phi_adjoint(const T *__restrict__ gmaps, double2 *__restrict__ G, int lmax, in
     }
 }
 
-template <int NT, int PT>
-__global__ void __launch_bounds__(NT)
+// Two columns per workgroup, as in the forward kernel.  The forward output lies
+// in the s-symmetric sequences (G(-r) = s G(r)), so the adjoint only sees the
+// symmetric part of the row gradient: with A_c the gradient placed on the circle
+// (zero off the kept rows), h(r) = A_1(r) + s1 A_1(-r) + i (A_2(r) - s1 A_2(-r)) is
+// twice the combined symmetric input.  Its transform Y separates as in the forward
+// direction, giving the combined spectrum conj(p(n)) (a Y(n) + b Y(-n)) with the
+// forward kernel's a and b halved; the length-n2 inverse f keeps the parities, and
+// F_adj1(j) = f(j) + s1 f(n2 - 1 - j), F_adj2(j) = -i (f(j) - s1 f(n2 - 1 - j)).
+template <int NT, int PT, typename S2, typename SOS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax, int nring, int rows, int W,
                 FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2, const double2 *__restrict__ twos,
                 const double2 *__restrict__ phase, const double *__restrict__ dphi) {
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
+    const int npair = lmax + 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = blk / nm;
-    const int mi = blk - k * nm;
+    const int k = blk / npair;
+    const int mi = 2 * (blk - k * npair);
+    const bool two = mi + 1 < nm;
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
     double2 *B = sbuf;  // length nos; the length-n2 transform runs in B[0 .. n2)
-    for (int t = tid; t < nos; t += nth) B[t] = make_double2(0.0, 0.0);
-    __syncthreads();
+    const double s1 = ((m - k) & 1) ? -1.0 : 1.0;
     const int r0 = -W / 2 + 1;
-    for (int row = tid; row < rows; row += nth) {
-        int r = row + r0;
-        r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
-        B[r] = G[((size_t)k * rows + row) * nm + mi];  // rows land on distinct indices
+    const int rtop = r0 + rows - 1;  // last kept row index (< nos / 2 + W)
+    const double2 *gk = G + (size_t)k * rows * nm + mi;
+    const double2 zero = make_double2(0.0, 0.0);
+    for (int r = tid; r < nos; r += nth) {
+        // kept row at circle index r (row r - r0, or a ghost row r - nos - r0), and at -r
+        const int rm = r == 0 ? 0 : nos - r;
+        const int ra = r <= rtop ? r - r0 : (r - nos >= r0 ? r - nos - r0 : -1);
+        const int rb = rm <= rtop ? rm - r0 : (rm - nos >= r0 ? rm - nos - r0 : -1);
+        double2 a1 = zero, a2 = zero, b1 = zero, b2 = zero;
+        if (ra >= 0) {
+            a1 = gk[(size_t)ra * nm];
+            if (two) a2 = gk[(size_t)ra * nm + 1];
+        }
+        if (rb >= 0) {
+            b1 = gk[(size_t)rb * nm];
+            if (two) b2 = gk[(size_t)rb * nm + 1];
+        }
+        // (a1 + s1 b1) + i (a2 - s1 b2)
+        const double2 u = make_double2(a1.x + s1 * b1.x, a1.y + s1 * b1.y);
+        const double2 v = make_double2(a2.x - s1 * b2.x, a2.y - s1 * b2.y);
+        B[r] = make_double2(u.x - v.y, u.y + v.x);
     }
     __syncthreads();
-    fft_lds<-1, NT, PT>(B, Pos, twos, tid, nth);
+    FftRun<-1, NT, PT, SOS>::run(B, Pos, twos, tid, nth);
     // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from n + nos to
     // n + n2 (disjoint since nos >= n2 + lmax); the rest of [0, n2) becomes zero.
     constexpr int MAXC = (PT + 1) / 2;
-    const double dm = dphi[m < 0 ? -m : m];
+    const double d1 = dphi[m < 0 ? -m : m];
+    const double d2 = two ? dphi[m + 1 < 0 ? -(m + 1) : m + 1] : d1;
+    const double ca = 0.25 * (d1 + d2), cb = 0.25 * s1 * (d1 - d2);
     double2 xs[MAXC];
 #pragma unroll
     for (int i = 0; i < MAXC; ++i) {
         const int t = tid + i * nth;
         if (t < nm) {
             const int n = t - lmax;
-            xs[i] = cscale(cmul(cconj(phase[t]), B[n < 0 ? n + nos : n]), dm);
+            const double2 yp = B[n < 0 ? n + nos : n], ym = B[n > 0 ? nos - n : -n];
+            const double2 y = make_double2(ca * yp.x + cb * ym.x, ca * yp.y + cb * ym.y);
+            xs[i] = cmul(cconj(phase[t]), y);
         }
     }
     __syncthreads();
@@ -236,15 +294,14 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
             B[n < 0 ? n + n2 : n] = xs[i];
         }
     }
-    for (int t = lmax + 1 + tid; t < n2 - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
+    for (int t = lmax + 1 + tid; t < n2 - lmax; t += nth) B[t] = zero;
     __syncthreads();
-    fft_lds<1, NT, PT>(B, P2, tw2, tid, nth);
-    double2 *A = B;
-    const double sg = ((m - k) & 1) ? -1.0 : 1.0;
+    FftRun<1, NT, PT, S2>::run(B, P2, tw2, tid, nth);
     double2 *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
-        const double2 a = A[j], b = A[n2 - 1 - j];
-        col[j] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+        const double2 a = B[j], b = B[n2 - 1 - j];
+        col[j] = make_double2(a.x + s1 * b.x, a.y + s1 * b.y);
+        if (two) col[nring + j] = make_double2(a.y - s1 * b.y, s1 * b.x - a.x);  // -i (a - s1 b)
     }
 }
 
@@ -258,7 +315,7 @@ static inline int fft_class(int n) {
 
 template <int NT, int PT, typename S2 = FftGeneric, typename SOS = FftGeneric>
 static hipError_t theta_up(sc_plan *p) {
-    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
+    const int nblk = (p->kmax + 1) * (p->lmax + 1);  // column pairs
     const size_t lds = sizeof(double2) * (size_t)p->n2os;
     auto kern = k_theta_upsample<NT, PT, S2, SOS>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
@@ -292,11 +349,11 @@ static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
     return hipGetLastError();
 }
 
-template <int NT, int PT>
+template <int NT, int PT, typename S2 = FftGeneric, typename SOS = FftGeneric>
 static hipError_t theta_adj(sc_plan *p) {
-    const int nblk = (p->kmax + 1) * (2 * p->lmax + 1);
+    const int nblk = (p->kmax + 1) * (p->lmax + 1);  // column pairs
     const size_t lds = sizeof(double2) * (size_t)p->n2os;
-    auto kern = k_theta_adjoint<NT, PT>;
+    auto kern = k_theta_adjoint<NT, PT, S2, SOS>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, p->F, p->lmax, p->nring, p->rows, p->W,
@@ -352,6 +409,9 @@ hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {
 }
 
 hipError_t sc_launch_theta_adjoint(sc_plan *p) {
+    if (p->n2 == 540 && p->n2os == 1080) return theta_adj<128, 9, F540, F1080>(p);
+    if (p->n2 == 1080 && p->n2os == 2160) return theta_adj<SC_FFT_NT, SC_FFT_PT, F1080, F2160>(p);
+    if (p->n2 == 2160 && p->n2os == 4320) return theta_adj<SC_FFT_NT_BIG, SC_FFT_PT, F2160, F4320>(p);
     switch (fft_class(p->n2os)) {
         case 0: return theta_adj<SC_FFT_NT, SC_FFT_PT>(p);
         case 1: return theta_adj<SC_FFT_NT_BIG, SC_FFT_PT>(p);

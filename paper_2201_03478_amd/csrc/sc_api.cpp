@@ -312,6 +312,8 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->n2 = next_smooth(2 * lmax + 2, true);
     p->nring = p->n2 / 2;
     p->n2os = next_smooth(2 * p->n2, true);
+    // every kept row (n2os / 2 + W of them) on its own grid index
+    if (p->n2os < 2 * W) p->n2os = next_smooth(2 * W, true);
     p->nphi = next_smooth(2 * (2 * lmax + 1), false);
     if (p->nphi < 2 * W) p->nphi = next_smooth(2 * W, false);
     p->rows = p->n2os / 2 + W;
