@@ -339,6 +339,16 @@ __device__ __forceinline__ void fft_passes_c(double2 *buf, const double2 *__rest
     if constexpr (sizeof...(Rest) > 0) fft_passes_c<DIR, NT, N, NS * R, Rest...>(buf, tw, tid);
 }
 
+// Length of a compile-time transform, 0 for the runtime-planned one.
+template <typename S>
+struct FftLen {
+    static constexpr int value = 0;
+};
+template <int N, int... Rs>
+struct FftLen<FftSpec<N, Rs...>> {
+    static constexpr int value = N;
+};
+
 template <int DIR, int NT, int PT, typename S>
 struct FftRun;
 

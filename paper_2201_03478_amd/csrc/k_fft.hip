@@ -34,6 +34,19 @@ __device__ inline void store_pair<float>(float *o, double a, double b) {
     *(float2 *)o = make_float2((float)a, (float)b);
 }
 
+// two adjacent component pairs as one aligned 16-byte store (FP32 maps)
+template <typename T>
+__device__ inline void store_quad(T *o, T a, T b, T c, T d);
+template <>
+__device__ inline void store_quad<float>(float *o, float a, float b, float c, float d) {
+    *(float4 *)o = make_float4(a, b, c, d);
+}
+template <>
+__device__ inline void store_quad<double>(double *o, double a, double b, double c, double d) {
+    ((double2 *)o)[0] = make_double2(a, b);
+    ((double2 *)o)[1] = make_double2(c, d);
+}
+
 // Two columns per workgroup.  Columns mi and mi + 1 (same k) have opposite
 // parities s1 = (-1)^{m-k} and s2 = -s1, and for an extended column with
 // f(n2 - 1 - j) = s f(j) the transform obeys X(-n) = s w^n X(n), w = e^{-2 pi i / n2}.
@@ -124,41 +137,103 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
 }
 
-template <typename T, int NT, int PT, typename SP>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
-k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
-                int W, FftPlan Pp, const double2 *__restrict__ twp) {
-    extern __shared__ double2 sbuf[];
-    const int nm = 2 * lmax + 1;
-    const int nk = gridDim.x / rows;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive k of one row share an XCD
-    const int row = blk / nk;
-    const int k = blk - row * nk;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int np = Pp.n;
-    double2 *A = sbuf;
-    for (int t = tid; t < np; t += nth) A[t] = make_double2(0.0, 0.0);
-    __syncthreads();
-    const double2 *src = G + ((size_t)k * rows + row) * nm;
-    for (int t = tid; t < nm; t += nth) {
-        const int m = t - lmax;
-        A[m < 0 ? m + np : m] = src[t];
-    }
-    __syncthreads();
-    FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
+// Map values of one k at one column, (M_{2k}, M_{2k+1}) = (2 Re T_k, -2 Im T_k) or (Re T_0, 0).
+__device__ __forceinline__ double2 phi_pair(double2 v, int k) {
+    return k == 0 ? make_double2(v.x, 0.0) : make_double2(2.0 * v.x, -2.0 * v.y);
+}
 
-    const int q0 = -W / 2 + 1;
-    T *dst = maps + (size_t)row * cols * ncp;
-    for (int col = tid; col < cols; col += nth) {
-        int q = col + q0;
-        q = q < 0 ? q + np : (q >= np ? q - np : q);
-        const double2 v = A[q];
-        // one aligned pair store per column: (M_{2k}, M_{2k+1}) = (2 Re T_k, -2 Im T_k), (Re T_0, 0)
-        const double s = k == 0 ? 1.0 : 2.0;
-        store_pair<T>(dst + (size_t)col * ncp + 2 * k, s * v.x, k == 0 ? 0.0 : -s * v.y);
+// G row (nm spectral values) into registers; lanes past nm read a valid duplicate,
+// which phi_scatter replaces by zero.
+template <int NT, int MAXC>
+__device__ __forceinline__ void phi_load(double2 (&spec)[MAXC], const double2 *__restrict__ src, int tid, int nm) {
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * NT;
+        spec[i] = src[t < nm ? t : nm - 1];
     }
 }
 
+// Zero-padded spectrum in A: m >= 0 at m, m < 0 at m + np, zeros in between (lanes
+// past nm write a zero into that band too).
+template <int NT, int MAXC>
+__device__ __forceinline__ void phi_scatter(double2 *A, const double2 (&spec)[MAXC], int tid, int lmax, int np) {
+    const int nm = 2 * lmax + 1;
+    for (int t = lmax + 1 + tid; t < np - lmax; t += NT) A[t] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+        const int t = tid + i * NT;
+        const int m = t - lmax;
+        const bool in = t < nm;
+        const double2 v = spec[i];
+        A[in ? (m < 0 ? m + np : m) : lmax + 1] = make_double2(in ? v.x : 0.0, in ? v.y : 0.0);
+    }
+}
+
+// One workgroup per (row, group of KP = 1 or 2 consecutive k).  With KP = 2 the two
+// transforms run one after the other in one LDS buffer: the second k's spectrum is
+// loaded into registers while the first is transformed, and the first k's columns
+// wait in registers, so each lane writes both k's component pairs of a column as
+// one 16-byte store (a column's map record is contiguous in k).
+template <typename T, int NT, int PT, typename SP, int KP>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
+                int W, int nk, FftPlan Pp, const double2 *__restrict__ twp) {
+    static_assert(KP == 1 || KP == 2, "one or two k per workgroup");
+    extern __shared__ double2 sbuf[];
+    const int nm = 2 * lmax + 1;
+    const int ngrp = (nk + KP - 1) / KP;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // consecutive k groups of one row share an XCD
+    const int row = blk / ngrp;
+    const int k0 = (blk - row * ngrp) * KP;
+    const bool two = KP == 2 && k0 + 1 < nk;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int np = Pp.n;
+    double2 *A = sbuf;
+    constexpr int NP = FftLen<SP>::value;  // 0: runtime-planned transform
+    constexpr int MAXC = (PT + 1) / 2;                            // nm <= NT MAXC
+    constexpr int MAXS = NP > 0 ? (NP + 15 + NT - 1) / NT : PT + 1;  // cols <= np + 15 <= NT MAXS
+    const int q0 = -W / 2 + 1;
+    const double2 *src = G + ((size_t)k0 * rows + row) * nm;
+    T *dst = maps + (size_t)row * cols * ncp + 2 * k0;
+    double2 spec[MAXC];
+    phi_load<NT, MAXC>(spec, src, tid, nm);
+    phi_scatter<NT, MAXC>(A, spec, tid, lmax, np);
+    __syncthreads();
+    T stage[KP == 2 ? MAXS : 1][2];
+    if (two) {
+        phi_load<NT, MAXC>(spec, src + (size_t)rows * nm, tid, nm);
+        FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            int col = tid + i * NT;
+            col = col < cols ? col : cols - 1;
+            int q = col + q0;
+            q = q < 0 ? q + np : (q >= np ? q - np : q);
+            const double2 v = phi_pair(A[q], k0);
+            stage[KP == 2 ? i : 0][0] = (T)v.x;
+            stage[KP == 2 ? i : 0][1] = (T)v.y;
+        }
+        __syncthreads();
+        phi_scatter<NT, MAXC>(A, spec, tid, lmax, np);
+        __syncthreads();
+    }
+    FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
+    const int k = two ? k0 + 1 : k0;
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        const int col = tid + i * NT;
+        if (col < cols) {
+            int q = col + q0;
+            q = q < 0 ? q + np : (q >= np ? q - np : q);
+            const double2 v = phi_pair(A[q], k);
+            T *o = dst + (size_t)col * ncp;
+            if (two)
+                store_quad<T>(o, stage[KP == 2 ? i : 0][0], stage[KP == 2 ? i : 0][1], (T)v.x, (T)v.y);
+            else
+                store_pair<T>(o, v.x, v.y);
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Adjoints of the two transform stages (for the gradient with respect to the
@@ -327,13 +402,17 @@ static hipError_t theta_up(sc_plan *p) {
 
 template <typename T, int NT, int PT, typename SP = FftGeneric>
 static hipError_t phi_syn(sc_plan *p) {
-    const int nblk = (p->kmax + 1) * p->rows;
+    // FP32 maps with a compile-time transform: two k per workgroup (16-byte stores);
+    // FP64 maps store 16 bytes per k already
+    constexpr int KP = sizeof(T) == 4 && FftLen<SP>::value > 0 ? 2 : 1;
+    const int nk = p->kmax + 1;
+    const int nblk = (nk + KP - 1) / KP * p->rows;
     const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    auto kern = k_phi_synthesis<T, NT, PT, SP>;
+    auto kern = k_phi_synthesis<T, NT, PT, SP, KP>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
-                       p->rows, p->cols, p->ncp, p->W, p->pphi, p->twphi);
+                       p->rows, p->cols, p->ncp, p->W, nk, p->pphi, p->twphi);
     return hipGetLastError();
 }
 
