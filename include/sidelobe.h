@@ -160,7 +160,11 @@ int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, con
  * the caller's device memory.  which = 0: ring sums F (complex128
  * [kmax+1][2 lmax+1][n_rings], F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j),
  * theta_j = (j + 1/2) pi / n_rings); which = 1: the component maps as stored
- * (map_rows x map_cols x n_comp_padded, FP64 or FP32 by precision).
+ * (map_rows x map_cols x n_comp_padded, FP64 or FP32 by precision);
+ * which = 2: the sample order of the most recent binning pass (int32, one entry
+ * per sample of that pass: the index, within the pass, of the sample at each
+ * position when the samples are grouped by interpolation anchor; SC_ESTATE if
+ * no binned interpolation has run).
  * Returns the number of bytes copied, or a negative code.
  */
 int64_t sc_debug_copy_stage(sc_plan *plan, int which, void *dst, int64_t capacity_bytes);

@@ -151,12 +151,15 @@ class Plan:
         N.check(self._lib.sc_plan_stage_times(self._p, ms, cnt, ns), "sc_plan_stage_times")
         return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
 
-    def debug_stage(self, which: int) -> torch.Tensor:
+    def debug_stage(self, which: int, n: int = 0) -> torch.Tensor:
         """Copy of an internal stage: 0 = ring sums F (complex128 [kmax+1, 2 lmax+1, n_rings]),
-        1 = the stored component maps ([map_rows, map_cols, n_comp_padded])."""
+        1 = the stored component maps ([map_rows, map_cols, n_comp_padded]),
+        2 = the anchor-grouped sample order of the last binning pass (int32 [n], n its samples)."""
         inf = self.info()
         dev = torch.device("cuda", torch.cuda.current_device())
-        if which == 0:
+        if which == 2:
+            t = torch.empty(n, dtype=torch.int32, device=dev)
+        elif which == 0:
             t = torch.empty((self.kmax + 1, 2 * self.lmax + 1, inf["n_rings"]), dtype=torch.complex128, device=dev)
         else:
             dt = torch.float64 if self.precision == N.SC_FP64 else torch.float32

@@ -6,7 +6,8 @@
 // block of the component maps.  A counting sort groups the samples by anchor
 // so that the gather can stage one block in LDS and reuse it for all of them:
 //
-//   k_bin_keys     anchor key and rank within the key (atomic counter) per sample
+//   k_bin_keys     anchor key and rank within the key per sample (counts
+//                  aggregated per workgroup in LDS, one global atomic per key)
 //   k_scan_*       exclusive scan of (samples, work items) per key
 //   k_bin_scatter  samples in key order: fractional offsets and psi (FP64)
 //                  and the original index
@@ -40,36 +41,76 @@ __device__ __forceinline__ void anchor_of(const double *ptg, int64_t s, const Bi
     if (!(psi >= 0.0 && psi < two_pi)) psi = 0.0;
 }
 
-// Anchor key and rank within the key.  Consecutive samples of a scan mostly
-// share an anchor, so the ranks are reserved per run of equal keys in a wave
-// (one atomic add of the run length by the run's first lane) rather than per
-// sample; a key that appears in several runs gets disjoint ranges.  (Blocks are
-// whole waves; the valid lanes of the last wave are a prefix.)
-__global__ void k_bin_keys(const double *__restrict__ ptg, int64_t n, BinGeom g, int *__restrict__ key,
-                           int *__restrict__ rank, int *__restrict__ count) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = s < n;
-    int k = -1;
-    if (valid) {
-        int r0, c0;
-        double fu, fv, psi;
-        anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
-        k = r0 * g.nkc + c0;
-        key[s] = k;
+// Anchor key and rank within the key.  A scan crosses about one anchor cell per
+// sample but retraces nearly the same cells on consecutive spin circles, so a
+// workgroup's span of consecutive samples hits each of its keys several times.
+// The workgroup counts its keys in an LDS hash table (local ranks from LDS
+// atomics), then reserves one global range per distinct key (one global atomic
+// per key instead of per sample): rank = global base + local rank.  Keys that find
+// no free slot within the probe limit take a global rank directly.  Ranges of
+// different workgroups, and direct ranks, are disjoint by construction.
+constexpr int KEYS_NT = 1024;        // threads per workgroup
+constexpr int KEYS_SPT = 16;         // samples per thread (a span of 16384 samples)
+constexpr int KEYS_HT = 4096;        // hash slots
+constexpr int KEYS_PROBE = 64;       // linear-probe limit
+constexpr int KEYS_EMPTY = -1;
+
+__global__ void __launch_bounds__(KEYS_NT) k_bin_keys(const double *__restrict__ ptg, int64_t n, BinGeom g,
+                                                      int *__restrict__ key, int *__restrict__ rank,
+                                                      int *__restrict__ count) {
+    __shared__ int hkey[KEYS_HT];
+    __shared__ int hcnt[KEYS_HT];  // local count, then the key's global base
+    const int tid = threadIdx.x;
+    for (int i = tid; i < KEYS_HT; i += KEYS_NT) {
+        hkey[i] = KEYS_EMPTY;
+        hcnt[i] = 0;
     }
-    const int lane = threadIdx.x & 63;
-    const int kprev = __shfl_up(k, 1);
-    const bool head = valid && (lane == 0 || kprev != k);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all ones at lane 63)
-    const int leader = 63 - __clzll(heads & upto);          // first lane of this lane's run
-    const unsigned long long above = heads & ~upto;
-    const int vend = 64 - __clzll(__ballot(valid));         // one past the last valid lane
-    const int next = above ? __ffsll((long long)above) - 1 : vend;
-    int base = 0;
-    if (head) base = atomicAdd(&count[k], next - lane);
-    base = __shfl(base, leader);
-    if (valid) rank[s] = base + (lane - leader);
+    __syncthreads();
+    const int64_t s0 = (int64_t)blockIdx.x * (KEYS_NT * KEYS_SPT);
+    int kk[KEYS_SPT], slot[KEYS_SPT], lr[KEYS_SPT];
+#pragma unroll
+    for (int i = 0; i < KEYS_SPT; ++i) {  // all keys first: the pointing loads overlap
+        const int64_t s = s0 + tid + (int64_t)i * KEYS_NT;
+        kk[i] = -1;
+        if (s < n) {
+            int r0, c0;
+            double fu, fv, psi;
+            anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
+            kk[i] = r0 * g.nkc + c0;
+            key[s] = kk[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < KEYS_SPT; ++i) {
+        const int k = kk[i];
+        slot[i] = -1;
+        lr[i] = 0;
+        if (k >= 0) {
+            int h = (int)(((unsigned)k * 2654435761u) >> 20) & (KEYS_HT - 1);
+            for (int q = 0; q < KEYS_PROBE; ++q) {
+                int cur = hkey[h];
+                if (cur == KEYS_EMPTY) cur = atomicCAS(&hkey[h], KEYS_EMPTY, k);
+                if (cur == KEYS_EMPTY || cur == k) {
+                    slot[i] = h;
+                    lr[i] = atomicAdd(&hcnt[h], 1);
+                    break;
+                }
+                h = (h + 1) & (KEYS_HT - 1);
+            }
+            if (slot[i] < 0) lr[i] = atomicAdd(&count[k], 1);  // table full along the probe path
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < KEYS_HT; i += KEYS_NT) {
+        const int k = hkey[i];
+        if (k != KEYS_EMPTY) hcnt[i] = atomicAdd(&count[k], hcnt[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KEYS_SPT; ++i) {
+        const int64_t s = s0 + tid + (int64_t)i * KEYS_NT;
+        if (s < n) rank[s] = slot[i] >= 0 ? hcnt[slot[i]] + lr[i] : lr[i];
+    }
 }
 
 // --- exclusive scan of int2 (x: samples per key, y: items per key) ------------
@@ -210,12 +251,14 @@ hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream) {
 
 hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
     BinWork &w = p->bw;
+    w.last_n = n;
     const BinGeom g = sc_bin_geom(p);
     const int64_t nkeys = (int64_t)g.nkr * g.nkc;
     const int bs = 256;
     const unsigned gs = (unsigned)((n + bs - 1) / bs);
     hipLaunchKernelGGL(k_fill_int, dim3(1024), dim3(256), 0, p->stream, w.count, nkeys, 0);
-    hipLaunchKernelGGL(k_bin_keys, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.count);
+    const unsigned gk = (unsigned)((n + KEYS_NT * KEYS_SPT - 1) / (KEYS_NT * KEYS_SPT));
+    hipLaunchKernelGGL(k_bin_keys, dim3(gk), dim3(KEYS_NT), 0, p->stream, ptg, n, g, w.key, w.rank, w.count);
     const int nblk = (int)((nkeys + SCAN_BLOCK - 1) / SCAN_BLOCK);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, p->bin_chunk);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, p->stream, w.sums, nblk, w.totals);

@@ -664,6 +664,10 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
     } else if (which == 1) {
         src = p->maps;
         bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
+    } else if (which == 2) {
+        if (!p->bw.sorted.idx) return fail(SC_ESTATE, "no binning pass has run on this plan");
+        src = p->bw.sorted.idx;
+        bytes = sizeof(int) * (size_t)p->bw.last_n;
     } else {
         return fail(SC_EINVAL, "unknown stage %d", which);
     }

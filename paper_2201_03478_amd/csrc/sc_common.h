@@ -77,6 +77,7 @@ struct BinWork {
     int *key, *rank;  // [cap]
     BinSorted sorted; // [cap]
     int4 *items;      // [cap] (key, first sorted sample, count, -)
+    int64_t last_n;   // samples of the most recent binning pass
     size_t bytes;
 };
 

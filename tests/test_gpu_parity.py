@@ -132,6 +132,28 @@ def test_end_to_end_sidelobe_workload_sampled(torch_dev, api, oracle_lib):
     assert e <= 1e-6
 
 
+@pytest.mark.parametrize("L,kind,n", [(64, "scan", 2_000_000), (512, "scan", 2_000_000),
+                                       (64, "uniform", 300_000), (64, "uniform", 777)])
+def test_binning_keeps_every_sample_once(torch_dev, api, L, kind, n):
+    """The anchor-grouped order of a binning pass is a permutation of its samples.
+
+    Scan pointings revisit their anchors on consecutive spin circles (ranks come
+    from the per-workgroup LDS tables); uniform pointings at lmax 64 overflow those
+    tables (direct global ranks); 777 samples leave most lanes of the only
+    workgroup empty."""
+    torch, dev = torch_dev
+    a, b = _inputs(L, 4, 11)
+    plan = api.Plan(L, 4)
+    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    if kind == "scan":
+        ptg = W.scan_pointings(n, device=dev)
+    else:
+        ptg = _to(torch, dev, W.uniform_pointings(n, W.config_seed(9, n % 97)))
+    plan.interpolate(ptg)
+    order = plan.debug_stage(2, n).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(n, dtype=np.int32))
+
+
 def test_zero_samples_and_errors(torch_dev, api):
     torch, dev = torch_dev
     from paper_2201_03478_amd import _native as N
