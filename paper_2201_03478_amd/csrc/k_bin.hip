@@ -9,8 +9,8 @@
 //   k_bin_keys     anchor key and rank within the key per sample (counts
 //                  aggregated per workgroup in LDS, one global atomic per key)
 //   k_scan_*       exclusive scan of (samples, work items) per key
-//   k_bin_scatter  samples in key order: fractional offsets and psi (FP64)
-//                  and the original index
+//   k_bin_scatter  sample records in key order: fractional offsets and psi
+//                  (FP64) and the original index, 32 bytes each
 //   k_bin_items    work items (key, first sorted sample, count <= the plan's bin chunk)
 //
 // Integer index arithmetic is exact; the fractional offsets u - floor(u) are
@@ -201,18 +201,37 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int *__restrict__ 
     }
 }
 
+// Sample records in anchor order.  Lane pairs write the two 16-byte halves of one
+// record in the same instruction (one 32-byte run per sample, not four partial
+// writes); the values come from the sample's own lane by shuffles.  (Blocks are
+// whole waves.)
 __global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom g, const int *__restrict__ key,
                               const int *__restrict__ rank, const int2 *__restrict__ offs, BinSorted out) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int r0, c0;
-    double fu, fv, psi;
-    anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
-    const int pos = offs[key[s]].x + rank[s];
-    out.fu[pos] = fu;
-    out.fv[pos] = fv;
-    out.psi[pos] = psi;
-    out.idx[pos] = (int)s;
+    const bool valid = s < n;
+    int pos = -1;
+    double fu = 0.0, fv = 0.0, psi = 0.0;
+    if (valid) {
+        int r0, c0;
+        anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
+        pos = offs[key[s]].x + rank[s];
+    }
+    const int lane = threadIdx.x & 63;
+    const int hi = lane & 1;
+    double2 *rec2 = (double2 *)out.rec;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int src = (lane >> 1) + 32 * half;  // the wave lane whose sample this lane writes
+        const int p = __shfl(pos, src);
+        const double su = __shfl(fu, src), sv = __shfl(fv, src), sp = __shfl(psi, src);
+        const int64_t sidx = s - lane + src;
+        if (p >= 0) {
+            // low half (fu, fv); high half (psi, idx in the low word and pad 0)
+            const double2 v = hi ? make_double2(sp, __longlong_as_double((long long)(unsigned)sidx))
+                                 : make_double2(su, sv);
+            rec2[2 * (size_t)p + hi] = v;
+        }
+    }
 }
 
 __global__ void k_bin_items(const int *__restrict__ count, const int2 *__restrict__ offs, int64_t nkeys,

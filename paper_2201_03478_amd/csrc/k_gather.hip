@@ -143,7 +143,7 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 const int q = e >> 6, sl = e & 63;
                 T w = (T)0;
                 if (sl < ns) {
-                    const T f = (q < 8) ? (T)srt.fu[pos0 + sl] : (T)srt.fv[pos0 + sl];
+                    const T f = (q < 8) ? (T)srt.rec[pos0 + sl].fu : (T)srt.rec[pos0 + sl].fv;
                     const T z = (f + (T)(3 - (q & 7))) * (T)0.25;  // (x - node) / (W/2)
                     w = es_weight<T>(z, tbeta);
                 }
@@ -153,8 +153,8 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 double ps = 0.0;
                 int ix = -1;
                 if (tid < ns) {
-                    ps = srt.psi[pos0 + tid];
-                    ix = srt.idx[pos0 + tid];
+                    ps = srt.rec[pos0 + tid].psi;
+                    ix = srt.rec[pos0 + tid].idx;
                 }
                 double sn, cs;
                 sincos(ps, &sn, &cs);
@@ -356,12 +356,12 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
     {
         const int ns0 = item.z < GCH ? item.z : GCH;
         if (sw < ns0) {
-            pf_u = D.srt.fu[item.y + sw];
-            pf_v = D.srt.fv[item.y + sw];
+            pf_u = D.srt.rec[item.y + sw].fu;
+            pf_v = D.srt.rec[item.y + sw].fv;
         }
         if (tid < ns0) {
-            pf_psi = D.srt.psi[item.y + tid];
-            pf_idx = D.srt.idx[item.y + tid];
+            pf_psi = D.srt.rec[item.y + tid].psi;
+            pf_idx = D.srt.rec[item.y + tid].idx;
         }
     }
     {
@@ -396,12 +396,12 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             const int nxt = ch + GCH;
             const int nns = item.z - nxt < GCH ? item.z - nxt : GCH;  // <= 0 past the last chunk
             if (sw < nns) {
-                pf_u = D.srt.fu[item.y + nxt + sw];
-                pf_v = D.srt.fv[item.y + nxt + sw];
+                pf_u = D.srt.rec[item.y + nxt + sw].fu;
+                pf_v = D.srt.rec[item.y + nxt + sw].fv;
             }
             if (tid < nns) {
-                pf_psi = D.srt.psi[item.y + nxt + tid];
-                pf_idx = D.srt.idx[item.y + nxt + tid];
+                pf_psi = D.srt.rec[item.y + nxt + tid].psi;
+                pf_idx = D.srt.rec[item.y + nxt + tid].idx;
             }
         }
 
@@ -541,12 +541,12 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
     {
         const int ns0 = item.z < GCH ? item.z : GCH;
         if (sw < ns0) {
-            pf_u = D.srt.fu[item.y + sw];
-            pf_v = D.srt.fv[item.y + sw];
+            pf_u = D.srt.rec[item.y + sw].fu;
+            pf_v = D.srt.rec[item.y + sw].fv;
         }
         if (tid < ns0) {
-            pf_psi = D.srt.psi[item.y + tid];
-            pf_idx = D.srt.idx[item.y + tid];
+            pf_psi = D.srt.rec[item.y + tid].psi;
+            pf_idx = D.srt.rec[item.y + tid].idx;
         }
     }
     float oscale;
@@ -623,12 +623,12 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
             const int nxt = ch + GCH;
             const int nns = item.z - nxt < GCH ? item.z - nxt : GCH;
             if (sw < nns) {
-                pf_u = D.srt.fu[item.y + nxt + sw];
-                pf_v = D.srt.fv[item.y + nxt + sw];
+                pf_u = D.srt.rec[item.y + nxt + sw].fu;
+                pf_v = D.srt.rec[item.y + nxt + sw].fv;
             }
             if (tid < nns) {
-                pf_psi = D.srt.psi[item.y + nxt + tid];
-                pf_idx = D.srt.idx[item.y + nxt + tid];
+                pf_psi = D.srt.rec[item.y + nxt + tid].psi;
+                pf_idx = D.srt.rec[item.y + nxt + tid].idx;
             }
         }
 

@@ -128,7 +128,7 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
                 const int q = e >> 6, sl = e & 63;
                 float w = 0.f;
                 if (sl < ns) {
-                    const float f = (q < 8) ? (float)srt.fu[pos0 + sl] : (float)srt.fv[pos0 + sl];
+                    const float f = (q < 8) ? (float)srt.rec[pos0 + sl].fu : (float)srt.rec[pos0 + sl].fv;
                     w = es_w<float>((f + (float)(3 - (q & 7))) * 0.25f, fbeta);
                 }
                 W1[e] = w;
@@ -137,8 +137,8 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
                 double ps = 0.0;
                 float yy = 0.f;
                 if (tid < ns) {
-                    ps = srt.psi[pos0 + tid];
-                    yy = y[srt.idx[pos0 + tid]];
+                    ps = srt.rec[pos0 + tid].psi;
+                    yy = y[srt.rec[pos0 + tid].idx];
                 }
                 double sn, cs;
                 sincos(ps, &sn, &cs);

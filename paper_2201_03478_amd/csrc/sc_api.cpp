@@ -139,8 +139,7 @@ void timing_end(sc_plan *p, int slot) {
 }
 
 void free_bin_work(BinWork &w) {
-    void *bufs[] = {w.count, w.offs, w.sums, w.totals, w.key, w.rank, w.sorted.fu, w.sorted.fv,
-                    w.sorted.psi, w.sorted.idx, w.items};
+    void *bufs[] = {w.count, w.offs, w.sums, w.totals, w.key, w.rank, w.sorted.rec, w.items};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     std::memset(&w, 0, sizeof(w));
@@ -171,10 +170,7 @@ int ensure_bin_work(sc_plan *p, int64_t need) {
     rc = rc ? rc : alloc((void **)&w.totals, sizeof(int) * 4, &tot);
     rc = rc ? rc : alloc((void **)&w.key, sizeof(int) * need, &tot);
     rc = rc ? rc : alloc((void **)&w.rank, sizeof(int) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.sorted.fu, sizeof(double) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.sorted.fv, sizeof(double) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.sorted.psi, sizeof(double) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.sorted.idx, sizeof(int) * need, &tot);
+    rc = rc ? rc : alloc((void **)&w.sorted.rec, sizeof(BinRec) * need, &tot);
     rc = rc ? rc : alloc((void **)&w.items, sizeof(int4) * need, &tot);
     if (rc) {
         free_bin_work(w);
@@ -665,9 +661,16 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
         src = p->maps;
         bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
     } else if (which == 2) {
-        if (!p->bw.sorted.idx) return fail(SC_ESTATE, "no binning pass has run on this plan");
-        src = p->bw.sorted.idx;
-        bytes = sizeof(int) * (size_t)p->bw.last_n;
+        // the index field of each 32-byte sample record
+        if (!p->bw.sorted.rec) return fail(SC_ESTATE, "no binning pass has run on this plan");
+        const size_t nb = sizeof(int) * (size_t)p->bw.last_n;
+        if ((int64_t)nb > capacity) return fail(SC_EINVAL, "destination holds %lld bytes, need %zu",
+                                                (long long)capacity, nb);
+        if (nb == 0) return 0;
+        hipError_t e = hipMemcpy2DAsync(dst, sizeof(int), &p->bw.sorted.rec[0].idx, sizeof(BinRec), sizeof(int),
+                                        (size_t)p->bw.last_n, hipMemcpyDeviceToDevice, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "stage copy");
+        return (int64_t)nb;
     } else {
         return fail(SC_EINVAL, "unknown stage %d", which);
     }

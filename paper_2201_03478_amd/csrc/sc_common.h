@@ -47,10 +47,14 @@ struct BinGeom {
 };
 
 // Samples in anchor order (structure of arrays).
+// One binned sample, 32 bytes: u - floor(u) and v - floor(v) in grid units, psi
+// reduced to [0, 2 pi), and the index of the sample within its pass.
+struct __attribute__((aligned(32))) BinRec {
+    double fu, fv, psi;
+    int idx, pad;
+};
 struct BinSorted {
-    double *fu, *fv;  // u - floor(u), v - floor(v) in grid units
-    double *psi;     // psi reduced to [0, 2 pi)
-    int *idx;        // index of the sample within its pass
+    BinRec *rec;  // in anchor order
 };
 
 // One detector's inputs to the persistent (batched) FP32 gather.
