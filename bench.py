@@ -8,9 +8,10 @@ every pointing of a 1e7-sample synthetic scan.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--precision f64maps_f32gather|fp64]
 
-Per-kernel durations come from HIP events the library records on its stream
+Per-kernel durations come from HIP events the library records on its streams
 around each launch during the timed steps; the roofline object uses the
-dominant kernel.  The CPU baseline is the oracle (direct sum of Eq. 2) timed on
+dominant kernel of the plan's own stream (the pointing binning runs beside the
+map synthesis on a side stream).  The CPU baseline is the oracle (direct sum of Eq. 2) timed on
 a bounded random sample of the same pointings; its outputs also give the GPU
 result's error.
 """
@@ -110,8 +111,8 @@ def run_form(torch, api, dev, a, b, ptg, L, K, precision, width, steps, warmup):
     tod = torch.empty(n, dtype=plan.tod_dtype, device=dev)
 
     def step():
-        plan.set_sky_beam(a, b)
-        plan.interpolate(ptg, out=tod)
+        # maps from (a, b), then the TOD at ptg; the pointing binning overlaps the maps
+        plan.convolve(a, b, ptg, out=tod)
 
     for _ in range(warmup):
         step()
@@ -188,7 +189,11 @@ def main():
 
     model = stage_model(info, n, prec, plan.get_param("gather_mma"))
     per_launch = {s: (t / c if c else 0.0) for s, (t, c) in stages.items()}
-    dom = max(per_launch, key=per_launch.get)
+    # The binning runs on the plan's side stream beside the map synthesis
+    # (sc_plan_convolve): its events span the time it waits for compute units, and
+    # it is off the critical path, so the dominant kernel is taken among the rest.
+    OVERLAPPED = ("binning",)
+    dom = max((s_ for s_ in per_launch if s_ not in OVERLAPPED), key=per_launch.get)
     bound, units, unit, peak = model[dom]
     achieved = units / (per_launch[dom] * 1e-3)
     workload_name = "sidelobe-lmax512-kmax100-scan1e7"
@@ -214,6 +219,8 @@ def main():
         sc_ = 1e12 if un_ == "TFLOP/s" else 1e9
         stage_roofline[s_] = {"bound": b_, "achieved": a_ / sc_, "peak": pk_ / sc_, "unit": un_, "frac": a_ / pk_,
                               "avg_launch_ms": t_}
+        if s_ in OVERLAPPED:
+            stage_roofline[s_]["overlapped"] = "side stream, concurrent with the map synthesis (span includes waits)"
 
     result = {
         "metric": METRIC,
@@ -358,8 +365,7 @@ def extra_adjoint(torch, api, W, dev, no_oracle):
     grad = torch.empty_like(a)
 
     def fwd():
-        plan.set_sky_beam(a, b)
-        plan.interpolate(ptg, out=tod)
+        plan.convolve(a, b, ptg, out=tod)
 
     def adj():
         plan.adjoint(b, ptg, y, out=grad)

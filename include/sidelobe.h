@@ -130,9 +130,20 @@ int sc_set_sky_beam(sc_plan *plan, const double *alm, const double *blm);
 int sc_interpolate(sc_plan *plan, const double *ptg, int64_t n, void *tod);
 
 /*
+ * sc_set_sky_beam followed by sc_interpolate, as one call: the pointing binning
+ * of the first pass (it needs only ptg) runs on a plan-owned side stream while
+ * the maps are synthesised, and joins the plan's stream before the gather.
+ * Same arguments, layouts and errors as the two calls; the side stream is
+ * created on first use, waits for all work queued before the call, and holds
+ * no work after the call's own gather.
+ */
+int sc_plan_convolve(sc_plan *plan, const double *alm, const double *blm, const double *ptg, int64_t n,
+                     void *tod);
+
+/*
  * One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod: creates (or
  * reuses a cached) plan for (lmax, kmax, precision, default W) on the stream,
- * synthesises the maps and interpolates.  Same layouts as above.
+ * and runs sc_plan_convolve on it.  Same layouts as above.
  */
 int sc_convolve(const double *alm, const double *blm, int lmax, int kmax,
                 const double *ptg, int64_t n, void *tod, int precision, void *stream);
@@ -229,7 +240,7 @@ int sc_plan_get_param(const sc_plan *plan, int param, int64_t *value);
  *
  *   lmax, kmax  the detector's beam band limit and truncation (lmax <= lmax_sky)
  *   blm         device complex128, layout of (lmax, kmax)
- *   ptg, n      device float64 [n][3], 0 <= n <= 2^24
+ *   ptg, n      device float64 [n][3], 0 <= n <= 2^27
  *   tod         device float32 [n] output
  */
 typedef struct sc_det_desc {

@@ -118,6 +118,29 @@ class Plan:
             N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
         return out
 
+    def convolve(self, alm: torch.Tensor, blm: torch.Tensor, ptg: torch.Tensor,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        """set_sky_beam + interpolate in one call (sc_plan_convolve: the pointing
+        binning overlaps the map synthesis on a side stream)."""
+        _dev(alm, "alm", torch.complex128)
+        _dev(blm, "blm", torch.complex128)
+        if alm.numel() != n_alm(self.get_param("sky_lmax")) or blm.numel() != n_alm(self.lmax, self.kmax):
+            raise ValueError("alm/blm sizes do not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
+        _dev(ptg, "ptg", torch.float64)
+        if ptg.dim() != 2 or ptg.shape[1] != 3:
+            raise ValueError("ptg must be [n, 3]")
+        n = ptg.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
+        _dev(out, "tod", self.tod_dtype)
+        if out.numel() != n:
+            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
+        self.set_stream()
+        N.check(self._lib.sc_plan_convolve(self._p, alm.data_ptr(), blm.data_ptr(), ptg.data_ptr(), n,
+                                           out.data_ptr()), "sc_plan_convolve")
+        self._keep = (alm, blm)
+        return out
+
     def adjoint(self, blm: torch.Tensor, ptg: torch.Tensor, tod_grad: torch.Tensor,
                 out: torch.Tensor | None = None) -> torch.Tensor:
         """sc_convolve_adjoint: g_lm = dL/dRe a_lm + i dL/dIm a_lm of L = sum_t y_t c_t (complex128)."""

@@ -394,6 +394,13 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
 int sc_plan_destroy(sc_plan *p) {
     if (!p) return SC_OK;
     hipError_t e = hipStreamSynchronize(p->stream);
+    if (p->side) {
+        const hipError_t es = hipStreamSynchronize(p->side);
+        if (e == hipSuccess) e = es;
+        (void)hipStreamDestroy(p->side);
+    }
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     free_plan_buffers(p);
     delete p;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in sc_plan_destroy");
@@ -439,39 +446,102 @@ int sc_set_sky_beam(sc_plan *p, const double *alm, const double *blm) {
     return SC_OK;
 }
 
+// Argument checks of an interpolation (n > 0).
+static int check_interp_args(sc_plan *p, const double *ptg, void *tod) {
+    if (!is_device_ptr(ptg)) return fail(SC_EINVAL, "ptg is not device memory");
+    if (!is_device_ptr(tod)) return fail(SC_EINVAL, "tod is not device memory");
+    if (((uintptr_t)ptg & 7) || ((uintptr_t)tod & (p->prec == SC_FP64 ? 7 : 3)))
+        return fail(SC_EINVAL, "ptg/tod misaligned");
+    return SC_OK;
+}
+
+static bool uses_binning(const sc_plan *p) { return !p->gather_direct && sc_gather_binned_supported(p); }
+
+// Binning pass of samples [off, off + cnt) on the plan's current stream.
+static int bin_pass(sc_plan *p, const double *ptg, int64_t off, int64_t cnt) {
+    const int slot = timing_begin(p, SC_STAGE_BIN);
+    const hipError_t e = sc_launch_binning(p, ptg + 3 * off, cnt);
+    timing_end(p, slot);
+    return e != hipSuccess ? hip_fail(e, "binning launch") : SC_OK;
+}
+
+// Binned interpolation in passes; the first pass's binning has already been
+// issued when first_binned is set.
+static int interpolate_passes(sc_plan *p, const double *ptg, int64_t n, void *tod, bool first_binned) {
+    const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
+    const size_t esz = p->prec == SC_FP64 ? 8 : 4;
+    for (int64_t off = 0; off < n; off += pass) {
+        const int64_t cnt = n - off < pass ? n - off : pass;
+        if (off > 0 || !first_binned) {
+            const int rc = bin_pass(p, ptg, off, cnt);
+            if (rc) return rc;
+        }
+        const int slot = timing_begin(p, SC_STAGE_GATHER);
+        const hipError_t e = sc_launch_gather_binned(p, (char *)tod + esz * off);
+        timing_end(p, slot);
+        if (e != hipSuccess) return hip_fail(e, "binned gather launch");
+    }
+    return SC_OK;
+}
+
 int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     g_msg[0] = 0;
     if (!p) return fail(SC_EINVAL, "plan is NULL");
     if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
     if (n == 0) return SC_OK;
     if (!p->have_maps) return fail(SC_ESTATE, "sc_interpolate before sc_set_sky_beam");
-    if (!is_device_ptr(ptg)) return fail(SC_EINVAL, "ptg is not device memory");
-    if (!is_device_ptr(tod)) return fail(SC_EINVAL, "tod is not device memory");
-    if (((uintptr_t)ptg & 7) || ((uintptr_t)tod & (p->prec == SC_FP64 ? 7 : 3)))
-        return fail(SC_EINVAL, "ptg/tod misaligned");
-    if (p->gather_direct || !sc_gather_binned_supported(p)) {
+    int rc = check_interp_args(p, ptg, tod);
+    if (rc) return rc;
+    if (!uses_binning(p)) {
         int slot = timing_begin(p, SC_STAGE_GATHER);
         hipError_t e = sc_launch_gather(p, ptg, n, tod);
         timing_end(p, slot);
         if (e != hipSuccess) return hip_fail(e, "gather launch");
         return SC_OK;
     }
-    const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
-    int rc = ensure_bin_work(p, pass);
+    rc = ensure_bin_work(p, n < p->bin_pass_max ? n : p->bin_pass_max);
     if (rc) return rc;
-    const size_t esz = p->prec == SC_FP64 ? 8 : 4;
-    for (int64_t off = 0; off < n; off += pass) {
-        const int64_t cnt = n - off < pass ? n - off : pass;
-        int slot = timing_begin(p, SC_STAGE_BIN);
-        hipError_t e = sc_launch_binning(p, ptg + 3 * off, cnt);
-        timing_end(p, slot);
-        if (e != hipSuccess) return hip_fail(e, "binning launch");
-        slot = timing_begin(p, SC_STAGE_GATHER);
-        e = sc_launch_gather_binned(p, (char *)tod + esz * off);
-        timing_end(p, slot);
-        if (e != hipSuccess) return hip_fail(e, "binned gather launch");
+    return interpolate_passes(p, ptg, n, tod, false);
+}
+
+int sc_plan_convolve(sc_plan *p, const double *alm, const double *blm, const double *ptg, int64_t n, void *tod) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n == 0 || !uses_binning(p)) {
+        const int rc = sc_set_sky_beam(p, alm, blm);
+        return rc ? rc : sc_interpolate(p, ptg, n, tod);
     }
-    return SC_OK;
+    int rc = check_interp_args(p, ptg, tod);
+    if (rc) return rc;
+    rc = ensure_bin_work(p, n < p->bin_pass_max ? n : p->bin_pass_max);
+    if (rc) return rc;
+    if (!p->side) {
+        hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "side stream setup");
+    }
+    // The first binning pass depends only on the pointings: it runs on the side
+    // stream (after everything queued so far on the plan's stream, which may still
+    // read the binning buffers) while the maps are synthesised.
+    hipStream_t main = p->stream;
+    hipError_t e = hipEventRecord(p->ev_fork, main);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "stream fork");
+    p->stream = p->side;
+    rc = bin_pass(p, ptg, 0, n < p->bin_pass_max ? n : p->bin_pass_max);
+    p->stream = main;
+    e = hipEventRecord(p->ev_join, p->side);
+    if (rc == SC_OK && e != hipSuccess) rc = hip_fail(e, "stream join");
+    const int rs = sc_set_sky_beam(p, alm, blm);
+    // join before anything else can fail, so the side stream never runs ahead of a
+    // later call's use of the binning buffers
+    e = hipStreamWaitEvent(main, p->ev_join, 0);
+    if (rc) return rc;
+    if (rs) return rs;
+    if (e != hipSuccess) return hip_fail(e, "stream join");
+    return interpolate_passes(p, ptg, n, tod, true);
 }
 
 int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const double *ptg, int64_t n, void *tod,
@@ -494,9 +564,7 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const 
         p = it->second;
         p->stream = (hipStream_t)stream;
     }
-    int rc = sc_set_sky_beam(p, alm, blm);
-    if (rc) return rc;
-    return sc_interpolate(p, ptg, n, tod);
+    return sc_plan_convolve(p, alm, blm, ptg, n, tod);
 }
 
 int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const void *tod_grad, int64_t n,

@@ -35,9 +35,10 @@ struct FftPlan {
     unsigned mag[SC_MAX_RADICES];
 };
 
-// Default samples per work item of the binned gather, and samples per binning pass.
+// Default samples per work item of the binned gather, and samples per binning pass
+// (a pass of 2^27 samples holds about 7.5 GB of binning workspace, 56 bytes per sample).
 #define BIN_CHUNK 256
-#define BIN_PASS_MAX (1 << 24)
+#define BIN_PASS_MAX (1 << 27)
 
 // Anchor grid of the binned gather: key = row0 * nkc + col0.
 struct BinGeom {
@@ -97,6 +98,8 @@ struct sc_plan {
     int rpt, ngroups;  // recursion layout: rings per lane, ring groups per (k, m)
     int rpt_mx, ngroups_mx;  // the same for the FP32 (mixed-precision) recursion
     hipStream_t stream;
+    hipStream_t side;             // sc_plan_convolve: binning beside the map synthesis
+    hipEvent_t ev_fork, ev_join;  // (created on first use)
 
     FftPlan p2, p2os, pphi;
 

@@ -188,6 +188,30 @@ def _run_env(env, fn):
                 os.environ[k] = v
 
 
+@pytest.mark.parametrize("passmax", [None, "70000"])
+def test_plan_convolve_matches_two_calls(torch_dev, api, passmax):
+    """sc_plan_convolve (first binning pass on the side stream, beside the map
+    synthesis) gives the TOD of sc_set_sky_beam + sc_interpolate bit for bit, on
+    repeated calls and over several binning passes."""
+    torch, dev = torch_dev
+    L, K, n = 64, 8, 200_000
+    a, b = _inputs(L, K, 31)
+    ptg = W.scan_pointings(n, device=dev)
+
+    def run():
+        plan = api.Plan(L, K, "f64maps_f32gather")
+        at, bt = _to(torch, dev, a), _to(torch, dev, b)
+        plan.set_sky_beam(at, bt)
+        t1 = plan.interpolate(ptg).clone()
+        t2 = plan.convolve(at, bt, ptg).clone()
+        t3 = plan.convolve(at, bt, ptg)
+        torch.cuda.synchronize()
+        return t1, t2, t3
+
+    t1, t2, t3 = run() if passmax is None else _run_env({"SC_BIN_PASS_MAX": passmax}, run)
+    assert torch.equal(t1, t2) and torch.equal(t1, t3)
+
+
 @pytest.mark.parametrize("prec", ["f64maps_f32gather", "fp64"])
 def test_binned_gather_edge_cases(torch_dev, api, oracle_lib, prec):
     """Anchor binning: poles, phi at 2 pi, > BIN_CHUNK samples on one anchor, several
