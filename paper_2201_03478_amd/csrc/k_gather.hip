@@ -286,7 +286,7 @@ constexpr int GCH = 128;       // samples per chunk
 constexpr int GW1 = GCH + 16;  // weight row stride (floats)
 
 __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
-    return sizeof(float) * (64 * (16 * (size_t)CT + 16) + 16 * GW1) + GCH * (sizeof(double) + sizeof(int));
+    return sizeof(float) * (64 * (16 * (size_t)CT + 16) + 16 * GW1) + GCH * (sizeof(double2) + sizeof(int));
 }
 
 // The k-sum of one chunk: lane (r, grp) of wave w holds, for each of its TPW
@@ -294,14 +294,12 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
 // 16 TPW w + r); it forms sum_c basis_c(psi) X[c] over them, the four lanes of
 // the sample add their parts, and the sum (times oscale) is the sample's value.
 template <int CT, int TPW>
-__device__ __forceinline__ void ksum_store(const GatherDet &D, const floatx4 (&acc)[TPW][CT], const double *Psi,
+__device__ __forceinline__ void ksum_store(const GatherDet &D, const floatx4 (&acc)[TPW][CT], const double2 *E,
                                            const int *Idx, int s0, int grp, int ns, float oscale) {
 #pragma unroll
     for (int h = 0; h < TPW; ++h) {
         const int sl = s0 + 16 * h;
-        double sn, cs;
-        sincos(Psi[sl], &sn, &cs);
-        const double2 e1 = make_double2(cs, sn);
+        const double2 e1 = E[sl];  // (cos psi, sin psi) of the sample
         const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
         const double2 e8 = cmul(e4, e4);
         double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
@@ -340,8 +338,8 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
     constexpr int NCS = NC + ((CT & 1) ? 0 : 16); // LDS row stride
     float *Psh = (float *)smem_d;                 // [64 taps][NCS]
     float *W1 = Psh + 64 * NCS;                   // [16][GW1]: theta (0..7) and phi (8..15) factors
-    double *Psi = (double *)(W1 + 16 * GW1);      // [GCH]
-    int *Idx = (int *)(Psi + GCH);                // [GCH]
+    double2 *E = (double2 *)(W1 + 16 * GW1);      // [GCH] (cos psi, sin psi)
+    int *Idx = (int *)(E + GCH);                  // [GCH]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -388,7 +386,9 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             }
         }
         if (tid < GCH) {
-            Psi[tid] = tid < ns ? pf_psi : 0.0;
+            double sn, cs;  // once per sample (the k-sum's four lanes of a sample share it)
+            sincos(tid < ns ? pf_psi : 0.0, &sn, &cs);
+            E[tid] = make_double2(cs, sn);
             Idx[tid] = tid < ns ? pf_idx : -1;
         }
         __syncthreads();
@@ -454,8 +454,8 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
             for (int ct = 0; ct < CT; ++ct) a[ct] = an[ct];
         }
 
-        ksum_store<CT, TPW>(D, acc, Psi, Idx, s0, grp, ns, 1.f);
-        __syncthreads();  // W1, Psi, Idx are rewritten by the next chunk
+        ksum_store<CT, TPW>(D, acc, E, Idx, s0, grp, ns, 1.f);
+        __syncthreads();  // W1, E, Idx are rewritten by the next chunk
     }
 }
 
@@ -491,7 +491,7 @@ constexpr float SPLIT_RSCALE = 16384.f;  // 2^14
 
 __host__ __device__ constexpr size_t split_lds_bytes(int CT) {
     return 2 * (2 * (size_t)CT * 64 * sizeof(half8)) + 2 * (size_t)CT * 64 * sizeof(long) + sizeof(float) * 16 * GW1 +
-           GCH * (sizeof(double) + sizeof(int));
+           GCH * (sizeof(double2) + sizeof(int));
 }
 
 // An empty use of a register value (keeps it allocated up to this point).
@@ -528,8 +528,8 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
     half8 *Alo = Ahi + 2 * CT * 64;            // a2
     long *Arm = (long *)(Alo + 2 * CT * 64);   // a3 (FP8 x 8)
     float *W1 = (float *)(Arm + 2 * CT * 64);  // [16][GW1]: theta (0..7) and phi (8..15) factors
-    double *Psi = (double *)(W1 + 16 * GW1);   // [GCH]
-    int *Idx = (int *)(Psi + GCH);             // [GCH]
+    double2 *E = (double2 *)(W1 + 16 * GW1);   // [GCH] (cos psi, sin psi)
+    int *Idx = (int *)(E + GCH);               // [GCH]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -615,7 +615,9 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
             }
         }
         if (tid < GCH) {
-            Psi[tid] = tid < ns ? pf_psi : 0.0;
+            double sn, cs;  // once per sample (the k-sum's four lanes of a sample share it)
+            sincos(tid < ns ? pf_psi : 0.0, &sn, &cs);
+            E[tid] = make_double2(cs, sn);
             Idx[tid] = tid < ns ? pf_idx : -1;
         }
         __syncthreads();
@@ -710,8 +712,8 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
                 ar = arn;
             }
         }
-        ksum_store<CT, TPW>(D, acc, Psi, Idx, s0, grp, ns, oscale);
-        __syncthreads();  // W1, Psi, Idx are rewritten by the next chunk
+        ksum_store<CT, TPW>(D, acc, E, Idx, s0, grp, ns, oscale);
+        __syncthreads();  // W1, E, Idx are rewritten by the next chunk
     }
 }
 
