@@ -293,6 +293,12 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int CT) {
 // sample tiles h, components 16 ct + 4 grp + v of sample s0 + 16 h (s0 =
 // 16 TPW w + r); it forms sum_c basis_c(psi) X[c] over them, the four lanes of
 // the sample add their parts, and the sum (times oscale) is the sample's value.
+// With k0 = 8 ct + 2 grp the lane's four components are the pairs of k0 and
+// k0 + 1, so its part is Re[e^{2 i grp psi} sum_ct (A_ct + B_ct e^{i psi}) w^ct]
+// with A_ct = X[c0] - i X[c0 + 1], B_ct = X[c0 + 2] - i X[c0 + 3] and w = e^{8 i psi},
+// evaluated by Horner's rule in w (FP64).  Component tiles other than the last are
+// full (the padded count is the next multiple of 16); the last one's components
+// past ncomp are left out.
 template <int CT, int TPW>
 __device__ __forceinline__ void ksum_store(const GatherDet &D, const floatx4 (&acc)[TPW][CT], const double2 *E,
                                            const int *Idx, int s0, int grp, int ns, float oscale) {
@@ -302,27 +308,28 @@ __device__ __forceinline__ void ksum_store(const GatherDet &D, const floatx4 (&a
         const double2 e1 = E[sl];  // (cos psi, sin psi) of the sample
         const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
         const double2 e8 = cmul(e4, e4);
-        double2 z = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
-        float part = 0.f;
+        const double2 z0 = grp == 0 ? make_double2(1.0, 0.0) : grp == 1 ? e2 : grp == 2 ? e4 : cmul(e4, e2);
+        double2 q = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            // components c0 .. c0 + 3 are the pairs k0 = c0 / 2 and k0 + 1; z = e^{i k0 psi}
+        for (int ct = CT - 1; ct >= 0; --ct) {
             const int c0 = 16 * ct + 4 * grp;
-            const double2 z1 = cmul(z, e1);
             const floatx4 x = acc[h][ct];
-            if (c0 < D.ncomp) {
-                part = fmaf((float)z.x, x[0], part);
-                part = fmaf((float)z.y, x[1], part);
+            double ax = (double)x[0], ay = -(double)x[1], bx = (double)x[2], by = -(double)x[3];
+            if (ct == CT - 1) {
+                if (c0 >= D.ncomp) ax = ay = 0.0;
+                if (c0 + 2 >= D.ncomp) bx = by = 0.0;
             }
-            if (c0 + 2 < D.ncomp) {
-                part = fmaf((float)z1.x, x[2], part);
-                part = fmaf((float)z1.y, x[3], part);
-            }
-            z = cmul(z, e8);
+            // C = A + B e1;  q = q w + C
+            const double cx = fma(bx, e1.x, fma(-by, e1.y, ax));
+            const double cy = fma(bx, e1.y, fma(by, e1.x, ay));
+            const double qx = fma(q.x, e8.x, fma(-q.y, e8.y, cx));
+            const double qy = fma(q.x, e8.y, fma(q.y, e8.x, cy));
+            q = make_double2(qx, qy);
         }
+        double part = z0.x * q.x - z0.y * q.y;
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (grp == 0 && sl < ns) D.tod[Idx[sl]] = part * oscale;
+        if (grp == 0 && sl < ns) D.tod[Idx[sl]] = (float)part * oscale;
     }
 }
 
