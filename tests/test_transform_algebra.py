@@ -1,0 +1,136 @@
+"""Host-side checks of the transform algebra the theta kernels rely on (CPU).
+
+The theta stage extends each ring-sum column F_k(., m) to the full circle with
+the parity F(-theta) = (-1)^{m-k} F(theta) (from d^l_mk(-theta) =
+(-1)^{m-k} d^l_mk(theta)), transforms it, divides by the interpolation
+kernel's transform and upsamples (the finite-resolution grid of Galloway et
+al. 2022, Sec. 2.1).  The kernels transform two columns of opposite parity
+with one complex FFT pair and separate them afterwards.  These tests restate
+that separation with numpy FFTs on random columns and compare it with the
+column-by-column computation, and check that the paired adjoint is the
+transpose of the paired forward map (dot-product identity).  They pin the
+identities, not the HIP code; the GPU tests compare the HIP path with the
+oracle.
+"""
+import numpy as np
+import pytest
+
+
+def _setup(lmax=20, n2=44, nos=90, W=8, seed=1):
+    rng = np.random.default_rng(seed)
+    n = np.arange(-lmax, lmax + 1)
+    q = rng.uniform(0.5, 2.0, lmax + 1)          # a real, even kernel factor
+    phase = np.exp(-1j * np.pi * n / n2) * q[np.abs(n)]  # half-ring shift times 1/kernel
+    dphi = rng.uniform(0.5, 2.0, lmax + 1)
+    rows = nos // 2 + W
+    r0 = -W // 2 + 1
+    return dict(lmax=lmax, n2=n2, nos=nos, rows=rows, r0=r0, n=n, phase=phase, dphi=dphi, rng=rng)
+
+
+def _single(S, Fc, m, k):
+    """One column: parity extension, FFT, deconvolution, zero padding, inverse FFT, kept rows."""
+    n2, nos, n = S["n2"], S["nos"], S["n"]
+    nring = n2 // 2
+    s = -1.0 if (m - k) & 1 else 1.0
+    f = np.zeros(n2, complex)
+    f[:nring] = Fc
+    f[n2 - 1 - np.arange(nring)] = s * Fc
+    X = np.fft.fft(f)
+    Y = np.zeros(nos, complex)
+    Y[n % nos] = X[n % n2] * S["phase"] * S["dphi"][abs(m)]
+    O = np.fft.ifft(Y) * nos
+    return O[(np.arange(S["rows"]) + S["r0"]) % nos]
+
+
+def _paired(S, F1, F2, m, k, two=True):
+    """Columns m and m + 1 through one forward and one inverse transform (the kernels' scheme)."""
+    n2, nos, n = S["n2"], S["nos"], S["n"]
+    nring = n2 // 2
+    s1 = -1.0 if (m - k) & 1 else 1.0
+    if not two:
+        F2 = np.zeros_like(F1)
+    j = np.arange(nring)
+    h = np.zeros(n2, complex)
+    h[j] = F1 + 1j * F2
+    h[n2 - 1 - j] = s1 * (F1 - 1j * F2)
+    H = np.fft.fft(h)
+    d1 = S["dphi"][abs(m)]
+    d2 = S["dphi"][abs(m + 1)] if two else d1
+    ca, cb = 0.25 * (d1 + d2), 0.25 * s1 * (d1 - d2)
+    Z = ca * S["phase"] * H[n % n2] + cb * np.conj(S["phase"]) * H[(-n) % n2]
+    B = np.zeros(nos, complex)
+    B[n % nos] = Z
+    O = np.fft.ifft(B) * nos
+    r = (np.arange(S["rows"]) + S["r0"]) % nos
+    rm = (-r) % nos
+    return O[r] + s1 * O[rm], -1j * (O[r] - s1 * O[rm])
+
+
+def _paired_adjoint(S, G1, G2, m, k, two=True):
+    n2, nos, n, rows, r0 = S["n2"], S["nos"], S["n"], S["rows"], S["r0"]
+    nring = n2 // 2
+    s1 = -1.0 if (m - k) & 1 else 1.0
+    if not two:
+        G2 = np.zeros_like(G1)
+    rtop = r0 + rows - 1
+
+    def row_of(r):
+        return r - r0 if r <= rtop else (r - nos - r0 if r - nos >= r0 else -1)
+
+    h = np.zeros(nos, complex)
+    for r in range(nos):
+        a, b = row_of(r), row_of((nos - r) % nos)
+        a1 = G1[a] if a >= 0 else 0
+        a2 = G2[a] if a >= 0 else 0
+        b1 = G1[b] if b >= 0 else 0
+        b2 = G2[b] if b >= 0 else 0
+        h[r] = (a1 + s1 * b1) + 1j * (a2 - s1 * b2)
+    Y = np.fft.fft(h)
+    d1 = S["dphi"][abs(m)]
+    d2 = S["dphi"][abs(m + 1)] if two else d1
+    ca, cb = 0.25 * (d1 + d2), 0.25 * s1 * (d1 - d2)
+    Z = np.conj(S["phase"]) * (ca * Y[n % nos] + cb * Y[(-n) % nos])
+    B = np.zeros(n2, complex)
+    B[n % n2] = Z
+    f = np.fft.ifft(B) * n2
+    j = np.arange(nring)
+    return f[j] + s1 * f[n2 - 1 - j], -1j * (f[j] - s1 * f[n2 - 1 - j])
+
+
+@pytest.mark.parametrize("m,k", [(-20, 0), (-3, 2), (0, 3), (5, 1), (19, 4)])
+def test_paired_columns_match_single_columns(m, k):
+    S = _setup()
+    nring = S["n2"] // 2
+    rng = S["rng"]
+    F1 = rng.standard_normal(nring) + 1j * rng.standard_normal(nring)
+    F2 = rng.standard_normal(nring) + 1j * rng.standard_normal(nring)
+    g1, g2 = _paired(S, F1, F2, m, k)
+    ref1, ref2 = _single(S, F1, m, k), _single(S, F2, m + 1, k)
+    scale = max(np.abs(ref1).max(), np.abs(ref2).max())
+    assert np.abs(g1 - ref1).max() <= 1e-13 * scale
+    assert np.abs(g2 - ref2).max() <= 1e-13 * scale
+
+
+def test_last_column_alone():
+    """An odd column count leaves the last column without a partner (f2 = 0, d2 = d1)."""
+    S = _setup()
+    F1 = S["rng"].standard_normal(S["n2"] // 2) + 0j
+    g1, _ = _paired(S, F1, None, 20, 3, two=False)
+    ref = _single(S, F1, 20, 3)
+    assert np.abs(g1 - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("m,k", [(-20, 0), (-1, 1), (4, 3)])
+def test_paired_adjoint_is_the_transpose(m, k):
+    S = _setup(seed=7)
+    nring, rows, rng = S["n2"] // 2, S["rows"], S["rng"]
+    F1 = rng.standard_normal(nring) + 1j * rng.standard_normal(nring)
+    F2 = rng.standard_normal(nring) + 1j * rng.standard_normal(nring)
+    G1 = rng.standard_normal(rows) + 1j * rng.standard_normal(rows)
+    G2 = rng.standard_normal(rows) + 1j * rng.standard_normal(rows)
+    g1, g2 = _paired(S, F1, F2, m, k)
+    a1, a2 = _paired_adjoint(S, G1, G2, m, k)
+    ip = lambda u, v: np.real(np.vdot(u, v))
+    lhs = ip(g1, G1) + ip(g2, G2)
+    rhs = ip(F1, a1) + ip(F2, a2)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
