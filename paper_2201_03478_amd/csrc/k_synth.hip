@@ -35,9 +35,9 @@
 // products of gamma telescope to about sqrt(l0 / l)), so u stays as well
 // conditioned as d.  Every ring accumulates its scaled u unconditionally: while
 // e < 0 the sums are meaningless, so they are cleared at the check where e
-// reaches 0 (what the ring added before that is below 2^-600 of its true size,
+// reaches 0 (what the ring added before that is below 2^-248 in true units,
 // i.e. nothing), and a ring that ends with e < 0 writes zero.  The check runs
-// every 8 steps while some ring of the wave has e < 0; once all have e = 0
+// every 32 steps while some ring of the wave has e < 0; once all have e = 0
 // (|d| <= 1, |u| = O(1) from then on) the loop runs without it.  Both loops
 // cost the same six FMAs per d value.
 //
@@ -194,10 +194,12 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
             rec_steps<RPT>(0, nl, cA, cB, cWp, cWm, x, u, up, fp, fm);
             continue;
         }
-        // Rescaling is checked once per 8 steps: one step grows |u| by at most
-        // ~2^11, far inside the 2^424 left below overflow.
-        for (int t0 = 0; t0 < nl; t0 += 8) {
-            const int t1 = t0 + 8 < nl ? t0 + 8 : nl;
+        // Rescaling is checked once per 32 steps: one step grows |u| by at most
+        // ~2^11, so 32 steps stay inside the 2^424 left below overflow, and what a
+        // ring accumulates between passing 2^600 and its rescale (true values below
+        // 2^{-600 + 352}) is dropped harmlessly with the scaled sums.
+        for (int t0 = 0; t0 < nl; t0 += 32) {
+            const int t1 = t0 + 32 < nl ? t0 + 32 : nl;
             rec_steps<RPT>(t0, t1, cA, cB, cWp, cWm, x, u, up, fp, fm);
             if (fast) continue;
             bool low = false;
