@@ -43,8 +43,9 @@
 //
 // Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
 // rings.  Recursion coefficients and weights for 64 consecutive l are built
-// cooperatively in LDS (one l per lane; S_l by a product scan over the lanes of
-// each parity) and read as broadcasts.
+// cooperatively in LDS (one l per lane, the square roots of alpha_l and gamma_l
+// from a per-plan table of sqrt((l+1)^2 - x^2); S_l by a product scan over the
+// lanes of each parity) and read as broadcasts.
 #include "wigner_rec.h"
 
 namespace {
@@ -111,7 +112,7 @@ template <int RPT>
 __global__ void __launch_bounds__(64)
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
-            const double *__restrict__ rtab, int lmax, int kmax, int nring,
+            const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
     __shared__ double cA[64], cB[64];
     __shared__ double2 cWp[64], cWm[64];
@@ -150,7 +151,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     }
     bool fast = !__any(scaled);
 
-    const double mm = (double)m * m, kk = (double)k * k, mk = (double)m * k;
+    const double mk = (double)m * k;
     const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     double s_prev = 1.0, s_cur = 1.0;  // S_{lc-1}, S_{lc} (S_{l0-1} := 1 only seeds the scan)
@@ -159,7 +160,22 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         double A = 1.0, B = 0.0, C = 1.0;
         double2 wp = make_double2(0.0, 0.0), wm = make_double2(0.0, 0.0);
         if (l <= lmax) {
-            rec_coefs(l, mm, kk, mk, A, B, C);
+            if (l == 0) {
+                A = 1.0;
+                B = 0.0;
+                C = 0.0;
+            } else {
+                // alpha_l, beta_l, gamma_l from the root table: q = r(m, l) r(k, l) with
+                // r(x, l) = sqrt((l+1)^2 - x^2), and sqrt((l^2-m^2)(l^2-k^2)) = r(m, l-1) r(k, l-1)
+                const double2 tm = rroot[(size_t)m * (lmax + 1) + l], tk = rroot[(size_t)k * (lmax + 1) + l];
+                const double2 pm = rroot[(size_t)m * (lmax + 1) + l - 1], pk = rroot[(size_t)k * (lmax + 1) + l - 1];
+                const double L = (double)l, L1 = L + 1.0;
+                const double rq = tm.y * tk.y;
+                const double inv = 1.0 / (L * L1);
+                A = (2.0 * L + 1.0) * L1 * rq;
+                B = A * mk * inv;
+                C = L1 * L1 * inv * (pm.x * pk.x) * rq;
+            }
             double2 a = alm[aoff + l];
             double2 bb = blm[boff + l];
             if (m == 0) a.y = 0.0;
@@ -239,7 +255,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 #define SC_RING_CASE(R)                                                                                      \
     case R:                                                                                                  \
         hipLaunchKernelGGL(k_ring_sums<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,         \
-                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring,      \
+                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, \
                            p->ngroups, p->alm_lmax);                                                         \
         break;
 

@@ -9,6 +9,8 @@
 //    computed with z = sin t (which removes the endpoint square root) by
 //    Gauss-Legendre quadrature in t.  Each spectral coefficient is divided by
 //    hhat (theta and phi factors) before the grid is synthesised.
+//  * sqrt((l+1)^2 - x^2) and its reciprocal for 0 <= x, l <= lmax (the roots of
+//    the recursion coefficients).
 //  * sqrt(C(2 l, l + n)) as (mantissa, binary exponent) pairs: the prefactor of
 //    the closed-form start values d^l_{l k} and d^l_{m l} of the Wigner-d
 //    recursion (Wigner's explicit sum with a single surviving term).
@@ -97,6 +99,22 @@ __global__ void k_deconv(double2 *phase, double *dphi, int lmax, int n2, int n2o
     if (t <= lmax) dphi[t] = 1.0 / kernel_transform((double)t, two_pi / nphi, W, beta, glx, glw, nq);
 }
 
+// Recursion roots: at [x][l], sqrt((l+1)^2 - x^2) and its reciprocal (zero where
+// l + 1 <= x), so that the recursion coefficients of step l need one division.
+__global__ void k_rec_roots(double2 *t, int lmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nl = lmax + 1;
+    if (i >= nl * nl) return;
+    const int x = (int)(i / nl), l = (int)(i - (int64_t)x * nl);
+    const double v = (double)(l + 1) * (l + 1) - (double)x * x;  // exact
+    double2 r = make_double2(0.0, 0.0);
+    if (v > 0.0) {
+        const double s = sqrt(v);
+        r = make_double2(s, 1.0 / s);
+    }
+    t[i] = r;
+}
+
 __global__ void k_sqrt_binom(double *sm, int *se, int lmax, int kmax) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = id / (kmax + 1), n = id - l * (kmax + 1);
@@ -139,6 +157,8 @@ hipError_t sc_launch_tables(sc_plan *p) {
     hipLaunchKernelGGL(k_deconv, dim3((nt + 63) / 64), dim3(64), 0, p->stream, p->phase, p->dphi, p->lmax, p->n2,
                        p->n2os, p->nphi, p->W, p->beta, p->glx, p->glw, p->nq);
     const int nb = (p->lmax + 1) * (p->kmax + 1);
+    const int64_t nr = (int64_t)(p->lmax + 1) * (p->lmax + 1);
+    hipLaunchKernelGGL(k_rec_roots, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, p->stream, p->rroot, p->lmax);
     hipLaunchKernelGGL(k_sqrt_binom, dim3((nb + 255) / 256), dim3(256), 0, p->stream, p->sbin_m, p->sbin_e,
                        p->lmax, p->kmax);
     return hipGetLastError();

@@ -196,7 +196,7 @@ void free_plan_buffers(sc_plan *p) {
     std::free(p->tl);
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
-    void *bufs[] = {p->F, p->G, p->maps, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
+    void *bufs[] = {p->F, p->G, p->maps, p->rroot, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
                     p->phase, p->dphi, p->glx, p->glw};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -347,6 +347,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     rc = rc ? rc : alloc((void **)&p->F, sizeof(double2) * (kmax + 1) * nm * p->nring, &tot);
     rc = rc ? rc : alloc((void **)&p->G, sizeof(double2) * (kmax + 1) * (size_t)p->rows * nm, &tot);
     rc = rc ? rc : alloc(&p->maps, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, &tot);
+    rc = rc ? rc : alloc((void **)&p->rroot, sizeof(double2) * (size_t)(lmax + 1) * (lmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_m, sizeof(double) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_e, sizeof(int) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->rtab, sizeof(double) * 5 * p->nring, &tot);

@@ -107,6 +107,7 @@ struct sc_plan {
     double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums
     double2 *G;        // [kmax+1][rows][2 lmax+1] theta-upsampled, deconvolved
     void *maps;        // [rows][cols][ncp] float or double
+    double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
     double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
     int *sbin_e;       // [lmax+1][kmax+1] binary exponent
     double *rtab;      // [nring][5] cos(theta_j); log2 cos(theta_j / 2), log2 sin(theta_j / 2) as (hi, lo) pairs
