@@ -151,7 +151,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -171,7 +171,7 @@ def main():
     from paper_2201_03478_amd import api
 
     dev = torch.device("cuda", 0)
-    cfg = W.CONFIGS[2]
+    cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
     L, K, n = cfg["lmax"], cfg["kmax"], args.samples
     a_np = W.sky_alm(L, W.config_seed(2, 1))
     b_np = W.beam_alm(L, K, W.config_seed(2, 2), kind="sidelobe")
@@ -335,7 +335,7 @@ def _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, tod, m, seed):
 
 def extra_precision(torch, api, W, dev, no_oracle):
     """lmax 1024, kmax 16, 1e8 scan samples: mixed form vs the FP64-recursion form."""
-    cfg = W.CONFIGS[3]
+    cfg = W.CONFIGS["precision-lmax1024-kmax16"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a_np, b_np = W.sky_alm(L, W.config_seed(3, 1)), W.beam_alm(L, K, W.config_seed(3, 2))
     a, b = torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev)
@@ -354,7 +354,7 @@ def extra_precision(torch, api, W, dev, no_oracle):
 
 def extra_adjoint(torch, api, W, dev, no_oracle):
     """lmax 512, kmax 32, 1e8 scan samples: forward and adjoint, with the dot-product test."""
-    cfg = W.CONFIGS[5]
+    cfg = W.CONFIGS["adjoint-lmax512-kmax32"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a_np, b_np = W.sky_alm(L, W.config_seed(5, 1)), W.beam_alm(L, K, W.config_seed(5, 2))
     a, b = torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev)

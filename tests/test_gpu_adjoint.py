@@ -109,7 +109,7 @@ def test_adjoint_workload_full_size(env):
     """lmax 512, kmax 32, 1e8 scan samples, float32 residual y ~ N(0, 1):
     <y, A a> = <A^T y, a> to 1e-5 and central differences at 16 seeded a_lm."""
     torch, api, dev = env
-    cfg = W.CONFIGS[5]
+    cfg = W.CONFIGS["adjoint-lmax512-kmax32"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a = W.sky_alm(L, W.config_seed(5, 1))
     b = W.beam_alm(L, K, W.config_seed(5, 2))

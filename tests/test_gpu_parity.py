@@ -81,7 +81,7 @@ def test_ring_sums_near_poles_lmax512(torch_dev, api, oracle_lib):
 def test_end_to_end_fp64_tiny_workload(torch_dev, api, oracle_lib):
     """lmax 64, kmax 4, Gaussian beam, 1e5 uniform pointings: FP64 plan vs oracle on all samples."""
     torch, dev = torch_dev
-    cfg = W.CONFIGS[1]
+    cfg = W.CONFIGS["fp64-tiny"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a, b = _inputs(L, K, 1, beam="gauss")
     p = W.uniform_pointings(n, W.config_seed(1, 3))
@@ -114,7 +114,7 @@ def test_end_to_end_f32_small(torch_dev, api, oracle_lib, L, K, n):
 def test_end_to_end_sidelobe_workload_sampled(torch_dev, api, oracle_lib):
     """lmax 512, kmax 100, 1e7 scan samples (the benchmarked configuration): sampled outputs vs oracle."""
     torch, dev = torch_dev
-    cfg = W.CONFIGS[2]
+    cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a, b = _inputs(L, K, 2)
     ptg = W.scan_pointings(n, device=dev)

@@ -100,7 +100,7 @@ def test_mixed_ring_sums_small(env, oracle_lib, L, K):
 def test_precision_workload_sampled(env, oracle_lib, prec, tol):
     """lmax 1024, kmax 16, 1e8 scan samples; 16 sampled outputs against the oracle."""
     torch, api, dev = env
-    cfg = W.CONFIGS[3]
+    cfg = W.CONFIGS["precision-lmax1024-kmax16"]
     L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
     a = W.sky_alm(L, W.config_seed(3, 1))
     b = W.beam_alm(L, K, W.config_seed(3, 2))

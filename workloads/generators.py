@@ -22,16 +22,16 @@ import math
 
 import numpy as np
 
-# Workloads.  "precision" names the arithmetic of the GPU path for that case.
+# Workloads by name; "seed" is the namespace of their seeds (config_seed).
 CONFIGS = {
-    1: dict(name="fp64-tiny", lmax=64, kmax=4, n=100_000, beam="gauss", pointing="uniform"),
-    2: dict(name="sidelobe-lmax512-kmax100", lmax=512, kmax=100, n=10_000_000, beam="sidelobe",
-            pointing="scan"),
-    3: dict(name="precision-lmax1024-kmax16", lmax=1024, kmax=16, n=100_000_000, beam="sidelobe",
-            pointing="scan"),
-    4: dict(name="batched-12det", lmax=1024, kmax=100, n=40_000_000, beam="sidelobe", pointing="scan"),
-    5: dict(name="adjoint-lmax512-kmax32", lmax=512, kmax=32, n=100_000_000, beam="sidelobe",
-            pointing="scan"),
+    "fp64-tiny": dict(seed=1, lmax=64, kmax=4, n=100_000, beam="gauss", pointing="uniform"),
+    "sidelobe-lmax512-kmax100": dict(seed=2, lmax=512, kmax=100, n=10_000_000, beam="sidelobe",
+                                     pointing="scan"),
+    "precision-lmax1024-kmax16": dict(seed=3, lmax=1024, kmax=16, n=100_000_000, beam="sidelobe",
+                                      pointing="scan"),
+    "batched-12det": dict(seed=4, lmax=1024, kmax=100, n=40_000_000, beam="sidelobe", pointing="scan"),
+    "adjoint-lmax512-kmax32": dict(seed=5, lmax=512, kmax=32, n=100_000_000, beam="sidelobe",
+                                   pointing="scan"),
 }
 
 # Batched workload: per-detector (lmax, kmax, n); detector d starts at t0 = d * 1000 s
