@@ -301,7 +301,7 @@ def main():
 
     if not args.no_extras:
         for name, fn in (("precision_variant", extra_precision), ("adjoint", extra_adjoint),
-                         ("batched", extra_batched)):
+                         ("batched", extra_batched), ("dipole", extra_dipole)):
             try:
                 result[name] = fn(torch, api, W, dev, args.no_cpu_baseline)
             except Exception as exc:  # an extra must not lose the headline line
@@ -383,6 +383,26 @@ def extra_adjoint(torch, api, W, dev, no_oracle):
             "forward_ms": fms, "adjoint_ms": ams, "adjoint_value": n / (ams * 1e-3),
             "adjoint_stages_ms": {k: t / 4 for k, (t, c) in st.items() if c},
             "dot_test_rel": abs(lhs - rhs) / abs(lhs)}
+
+
+def extra_dipole(torch, api, W, dev, no_oracle):
+    """Orbital dipole + quadrupole response (Sec. 3.3) on the 1e7-sample scan: one velocity per
+    hour of samples; HBM-bound (24 B of pointing read and 8 B written per sample)."""
+    cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    b = torch.from_numpy(W.beam_alm(L, K, W.config_seed(2, 2), kind="sidelobe")).to(dev)
+    ptg = W.scan_pointings(n, device=dev)
+    spp = 117_000  # one hour at 32.5 Hz
+    nper = (n + spp - 1) // spp
+    g = torch.Generator(device=dev).manual_seed(W.config_seed(2, 7))
+    beta = 1e-4 * torch.randn((nper, 3), generator=g, device=dev, dtype=torch.float64)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    ms = _event_ms(torch, lambda: api.dipole_response(b, L, K, ptg, beta, spp, 2.7255, 1.25, out=out), 20)
+    bytes_per = 32.0 * n
+    return {"workload": "dipole-scan1e7", "n_samples": n, "ms": ms, "value": n / (ms * 1e-3),
+            "unit": "samples/s", "roofline": {"bound": "hbm", "achieved": bytes_per / (ms * 1e-3) / 1e9,
+                                              "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                                              "frac": bytes_per / (ms * 1e-3) / PEAK["hbm"]}}
 
 
 def extra_batched(torch, api, W, dev, no_oracle):

@@ -167,6 +167,25 @@ int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, con
                         double *alm_grad);
 
 /*
+ * Orbital dipole and quadrupole through the full beam (Galloway et al. 2022,
+ * Sec. 3.3, Eqs. 14-19): for the kinematic sky D(n) = T0 [beta.n + q (beta.n)^2]
+ * the convolution at pointing (theta, phi, psi) is T0 [u.S + q u^T S2 u] with
+ * u = R^T beta, R = R_z(phi) R_y(theta) R_z(psi), and S, S2 the beam's first
+ * and second moments in the beam frame (formed on the device from its l <= 2
+ * coefficients).  No plan is needed.
+ *   blm                 device complex128, layout of (lmax, kmax) as for the plans.
+ *   ptg, n              device float64 [n][3] (theta, phi, psi).
+ *   beta                device float64 [ceil(n / samples_per_period)][3]: v / c in the
+ *                       sky frame, one entry per pointing period; sample s uses
+ *                       entry s / samples_per_period.
+ *   T0, q               CMB temperature and the frequency-dependent quadrupole factor.
+ *   out                 device float64 [n].
+ * Asynchronous on `stream`; SC_EINVAL for host or misaligned pointers or bad sizes.
+ */
+int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
+                       int64_t samples_per_period, double T0, double q, double *out, void *stream);
+
+/*
  * Device-side numerical details for tests: copies internal stage buffers to
  * the caller's device memory.  which = 0: ring sums F (complex128
  * [kmax+1][2 lmax+1][n_rings], F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j),

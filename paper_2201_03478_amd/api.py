@@ -211,6 +211,31 @@ def convolve(alm: torch.Tensor, blm: torch.Tensor, lmax: int, kmax: int, ptg: to
     return out
 
 
+def dipole_response(blm: torch.Tensor, lmax: int, kmax: int, ptg: torch.Tensor, beta: torch.Tensor,
+                    samples_per_period: int, T0: float, q: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Orbital dipole + quadrupole through the full beam (sc_dipole_response).
+
+    beta: float64 [ceil(n / samples_per_period), 3], v / c per pointing period."""
+    lib = N.load()
+    _dev(blm, "blm", torch.complex128)
+    _dev(ptg, "ptg", torch.float64)
+    _dev(beta, "beta", torch.float64)
+    n = ptg.shape[0]
+    if ptg.dim() != 2 or ptg.shape[1] != 3:
+        raise ValueError("ptg must be [n, 3]")
+    if blm.numel() != n_alm(lmax, kmax):
+        raise ValueError("blm size does not match lmax=%d kmax=%d" % (lmax, kmax))
+    if beta.numel() < 3 * ((n + samples_per_period - 1) // samples_per_period):
+        raise ValueError("beta holds too few pointing periods")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=ptg.device)
+    _dev(out, "out", torch.float64)
+    N.check(lib.sc_dipole_response(blm.data_ptr(), int(lmax), int(kmax), ptg.data_ptr(), n, beta.data_ptr(),
+                                   int(samples_per_period), float(T0), float(q), out.data_ptr(),
+                                   ctypes.c_void_p(_stream_handle())), "sc_dipole_response")
+    return out
+
+
 class SidelobeConv(torch.autograd.Function):
     """tod = A(alm) for a fixed beam and pointing; backward is the library's adjoint.
 

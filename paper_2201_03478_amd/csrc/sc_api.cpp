@@ -568,6 +568,22 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const 
     return sc_plan_convolve(p, alm, blm, ptg, n, tod);
 }
 
+int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
+                       int64_t samples_per_period, double T0, double q, double *out, void *stream) {
+    g_msg[0] = 0;
+    if (lmax < 0 || kmax < 0 || kmax > lmax) return fail(SC_EINVAL, "lmax = %d, kmax = %d", lmax, kmax);
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (samples_per_period < 1) return fail(SC_EINVAL, "samples_per_period = %lld < 1", (long long)samples_per_period);
+    if (n == 0) return SC_OK;
+    if (!is_device_ptr(blm) || !is_device_ptr(ptg) || !is_device_ptr(beta) || !is_device_ptr(out))
+        return fail(SC_EINVAL, "blm/ptg/beta/out must be device memory");
+    if (((uintptr_t)blm & 15) || ((uintptr_t)ptg & 7) || ((uintptr_t)beta & 7) || ((uintptr_t)out & 7))
+        return fail(SC_EINVAL, "blm/ptg/beta/out misaligned");
+    const hipError_t e = sc_launch_dipole(blm, lmax, kmax, ptg, n, beta, samples_per_period, T0, q, out,
+                                          (hipStream_t)stream);
+    return e != hipSuccess ? hip_fail(e, "dipole launch") : SC_OK;
+}
+
 int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
                         double *alm_grad) {
     g_msg[0] = 0;

@@ -166,6 +166,8 @@ bool sc_scatter_binned_supported(const sc_plan *p);
 hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
 hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
+hipError_t sc_launch_dipole(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
+                            int64_t spp, double T0, double q, double *out, hipStream_t stream);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
 GatherDet sc_gather_det(const sc_plan *p, void *tod);
 hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu, int waves,
