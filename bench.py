@@ -379,10 +379,17 @@ def extra_adjoint(torch, api, W, dev, no_oracle):
     fwd()
     lhs = float(torch.dot(tod.double(), y.double()))
     rhs = float(torch.sum(torch.conj(grad) * a).real)
+    # gradient with respect to the beam (same scatter and transforms, contraction with the sky)
+    bgrad = torch.empty_like(b)
+    bms = _event_ms(torch, lambda: plan.adjoint_beam(a, ptg, y, out=bgrad), 3)
+    b_real0 = b.clone()
+    b_real0[:L + 1] = b_real0[:L + 1].real.to(b.dtype)
+    rhs_b = float(torch.sum(torch.conj(bgrad) * b_real0).real)
     return {"workload": "adjoint-lmax512-kmax32-scan1e8", "n_samples": n,
             "forward_ms": fms, "adjoint_ms": ams, "adjoint_value": n / (ams * 1e-3),
             "adjoint_stages_ms": {k: t / 4 for k, (t, c) in st.items() if c},
-            "dot_test_rel": abs(lhs - rhs) / abs(lhs)}
+            "dot_test_rel": abs(lhs - rhs) / abs(lhs),
+            "beam_adjoint_ms": bms, "beam_dot_test_rel": abs(lhs - rhs_b) / abs(lhs)}
 
 
 def extra_dipole(torch, api, W, dev, no_oracle):

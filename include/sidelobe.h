@@ -167,6 +167,23 @@ int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, con
                         double *alm_grad);
 
 /*
+ * Adjoint with respect to the beam coefficients: for a TOD gradient y it returns
+ * h_lk = dL/dRe(b_lk) + i dL/dIm(b_lk) of L = sum_t y_t c_t (h_l0 real), i.e.
+ * <y, c> = Re sum_{l, k >= 0} conj(h_lk) b_lk with Im b_l0 ignored.  The TOD is
+ * bilinear in (a, b): the scatter and the adjoint transforms are those of
+ * sc_convolve_adjoint, and the adjoint ring sums contract with the sky instead
+ * of the beam (summing over m instead of k).
+ *   alm       device complex128, the sky in the plan's sky layout (SC_PARAM_SKY_LMAX).
+ *   ptg       device float64 [n][3].
+ *   tod_grad  device float64 [n] (SC_FP64) or float32 [n].
+ *   blm_grad  device complex128, blm layout of (lmax, kmax) (overwritten).
+ * Allocates (lmax+1) n_blm complex128 of plan workspace on first use.  Same
+ * stream, rounding and buffer behaviour as sc_convolve_adjoint.
+ */
+int sc_convolve_adjoint_beam(sc_plan *plan, const double *alm, const double *ptg, const void *tod_grad, int64_t n,
+                             double *blm_grad);
+
+/*
  * Orbital dipole and quadrupole through the full beam (Galloway et al. 2022,
  * Sec. 3.3, Eqs. 14-19): for the kinematic sky D(n) = T0 [beta.n + q (beta.n)^2]
  * the convolution at pointing (theta, phi, psi) is T0 [u.S + q u^T S2 u] with

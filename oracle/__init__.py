@@ -141,3 +141,38 @@ def adjoint(blm, lmax: int, kmax: int, ptg, y, nthreads: int = 0) -> np.ndarray:
     if rc != 0:
         raise ValueError("sco_adjoint failed: %d" % rc)
     return g.view(np.complex128)
+
+
+def beam_adjoint(alm, lmax: int, kmax: int, ptg, y) -> np.ndarray:
+    """h_lk = dL/dRe b_lk + i dL/dIm b_lk for L = sum_t y_t c_t (k >= 0; h_l0 real).
+
+    Eq. 2 with both signs of k, c = sum_{l, |k| <= kmax} conj(b_lk) X_lk with
+    X_lk(t) = sum_{|m| <= l} a_lm e^{i m phi_t} d^l_mk(theta_t) e^{i k psi_t}; the
+    real-field relations (Eq. 6) pair k and -k, so c = sum_l [b_l0 X_l0 +
+    2 sum_{k >= 1} Re(conj(b_lk) X_lk)] and h_lk = 2 sum_t y_t X_lk (k >= 1),
+    h_l0 = sum_t y_t Re X_l0.  Plain loops over samples (small cases only).
+    """
+    a = np.asarray(alm, dtype=np.complex128)
+    p = np.ascontiguousarray(ptg, dtype=np.float64).reshape(-1, 3)
+    yy = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    # all orders m of the real sky: a_{l,-m} = (-1)^m conj(a_lm)
+    A = np.zeros((lmax + 1, 2 * lmax + 1), dtype=np.complex128)
+    for m in range(lmax + 1):
+        for l in range(m, lmax + 1):
+            v = a[alm_index(lmax, l, m)]
+            if m == 0:
+                v = complex(v.real, 0.0)
+            A[l, m + lmax] = v
+            A[l, lmax - m] = (-1) ** m * np.conj(v)
+    ms = np.arange(-lmax, lmax + 1)
+    h = np.zeros(n_alm(lmax, kmax), dtype=np.complex128)
+    for t in range(p.shape[0]):
+        th, ph, ps = p[t]
+        d = wigner_d(lmax, kmax, th)  # [k + kmax, m + lmax, l]
+        em = np.exp(1j * ms * ph)
+        for k in range(kmax + 1):
+            X = np.einsum("lm,m,ml->l", A, em, d[k + kmax]) * np.exp(1j * k * ps)
+            for l in range(k, lmax + 1):
+                h[k * (2 * lmax + 1 - k) // 2 + l] += yy[t] * (
+                    2.0 * X[l] if k > 0 else X[l].real)
+    return h

@@ -160,6 +160,27 @@ class Plan:
                                               out.data_ptr()), "sc_convolve_adjoint")
         return out
 
+    def adjoint_beam(self, alm: torch.Tensor, ptg: torch.Tensor, tod_grad: torch.Tensor,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """sc_convolve_adjoint_beam: h_lk = dL/dRe b_lk + i dL/dIm b_lk of L = sum_t y_t c_t (complex128)."""
+        _dev(alm, "alm", torch.complex128)
+        _dev(ptg, "ptg", torch.float64)
+        _dev(tod_grad, "tod_grad", self.tod_dtype)
+        if alm.numel() != n_alm(self.get_param("sky_lmax")):
+            raise ValueError("alm size does not match the plan's sky layout")
+        n = ptg.shape[0]
+        if tod_grad.numel() != n:
+            raise ValueError("tod_grad has %d entries, need %d" % (tod_grad.numel(), n))
+        if out is None:
+            out = torch.empty(n_alm(self.lmax, self.kmax), dtype=torch.complex128, device=ptg.device)
+        _dev(out, "blm_grad", torch.complex128)
+        if out.numel() != n_alm(self.lmax, self.kmax):
+            raise ValueError("blm_grad size does not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
+        self.set_stream()
+        N.check(self._lib.sc_convolve_adjoint_beam(self._p, alm.data_ptr(), ptg.data_ptr(), tod_grad.data_ptr(), n,
+                                                   out.data_ptr()), "sc_convolve_adjoint_beam")
+        return out
+
     STAGES = ("ring_sums", "theta_upsample", "phi_synthesis", "gather", "binning", "scatter",
               "adjoint_transforms", "adjoint_ring_sums")
 

@@ -18,6 +18,15 @@
 // waves of a workgroup are the groups of one (k, m) and are combined in LDS.
 // Per-k contributions go to GA[k][alm index]; a second kernel sums over k in a
 // fixed order (deterministic).
+//
+// The same Q+- give the gradient with respect to the beam (BEAM = true): the
+// TOD is bilinear, and with the sky gradient above L = Re sum conj(g_lm) a_lm
+// is, as a function of b,
+//     L = Re sum_{l,k,m>0} [conj(b_lk) conj(Q+) a_lm + b_lk (-1)^{l+k+m} Q- a_lm]
+//       + Re sum_{l,k} b_lk Q+(m = 0) a_l0,
+// so h_lk = dL/dRe b_lk + i dL/dIm b_lk = sum_m [conj(Q+) a_lm +
+// (-1)^{l+k+m} conj(Q- a_lm)] (the Q- term for m > 0), real for k = 0.  Per-m
+// contributions go to GB[m][blm index] and are summed over m in a fixed order.
 #include "wigner_rec.h"
 
 namespace {
@@ -27,12 +36,13 @@ using namespace wrec;
 constexpr int ADJ_FLUSH = 8;   // l steps per LDS flush
 constexpr int ADJ_ROW = 65;    // padded row length (doubles) of the partial buffer
 
-template <int RPT>
+template <int RPT, bool BEAM>
 __global__ void __launch_bounds__(1024)
-k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ blm, double2 *__restrict__ GA,
+k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ coefs, double2 *__restrict__ GA,
                     const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
-            const double *__restrict__ rtab, int lmax, int kmax,
-                    int nring) {
+                    const double *__restrict__ rtab, int lmax, int kmax, int nring, int alm_lmax) {
+    // coefs: the beam b_lk (sky gradient into GA[k]) or, with BEAM, the sky a_lm
+    // in the alm_lmax layout (beam gradient into GA[m], blm layout)
     extern __shared__ __attribute__((aligned(16))) double adj_smem[];
     const int nw = blockDim.x >> 6;
     double *cA = adj_smem, *cB = cA + 64, *cC = cB + 64;                   // [64]
@@ -47,9 +57,12 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     const int nm = 2 * lmax + 1;
     const size_t aoff = (size_t)m * (2 * lmax + 1 - m) / 2;
     const size_t nalm = (size_t)(lmax + 1) * (lmax + 2) / 2;
-    double2 *gk = GA + (size_t)k * nalm + aoff;
+    const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
+    const size_t nblm = (size_t)(kmax + 1) * (2 * lmax + 2 - kmax) / 2;
+    // output column: (l, m) of GA[k] for the sky gradient, (l, k) of GA[m] for the beam
+    double2 *gk = BEAM ? GA + (size_t)m * nblm + boff : GA + (size_t)k * nalm + aoff;
     // orders below l0 have no d^l_mk: their contribution is zero
-    for (int l = m + tid; l < l0 && l <= lmax; l += blockDim.x) gk[l] = make_double2(0.0, 0.0);
+    for (int l = (BEAM ? k : m) + tid; l < l0 && l <= lmax; l += blockDim.x) gk[l] = make_double2(0.0, 0.0);
     if (l0 > lmax) return;
 
     double x[RPT], d[RPT], dp[RPT];
@@ -142,20 +155,46 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
                 q2 += qq[2];
                 q3 += qq[3];
             }
-            double2 bb = blm[(size_t)k * (2 * lmax + 1 - k) / 2 + l];
-            if (k == 0) bb.y = 0.0;
-            const double2 gp = cmul(make_double2(q0, q1), bb);
+            const double sg = ((l + k + m) & 1) ? -1.0 : 1.0;
             double2 g;
-            if (m == 0) {
-                g = make_double2(gp.x, 0.0);
+            if constexpr (BEAM) {
+                double2 aa = coefs[(size_t)m * (2 * alm_lmax + 1 - m) / 2 + l];
+                if (m == 0) aa.y = 0.0;
+                g = cmul(make_double2(q0, -q1), aa);  // conj(Q+) a
+                if (m > 0) {
+                    const double2 t = cmul(make_double2(q2, q3), aa);  // Q- a
+                    g.x += sg * t.x;
+                    g.y -= sg * t.y;
+                }
             } else {
-                const double2 gm = cmul(make_double2(q2, q3), bb);
-                const double sg = ((l + k + m) & 1) ? -1.0 : 1.0;
-                g = make_double2(gp.x + sg * gm.x, gp.y - sg * gm.y);
+                double2 bb = coefs[boff + l];
+                if (k == 0) bb.y = 0.0;
+                const double2 gp = cmul(make_double2(q0, q1), bb);
+                if (m == 0) {
+                    g = make_double2(gp.x, 0.0);
+                } else {
+                    const double2 gm = cmul(make_double2(q2, q3), bb);
+                    g = make_double2(gp.x + sg * gm.x, gp.y - sg * gm.y);
+                }
             }
             gk[l] = g;
         }
     }
+}
+
+// grad[i] = sum_m GB[m][i] in increasing m over the blm layout; the k = 0
+// column (entries i <= lmax) is real.
+__global__ void k_reduce_over_m(const double2 *__restrict__ GB, double2 *__restrict__ grad, int64_t nblm, int lmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nblm) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int m = 0; m <= lmax; ++m) {
+        const double2 v = GB[(size_t)m * nblm + i];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    if (i <= lmax) s.y = 0.0;
+    grad[i] = s;
 }
 
 // grad[i] = sum_k GA[k][i] in increasing k (entries with k > l are zero).
@@ -200,14 +239,14 @@ static void adj_layout(int nring, int *rpt, int *nw) {
 
 #define SC_ADJ_CASE(R)                                                                                       \
     case R: {                                                                                                \
-        auto kern = k_ring_sums_adjoint<R>;                                                                  \
-        e = sc_set_lds_attr((const void *)kern, lds);   \
+        auto kern = beam ? k_ring_sums_adjoint<R, true> : k_ring_sums_adjoint<R, false>;                      \
+        e = sc_set_lds_attr((const void *)kern, lds);                                                        \
         if (e != hipSuccess) return e;                                                                       \
-        hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)blm,      \
-                           p->GA, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring);                          \
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)coefs,    \
+                           out, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring, p->alm_lmax);     \
     } break;
 
-hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad) {
+static hipError_t ring_sums_adjoint(sc_plan *p, const double *coefs, double2 *out, bool beam) {
     int rpt, nw;
     adj_layout(p->nring, &rpt, &nw);
     const int nblk = (p->lmax + 1) * (p->kmax + 1);
@@ -220,10 +259,23 @@ hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *gr
         default:
         SC_ADJ_CASE(4)
     }
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad) {
+    hipError_t e = ring_sums_adjoint(p, blm, p->GA, false);
     if (e != hipSuccess) return e;
     const int64_t nalm = (int64_t)(p->lmax + 1) * (p->lmax + 2) / 2;
     hipLaunchKernelGGL(k_reduce_over_k, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, p->stream, p->GA,
                        (double2 *)grad, nalm, p->kmax);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, double *grad) {
+    hipError_t e = ring_sums_adjoint(p, alm, p->GB, true);
+    if (e != hipSuccess) return e;
+    const int64_t nblm = (int64_t)(p->kmax + 1) * (2 * p->lmax + 2 - p->kmax) / 2;
+    hipLaunchKernelGGL(k_reduce_over_m, dim3((unsigned)((nblm + 255) / 256)), dim3(256), 0, p->stream, p->GB,
+                       (double2 *)grad, nblm, p->lmax);
     return hipGetLastError();
 }

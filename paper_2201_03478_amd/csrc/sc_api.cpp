@@ -187,6 +187,8 @@ void free_plan_buffers(sc_plan *p) {
     free_bin_work(p->bw);
     if (p->gmaps) (void)hipFree(p->gmaps);
     if (p->GA) (void)hipFree(p->GA);
+    if (p->GB) (void)hipFree(p->GB);
+    p->GB = nullptr;
     p->gmaps = nullptr;
     p->GA = nullptr;
     for (int i = 0; i < p->tl_cap; ++i) {
@@ -584,18 +586,10 @@ int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg,
     return e != hipSuccess ? hip_fail(e, "dipole launch") : SC_OK;
 }
 
-int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
-                        double *alm_grad) {
-    g_msg[0] = 0;
-    if (!p) return fail(SC_EINVAL, "plan is NULL");
-    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
-    if (!is_device_ptr(blm)) return fail(SC_EINVAL, "blm is not device memory");
-    if (!is_device_ptr(alm_grad)) return fail(SC_EINVAL, "alm_grad is not device memory");
-    if (n > 0 && (!is_device_ptr(ptg) || !is_device_ptr(tod_grad)))
-        return fail(SC_EINVAL, "ptg/tod_grad is not device memory");
-    if (((uintptr_t)blm & 15) || ((uintptr_t)alm_grad & 15)) return fail(SC_EINVAL, "blm/alm_grad not 16-byte aligned");
-    if (n > 0 && (((uintptr_t)ptg & 7) || ((uintptr_t)tod_grad & (p->prec == SC_FP64 ? 7 : 3))))
-        return fail(SC_EINVAL, "ptg/tod_grad misaligned");
+// The part of the adjoint that depends on neither coefficient set: scatter of the
+// TOD gradient onto gradient maps, then the adjoint phi and theta transforms
+// (ring-sum gradients in p->F).
+static int adjoint_to_rings(sc_plan *p, const double *ptg, const void *tod_grad, int64_t n) {
     const size_t map_bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
     const size_t nalm = (size_t)(p->lmax + 1) * (p->lmax + 2) / 2;
     if (!p->gmaps) {
@@ -643,10 +637,56 @@ int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const 
     if (e == hipSuccess) e = sc_launch_theta_adjoint(p);
     timing_end(p, slot);
     if (e != hipSuccess) return hip_fail(e, "adjoint transform launch");
-    slot = timing_begin(p, SC_STAGE_ADJ_RING);
-    e = sc_launch_ring_sums_adjoint(p, blm, alm_grad);
+    return SC_OK;
+}
+
+static int check_adjoint_args(sc_plan *p, const double *coefs, const double *ptg, const void *tod_grad, int64_t n,
+                              double *grad) {
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (!is_device_ptr(coefs)) return fail(SC_EINVAL, "coefficients are not device memory");
+    if (!is_device_ptr(grad)) return fail(SC_EINVAL, "gradient output is not device memory");
+    if (n > 0 && (!is_device_ptr(ptg) || !is_device_ptr(tod_grad)))
+        return fail(SC_EINVAL, "ptg/tod_grad is not device memory");
+    if (((uintptr_t)coefs & 15) || ((uintptr_t)grad & 15)) return fail(SC_EINVAL, "coefficients/gradient not 16-byte aligned");
+    if (n > 0 && (((uintptr_t)ptg & 7) || ((uintptr_t)tod_grad & (p->prec == SC_FP64 ? 7 : 3))))
+        return fail(SC_EINVAL, "ptg/tod_grad misaligned");
+    return SC_OK;
+}
+
+int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
+                        double *alm_grad) {
+    g_msg[0] = 0;
+    int rc = check_adjoint_args(p, blm, ptg, tod_grad, n, alm_grad);
+    if (rc) return rc;
+    rc = adjoint_to_rings(p, ptg, tod_grad, n);
+    if (rc) return rc;
+    const int slot = timing_begin(p, SC_STAGE_ADJ_RING);
+    const hipError_t e = sc_launch_ring_sums_adjoint(p, blm, alm_grad);
     timing_end(p, slot);
     if (e != hipSuccess) return hip_fail(e, "adjoint ring-sum launch");
+    return SC_OK;
+}
+
+int sc_convolve_adjoint_beam(sc_plan *p, const double *alm, const double *ptg, const void *tod_grad, int64_t n,
+                             double *blm_grad) {
+    g_msg[0] = 0;
+    int rc = check_adjoint_args(p, alm, ptg, tod_grad, n, blm_grad);
+    if (rc) return rc;
+    if (!p->GB) {
+        const size_t nblm = (size_t)(p->kmax + 1) * (2 * p->lmax + 2 - p->kmax) / 2;
+        size_t tot = 0;
+        rc = alloc((void **)&p->GB, sizeof(double2) * (size_t)(p->lmax + 1) * nblm, &tot);
+        if (rc) return rc;
+        p->adj_bytes += tot;
+        p->ws_bytes += tot;
+    }
+    rc = adjoint_to_rings(p, ptg, tod_grad, n);
+    if (rc) return rc;
+    const int slot = timing_begin(p, SC_STAGE_ADJ_RING);
+    const hipError_t e = sc_launch_ring_sums_adjoint_beam(p, alm, blm_grad);
+    timing_end(p, slot);
+    if (e != hipSuccess) return hip_fail(e, "beam adjoint ring-sum launch");
     return SC_OK;
 }
 

@@ -122,6 +122,7 @@ struct sc_plan {
     BinWork bw;
     void *gmaps;       // adjoint: gradient maps, same layout as maps (allocated on first use)
     double2 *GA;       // adjoint: per-k gradient contributions [kmax+1][n_alm]
+    double2 *GB;       // beam adjoint: per-m gradient contributions [lmax+1][n_blm] (allocated on first use)
     size_t adj_bytes;
     int alm_lmax;          // band limit of the sky array's layout (>= lmax; a shared sky may be larger)
     int bin_fixed;         // binning buffers are referenced by a batch: never reallocate them
@@ -160,6 +161,7 @@ hipError_t sc_launch_phi_synthesis(sc_plan *p);
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps);
 hipError_t sc_launch_theta_adjoint(sc_plan *p);
 hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad);
+hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, double *grad);
 hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps);
 hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps);
 bool sc_scatter_binned_supported(const sc_plan *p);

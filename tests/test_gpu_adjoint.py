@@ -142,3 +142,43 @@ def test_adjoint_workload_full_size(env):
         worst = max(worst, abs(fd - g[i].real) / scale)
     print("full-size FD worst %.3e (relative to max |g|)" % worst)
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("f64maps_f32gather", 1e-5)])
+@pytest.mark.parametrize("L,K,n", [(20, 5, 300), (24, 0, 200), (16, 16, 250)])
+def test_beam_adjoint_matches_oracle(env, oracle_lib, prec, tol, L, K, n):
+    """Gradient with respect to b_lk (sc_convolve_adjoint_beam) against the oracle's direct form."""
+    torch, api, dev = env
+    a = W.sky_alm(L, 4400 + L)
+    p = W.uniform_pointings(n, 4500 + L)
+    p[0] = [0.0, 0.2, 0.3]
+    y = np.random.default_rng(4600 + L).standard_normal(n)
+    plan = api.Plan(L, K, prec)
+    yt = _to(torch, dev, y).to(plan.tod_dtype)
+    h = plan.adjoint_beam(_to(torch, dev, a), _to(torch, dev, p), yt).cpu().numpy()
+    ref = oracle_lib.beam_adjoint(a, L, K, p, yt.double().cpu().numpy())
+    e = _rel(h, ref)
+    print("beam adjoint %s L=%d K=%d rel %.3e" % (prec, L, K, e))
+    assert e <= tol
+    assert np.all(h[:L + 1].imag == 0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f64maps_f32gather", 1e-5)])
+def test_beam_adjoint_dot_product(env, prec, tol):
+    """<y, A(b)> = Re sum conj(h) b against the GPU forward with the same sky, larger size."""
+    torch, api, dev = env
+    L, K, n = 64, 12, 50000
+    a = W.sky_alm(L, 61)
+    b = W.beam_alm(L, K, 62)
+    b[:L + 1] = b[:L + 1].real
+    at, bt = _to(torch, dev, a), _to(torch, dev, b)
+    p = _to(torch, dev, W.uniform_pointings(n, 63))
+    plan = api.Plan(L, K, prec)
+    y = torch.randn(n, generator=torch.Generator().manual_seed(64), dtype=torch.float64).to(dev).to(plan.tod_dtype)
+    plan.set_sky_beam(at, bt)
+    lhs = float(torch.dot(plan.interpolate(p).double(), y.double()))
+    h = plan.adjoint_beam(at, p, y).cpu().numpy()
+    rhs = float(np.real(np.sum(np.conj(h) * b)))
+    e = abs(lhs - rhs) / abs(lhs)
+    print("beam dot test %s: %.3e" % (prec, e))
+    assert e <= tol

@@ -323,3 +323,27 @@ def test_adjoint_dot_product_and_finite_difference(oracle_lib):
             fd = (y @ oracle_lib.convolve(a + h * e, b, L, K, p) - y @ oracle_lib.convolve(a - h * e, b, L, K, p)) / (2 * h)
             ref = g[idx].real if part == "re" else g[idx].imag
             assert abs(fd - ref) < 1e-9 * max(1.0, abs(ref)), (idx, part)
+
+
+def test_P9_beam_gradient_dot_identity_and_difference(oracle_lib):
+    """The beam-gradient oracle is the transpose of the forward sum in b: sum_t y_t c_t(a, b) =
+    Re sum conj(h_lk) b_lk (c is linear in b), and a finite difference in one b_lk agrees."""
+    L, K, n = 10, 3, 30
+    a = W.sky_alm(L, 41)
+    b = W.beam_alm(L, K, 42)
+    b[:L + 1] = b[:L + 1].real  # the k = 0 column is real
+    p = W.uniform_pointings(n, 43)
+    y = _rng(44).standard_normal(n)
+    h = oracle_lib.beam_adjoint(a, L, K, p, y)
+    c = oracle_lib.convolve(a, b, L, K, p)
+    assert abs(float(y @ c) - float(np.real(np.vdot(h, b)))) < 1e-12 * abs(float(y @ c))
+    for (l, k) in ((4, 2), (7, 0)):
+        i = k * (2 * L + 1 - k) // 2 + l
+        for comp, unit in ((0, 1.0), (1, 1j)):
+            if k == 0 and comp == 1:
+                continue
+            e = np.zeros_like(b)
+            e[i] = unit
+            dlin = float(y @ (oracle_lib.convolve(a, b + e, L, K, p) - c))  # exact: c is linear in b
+            ref = h[i].real if comp == 0 else h[i].imag
+            assert abs(dlin - ref) < 1e-12 * max(1.0, abs(ref)), (l, k, comp)
