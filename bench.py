@@ -301,7 +301,7 @@ def main():
 
     if not args.no_extras:
         for name, fn in (("precision_variant", extra_precision), ("adjoint", extra_adjoint),
-                         ("batched", extra_batched), ("dipole", extra_dipole)):
+                         ("batched", extra_batched), ("dipole", extra_dipole), ("psi_cube", extra_psi_cube)):
             try:
                 result[name] = fn(torch, api, W, dev, args.no_cpu_baseline)
             except Exception as exc:  # an extra must not lose the headline line
@@ -410,6 +410,54 @@ def extra_dipole(torch, api, W, dev, no_oracle):
             "unit": "samples/s", "roofline": {"bound": "hbm", "achieved": bytes_per / (ms * 1e-3) / 1e9,
                                               "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                                               "frac": bytes_per / (ms * 1e-3) / PEAK["hbm"]}}
+
+
+def _next_smooth(n):
+    def smooth(m):
+        for q in (2, 3, 5):
+            while m % q == 0:
+                m //= q
+        return m == 1
+    while not smooth(n):
+        n += 1
+    return n
+
+
+def extra_psi_cube(torch, api, W, dev, no_oracle):
+    """The paper's second step on the lmax 512 / kmax 100 workload: the psi cube built from the
+    maps (one inverse FFT over k per pixel pair), then W^3 interpolation per sample on the 1e7
+    scan samples; compared with the exact cos/sin k-sum gather on the same maps."""
+    cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    a_np = W.sky_alm(L, W.config_seed(2, 1))
+    b_np = W.beam_alm(L, K, W.config_seed(2, 2), kind="sidelobe")
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    plan.set_sky_beam(torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev))
+    ptg = W.scan_pointings(n, device=dev)
+    info = plan.info()
+    Wk = 8
+    npsi = _next_smooth(max(2 * (2 * K + 1), 2 * Wk))
+    npst = (npsi + Wk - 1 + 3) // 4 * 4
+    cube_ms = _event_ms(torch, lambda: plan.build_psi_cube(), 5)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    gather_ms = _event_ms(torch, lambda: plan.interpolate_psi(ptg, out=out), 5)
+    exact = torch.empty(n, dtype=torch.float32, device=dev)
+    ksum_ms = _event_ms(torch, lambda: plan.interpolate(ptg, out=exact), 5)
+    d = float(torch.linalg.vector_norm((out - exact).double()) / torch.linalg.vector_norm(exact.double()))
+    npix = info["map_rows"] * info["map_cols"]
+    cube_bytes = 4.0 * npix * ((2 * K + 2) + npst)  # component maps read, cube written
+    res = {"workload": "psi-cube-lmax512-kmax100-scan1e7", "n_samples": n, "npsi": npsi,
+           "cube_gb": 4.0 * npix * npst / 1e9, "cube_build_ms": cube_ms, "gather_ms": gather_ms,
+           "value": n / (gather_ms * 1e-3), "unit": "samples/s", "ksum_gather_ms": ksum_ms,
+           "rel_l2_vs_ksum_path": d,
+           "cube_roofline": {"bound": "hbm", "achieved": cube_bytes / (cube_ms * 1e-3) / 1e9,
+                             "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                             "frac": cube_bytes / (cube_ms * 1e-3) / PEAK["hbm"]},
+           "gather_fma_per_sample": Wk ** 3 + Wk ** 2 + Wk}
+    if not no_oracle:
+        res["rel_err_vs_oracle"] = _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, out, 16, W.config_seed(2, 8))
+    plan.close()
+    return res
 
 
 def extra_batched(torch, api, W, dev, no_oracle):

@@ -130,6 +130,31 @@ int sc_set_sky_beam(sc_plan *plan, const double *alm, const double *blm);
 int sc_interpolate(sc_plan *plan, const double *ptg, int64_t n, void *tod);
 
 /*
+ * The second step of the two-step algorithm (Sec. 2.1): the Fourier series over
+ * k of the plan's current component maps, evaluated on a grid of npsi points in
+ * psi at every (theta, phi) grid point and divided by the interpolation
+ * kernel's transform along psi, giving the real cube c(theta, phi, psi).
+ * npsi = 0 picks the smallest product of 2, 3 and 5 >= max(2 (2 kmax + 1), 2 W);
+ * an explicit npsi must be such a product in [that bound, 512], else
+ * SC_EINVAL.  The cube (rows x cols x (npsi + W - 1 rounded up to 4) values of
+ * the map type, about 2 npsi / (2 kmax + 2) times the maps) is allocated by the
+ * plan on the first call or when npsi changes, and freed with the plan; a call
+ * before sc_set_sky_beam returns SC_ESTATE.  A later sc_set_sky_beam or
+ * sc_plan_convolve invalidates the cube.  Asynchronous on the plan's stream.
+ */
+int sc_plan_build_psi_cube(sc_plan *plan, int npsi);
+
+/*
+ * Evaluate the convolution at n pointings by interpolating the cube in theta,
+ * phi and psi with the same kernel (W^3 cube values per sample).  It
+ * approximates the same quantity as sc_interpolate, with the kernel's error
+ * in psi added.  ptg: device float64 [n][3]; tod: device float64/float32 [n]
+ * (the map type).  Without a cube of the current maps: SC_ESTATE; host memory
+ * or misaligned pointers: SC_EINVAL.  n = 0 is a no-op.
+ */
+int sc_interpolate_psi(sc_plan *plan, const double *ptg, int64_t n, void *tod);
+
+/*
  * sc_set_sky_beam followed by sc_interpolate, as one call: the pointing binning
  * of the first pass (it needs only ptg) runs on a plan-owned side stream while
  * the maps are synthesised, and joins the plan's stream before the gather.

@@ -118,6 +118,28 @@ class Plan:
             N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
         return out
 
+    def build_psi_cube(self, npsi: int = 0):
+        """The paper's second step: the cube c(theta, phi, psi) from the current maps
+        (npsi = 0: the smallest 2,3,5-smooth size >= 2 (2 kmax + 1))."""
+        self.set_stream()
+        N.check(self._lib.sc_plan_build_psi_cube(self._p, int(npsi)), "sc_plan_build_psi_cube")
+
+    def interpolate_psi(self, ptg: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """The convolution at ptg by three-dimensional interpolation of the cube."""
+        _dev(ptg, "ptg", torch.float64)
+        if ptg.dim() != 2 or ptg.shape[1] != 3:
+            raise ValueError("ptg must be [n, 3]")
+        n = ptg.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
+        _dev(out, "tod", self.tod_dtype)
+        if out.numel() != n:
+            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
+        self.set_stream()
+        if n:
+            N.check(self._lib.sc_interpolate_psi(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate_psi")
+        return out
+
     def convolve(self, alm: torch.Tensor, blm: torch.Tensor, ptg: torch.Tensor,
                  out: torch.Tensor | None = None) -> torch.Tensor:
         """set_sky_beam + interpolate in one call (sc_plan_convolve: the pointing

@@ -1,0 +1,174 @@
+// k_psi.hip -- the paper's second step: the cube c(theta, phi, psi) on a psi
+// grid, and three-dimensional interpolation of it at the pointings.
+//
+// The two-step algorithm of Galloway et al. 2022 (Sec. 2.1) first builds, for
+// every k, the spin-k map, and then takes, on every (theta, phi) grid point, the
+// Fourier series over k onto a grid in psi, so that the signal at any pointing
+// is an interpolation of one real cube.  Here the psi grid has npsi points,
+// psi_j = 2 pi j / npsi with npsi >= 2 (2 kmax + 1) (the same twofold
+// oversampling as the phi grid), and the series is divided by the transform
+// of the interpolation kernel so that interpolating the cube with it
+// reproduces the series (the deconvolution of Sec. 2.1 applied along psi):
+//     cube(r, q, j) = sum_{k <= kmax} g_k (M_2k(r, q) cos k psi_j + M_2k+1(r, q) sin k psi_j),
+//     g_k = 1 / hhat_psi(k),
+// with M_c the stored component maps (cos / sin pair of k at 2k, 2k + 1).
+//
+// Cube layout: [row][col][npst], psi fastest.  Entry s of a pixel holds grid
+// point (s - W/2 + 1) mod npsi for s < npsi + W - 1 (a periodic halo, so the W
+// psi nodes of a sample are W consecutive values), zero beyond.
+//
+// Build: one wave per two pixels.  The series of a pixel is real, so its
+// spectrum is Hermitian: Y(k) = g_k (M_2k - i M_2k+1) / 2 at +k, the conjugate at
+// -k, g_0 M_0 at 0.  Two pixels a, b share one complex inverse transform of
+// X = Y_a + i Y_b, whose output is c_a + i c_b.  The transform is the LDS
+// Stockham FFT (fft_lds.h) in FP64; values are stored in the map type.
+#include "fft_lds.h"
+
+namespace {
+
+constexpr int PSI_NT = 64;  // one wave per transform
+constexpr int PSI_PT = 8;   // npsi <= 512
+
+template <typename T>
+__global__ void __launch_bounds__(PSI_NT)
+k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int ncp, int kmax, int npsi, int npst,
+           int W, FftPlan P, const double2 *__restrict__ tw, const double *__restrict__ gpsi) {
+    __shared__ double2 buf[PSI_NT * PSI_PT];
+    const int tid = threadIdx.x;
+    const int half = W / 2;
+    const int ext = npsi + W - 1;
+    for (int64_t pair = blockIdx.x; 2 * pair < npix; pair += gridDim.x) {
+        const int64_t a = 2 * pair, b = a + 1;
+        const bool hb = b < npix;
+        const T *ma = maps + a * ncp, *mb = maps + (hb ? b : a) * ncp;
+        for (int t = tid; t < npsi; t += PSI_NT) {
+            const int k = t <= kmax ? t : (t >= npsi - kmax ? npsi - t : -1);
+            double2 x = make_double2(0.0, 0.0);
+            if (k >= 0) {
+                const double g = k == 0 ? gpsi[0] : 0.5 * gpsi[k];
+                const double sg = t <= kmax ? 1.0 : -1.0;  // +k: M_2k - i M_2k+1; -k: its conjugate
+                const double ca = (double)ma[2 * k], sa = (double)ma[2 * k + 1];
+                const double cb = hb ? (double)mb[2 * k] : 0.0, sb = hb ? (double)mb[2 * k + 1] : 0.0;
+                x = make_double2(g * (ca + sg * sb), g * (cb - sg * sa));
+            }
+            buf[t] = x;
+        }
+        __syncthreads();
+        fft_lds<+1, PSI_NT, PSI_PT>(buf, P, tw, tid, PSI_NT);
+        for (int s = tid; s < npst; s += PSI_NT) {
+            int j = s - half + 1;
+            j = j < 0 ? j + npsi : (j >= npsi ? j - npsi : j);
+            const double2 v = s < ext ? buf[j] : make_double2(0.0, 0.0);
+            cube[a * npst + s] = (T)v.x;
+            if (hb) cube[b * npst + s] = (T)v.y;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T es_w(T z, T beta) {
+    const T q = (T)1 - z * z;
+    return q > (T)0 ? exp(beta * (sqrt(q) - (T)1)) : (T)0;
+}
+
+// Grid coordinate in [0, n) of an angle on a periodic grid of n points.
+__device__ __forceinline__ double periodic_coord(double a, double inv_h, int n) {
+    const double two_pi = 6.283185307179586477;
+    double v = (a - two_pi * floor(a / two_pi)) * inv_h;
+    if (!(v < (double)n)) v = 0.0;  // 2 pi rounding, NaN
+    return v < 0.0 ? 0.0 : v;
+}
+
+// One thread per sample: W^3 products of separable kernel weights with the cube.
+// Grid indices and fractional offsets in FP64, as in the two-dimensional gather.
+template <typename T, int W>
+__global__ void __launch_bounds__(256)
+k_gather_psi(const double *__restrict__ ptg, int64_t n, const T *__restrict__ cube, T *__restrict__ tod, int cols,
+             int npst, double beta, double inv_hth, double inv_hph, double inv_hps, int n2os, int nphi, int npsi) {
+    constexpr int half = W / 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const double th = ptg[3 * s], ph = ptg[3 * s + 1], ps = ptg[3 * s + 2];
+        double u = th * inv_hth;
+        u = fmin(fmax(u, 0.0), 0.5 * (double)n2os);
+        const int r0 = (int)floor(u) - half + 1;
+        const double v = periodic_coord(ph, inv_hph, nphi);
+        const int q0 = (int)floor(v) - half + 1;
+        const double x = periodic_coord(ps, inv_hps, npsi);
+        const int p0 = (int)floor(x) - half + 1;
+        T wt[W], wp[W], wq[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            wt[i] = es_w<T>((T)((u - (double)(r0 + i)) / half), (T)beta);
+            wp[i] = es_w<T>((T)((v - (double)(q0 + i)) / half), (T)beta);
+            wq[i] = es_w<T>((T)((x - (double)(p0 + i)) / half), (T)beta);
+        }
+        const T *base = cube + ((size_t)(r0 + half - 1) * cols + (size_t)(q0 + half - 1)) * npst + (p0 + half - 1);
+        T acc = (T)0;
+        for (int i = 0; i < W; ++i) {
+            T ai = (T)0;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const T *c = base + ((size_t)i * cols + j) * npst;
+                T t = (T)0;
+#pragma unroll
+                for (int l = 0; l < W; ++l) t += wq[l] * c[l];
+                ai += wp[j] * t;
+            }
+            acc += wt[i] * ai;
+        }
+        tod[s] = acc;
+    }
+}
+
+template <typename T, int W>
+void launch_gather_psi(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk) {
+    const double two_pi = 6.283185307179586477;
+    hipLaunchKernelGGL((k_gather_psi<T, W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n, (const T *)p->cube,
+                       (T *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi, (double)p->nphi / two_pi,
+                       (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi);
+}
+
+template <typename T>
+void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk) {
+    switch (p->W) {
+        case 4: launch_gather_psi<T, 4>(p, ptg, n, tod, nblk); break;
+        case 6: launch_gather_psi<T, 6>(p, ptg, n, tod, nblk); break;
+        case 8: launch_gather_psi<T, 8>(p, ptg, n, tod, nblk); break;
+        case 10: launch_gather_psi<T, 10>(p, ptg, n, tod, nblk); break;
+        case 12: launch_gather_psi<T, 12>(p, ptg, n, tod, nblk); break;
+        case 14: launch_gather_psi<T, 14>(p, ptg, n, tod, nblk); break;
+        default: launch_gather_psi<T, 16>(p, ptg, n, tod, nblk); break;
+    }
+}
+
+}  // namespace
+
+int sc_psi_max_len() { return PSI_NT * PSI_PT; }
+
+hipError_t sc_launch_psi_cube(sc_plan *p) {
+    const int64_t npix = (int64_t)p->rows * p->cols;
+    const int64_t npairs = (npix + 1) / 2;
+    const unsigned nblk = (unsigned)(npairs < 32768 ? npairs : 32768);
+    if (p->prec == SC_FP64)
+        hipLaunchKernelGGL(k_psi_cube<double>, dim3(nblk), dim3(PSI_NT), 0, p->stream, (const double *)p->maps,
+                           (double *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi,
+                           p->gpsi);
+    else
+        hipLaunchKernelGGL(k_psi_cube<float>, dim3(nblk), dim3(PSI_NT), 0, p->stream, (const float *)p->maps,
+                           (float *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi,
+                           p->gpsi);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+    if (n == 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    if (p->prec == SC_FP64)
+        launch_gather_psi_w<double>(p, ptg, n, tod, (unsigned)nb);
+    else
+        launch_gather_psi_w<float>(p, ptg, n, tod, (unsigned)nb);
+    return hipGetLastError();
+}

@@ -99,6 +99,13 @@ __global__ void k_deconv(double2 *phase, double *dphi, int lmax, int n2, int n2o
     if (t <= lmax) dphi[t] = 1.0 / kernel_transform((double)t, two_pi / nphi, W, beta, glx, glw, nq);
 }
 
+// psi deconvolution: 1 / hhat(k) for the kernel on the npsi-point psi grid.
+__global__ void k_psi_deconv(double *gpsi, int kmax, int npsi, int W, double beta, const double *glx,
+                             const double *glw, int nq) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k <= kmax) gpsi[k] = 1.0 / kernel_transform((double)k, 6.283185307179586477 / npsi, W, beta, glx, glw, nq);
+}
+
 // Recursion roots: at [x][l], sqrt((l+1)^2 - x^2) and its reciprocal (zero where
 // l + 1 <= x), so that the recursion coefficients of step l need one division.
 __global__ void k_rec_roots(double2 *t, int lmax) {
@@ -161,5 +168,13 @@ hipError_t sc_launch_tables(sc_plan *p) {
     hipLaunchKernelGGL(k_rec_roots, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, p->stream, p->rroot, p->lmax);
     hipLaunchKernelGGL(k_sqrt_binom, dim3((nb + 255) / 256), dim3(256), 0, p->stream, p->sbin_m, p->sbin_e,
                        p->lmax, p->kmax);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_psi_tables(sc_plan *p) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->npsi + bs - 1) / bs), dim3(bs), 0, p->stream, p->twpsi, p->ppsi);
+    hipLaunchKernelGGL(k_psi_deconv, dim3((p->kmax + 64) / 64), dim3(64), 0, p->stream, p->gpsi, p->kmax, p->npsi,
+                       p->W, p->beta, p->glx, p->glw, p->nq);
     return hipGetLastError();
 }

@@ -199,7 +199,7 @@ void free_plan_buffers(sc_plan *p) {
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
     void *bufs[] = {p->F, p->G, p->maps, p->rroot, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
-                    p->phase, p->dphi, p->glx, p->glw};
+                    p->phase, p->dphi, p->glx, p->glw, p->twpsi, p->gpsi, p->cube};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -446,6 +446,7 @@ int sc_set_sky_beam(sc_plan *p, const double *alm, const double *blm) {
     }
     if (e != hipSuccess) return hip_fail(e, "map synthesis launch");
     p->have_maps = 1;
+    p->have_cube = 0;  // a cube holds the previous maps
     return SC_OK;
 }
 
@@ -505,6 +506,70 @@ int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     rc = ensure_bin_work(p, n < p->bin_pass_max ? n : p->bin_pass_max);
     if (rc) return rc;
     return interpolate_passes(p, ptg, n, tod, false);
+}
+
+// Free the psi cube and its tables (kept until the grid size changes).
+static void free_psi(sc_plan *p) {
+    void *bufs[] = {p->twpsi, p->gpsi, p->cube};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    p->twpsi = nullptr;
+    p->gpsi = nullptr;
+    p->cube = nullptr;
+    p->npsi = p->npst = 0;
+    p->have_cube = 0;
+}
+
+int sc_plan_build_psi_cube(sc_plan *p, int npsi) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (!p->have_maps) return fail(SC_ESTATE, "sc_plan_build_psi_cube before sc_set_sky_beam");
+    int lo = 2 * (2 * p->kmax + 1);
+    if (lo < 2 * p->W) lo = 2 * p->W;
+    if (npsi == 0) npsi = next_smooth(lo, false);
+    if (npsi < lo || npsi > sc_psi_max_len() || !is_smooth(npsi))
+        return fail(SC_EINVAL, "npsi = %d: needs a product of 2, 3, 5 in [%d, %d]", npsi, lo, sc_psi_max_len());
+    if (npsi != p->npsi) {
+        const hipError_t es = hipStreamSynchronize(p->stream);  // a previous cube may still be read
+        if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize before the cube reallocation");
+        free_psi(p);
+        FftPlan P;
+        if (!factor_fft(npsi, &P)) return fail(SC_EINVAL, "npsi = %d has no transform plan", npsi);
+        const int npst = (npsi + p->W - 1 + 3) & ~3;
+        const size_t bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * npst;
+        size_t tot = 0;
+        int rc = alloc((void **)&p->twpsi, sizeof(double2) * npsi, &tot);
+        rc = rc ? rc : alloc((void **)&p->gpsi, sizeof(double) * (p->kmax + 1), &tot);
+        rc = rc ? rc : alloc(&p->cube, bytes, &tot);
+        if (rc) {
+            free_psi(p);
+            return rc;
+        }
+        p->npsi = npsi;
+        p->npst = npst;
+        p->ppsi = P;
+        const hipError_t e = sc_launch_psi_tables(p);
+        if (e != hipSuccess) {
+            free_psi(p);
+            return hip_fail(e, "psi table launch");
+        }
+    }
+    const hipError_t e = sc_launch_psi_cube(p);
+    if (e != hipSuccess) return hip_fail(e, "psi cube launch");
+    p->have_cube = 1;
+    return SC_OK;
+}
+
+int sc_interpolate_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+    g_msg[0] = 0;
+    if (!p) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n == 0) return SC_OK;
+    if (!p->have_cube) return fail(SC_ESTATE, "sc_interpolate_psi without a cube of the current maps");
+    const int rc = check_interp_args(p, ptg, tod);
+    if (rc) return rc;
+    const hipError_t e = sc_launch_gather_psi(p, ptg, n, tod);
+    return e != hipSuccess ? hip_fail(e, "psi gather launch") : SC_OK;
 }
 
 int sc_plan_convolve(sc_plan *p, const double *alm, const double *blm, const double *ptg, int64_t n, void *tod) {

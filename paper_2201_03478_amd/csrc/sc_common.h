@@ -135,6 +135,13 @@ struct sc_plan {
     int64_t bin_pass_max;  // samples per binning pass (env SC_BIN_PASS_MAX, default BIN_PASS_MAX)
 
     // per-kernel event timing (see sc_plan_enable_timing)
+    // psi cube (the paper's second step): [rows][cols][npst], built on request
+    int npsi, npst;        // psi grid points; stored per pixel (npsi + W - 1 with halo, padded to 4)
+    FftPlan ppsi;
+    double2 *twpsi;        // pass-major twiddles of the npsi-point transform
+    double *gpsi;          // [kmax+1] 1 / hhat_psi(k)
+    void *cube;
+    int have_cube;
     int timing;
     struct TimedLaunch *tl;  // pool of event pairs
     int tl_n, tl_cap;
@@ -152,6 +159,10 @@ static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_
 
 // ---------------------------------------------------------------- launchers
 hipError_t sc_launch_tables(sc_plan *p);
+hipError_t sc_launch_psi_tables(sc_plan *p);
+hipError_t sc_launch_psi_cube(sc_plan *p);
+hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod);
+int sc_psi_max_len();
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm);

@@ -56,4 +56,6 @@ def test_null_plan_calls(lib):
     assert lib.sc_plan_destroy(None) == N.SC_OK
     assert lib.sc_set_sky_beam(None, None, None) == N.SC_EINVAL
     assert lib.sc_interpolate(None, None, 0, None) == N.SC_EINVAL
+    assert lib.sc_plan_build_psi_cube(None, 0) == N.SC_EINVAL
+    assert lib.sc_interpolate_psi(None, None, 0, None) == N.SC_EINVAL
     assert lib.sc_plan_info(None, None, 0) == N.SC_EINVAL

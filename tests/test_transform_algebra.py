@@ -134,3 +134,79 @@ def test_paired_adjoint_is_the_transpose(m, k):
     lhs = ip(g1, G1) + ip(g2, G2)
     rhs = ip(F1, a1) + ip(F2, a2)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------------------------------
+# The psi cube: the series over k of one pixel's cos/sin components on an npsi-point
+# grid, divided by the kernel transform, with two pixels packed into one complex
+# inverse transform of a Hermitian spectrum; interpolating it with the kernel
+# reproduces the series at any psi.
+
+def _es(z, beta):
+    q = 1.0 - z * z
+    return np.where(q > 0, np.exp(beta * (np.sqrt(np.maximum(q, 0.0)) - 1.0)), 0.0)
+
+
+def _kernel_transform(k, npsi, W, beta):
+    """hhat(k) = int w(y / (W/2)) cos(2 pi k y / npsi) dy over grid units y (midpoint rule)."""
+    y = (np.arange(200000) + 0.5) / 200000 * W - W / 2
+    return np.sum(_es(y / (W / 2), beta) * np.cos(2 * np.pi * k * y / npsi)) * (W / 200000)
+
+
+def _packed_cube(A, B, g, npsi):
+    """Two pixels (rows of A, B) through one complex inverse transform, as the cube kernel does."""
+    kmax = A.shape[1] - 1
+    X = np.zeros(npsi, complex)
+    for k in range(kmax + 1):
+        if k == 0:
+            X[0] = g[0] * (A[0, 0] + 1j * A[1, 0])
+            continue
+        ya = 0.5 * g[k] * (A[0, k] - 1j * B[0, k])
+        yb = 0.5 * g[k] * (A[1, k] - 1j * B[1, k])
+        X[k] = ya + 1j * yb
+        X[npsi - k] = np.conj(ya) + 1j * np.conj(yb)
+    c = np.fft.ifft(X) * npsi
+    return c.real, c.imag
+
+
+@pytest.mark.parametrize("kmax,npsi", [(0, 8), (3, 16), (10, 45), (20, 90)])
+def test_psi_series_two_pixels_per_transform(kmax, npsi):
+    rng = np.random.default_rng(kmax)
+    A = rng.standard_normal((2, kmax + 1))
+    B = rng.standard_normal((2, kmax + 1))
+    B[:, 0] = 0.0  # the stored sin 0 psi map is zero
+    g = rng.uniform(0.5, 2.0, kmax + 1)
+    ca, cb = _packed_cube(A, B, g, npsi)
+    psi = 2 * np.pi * np.arange(npsi) / npsi
+    k = np.arange(kmax + 1)[:, None]
+    for c, p in ((ca, 0), (cb, 1)):
+        ref = np.sum(g[:, None] * (A[p][:, None] * np.cos(k * psi) + B[p][:, None] * np.sin(k * psi)), axis=0)
+        assert np.abs(c - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("W,tol", [(8, 2e-7), (14, 1e-12)])
+def test_psi_interpolation_reproduces_series(W, tol):
+    """Deconvolved grid series + periodic halo + kernel weights in psi = the series, within the
+    kernel's accuracy for twofold oversampling (beta = 2.3 W)."""
+    kmax = 12
+    npsi = 2 * (2 * kmax + 1) + 0  # 50 = 2 * 5^2
+    beta = 2.30 * W
+    half = W // 2
+    rng = np.random.default_rng(W)
+    A = rng.standard_normal((2, kmax + 1))
+    B = rng.standard_normal((2, kmax + 1))
+    B[:, 0] = 0.0
+    g = np.array([1.0 / _kernel_transform(k, npsi, W, beta) for k in range(kmax + 1)])
+    ca, _ = _packed_cube(A, B, g, npsi)
+    # stored entry s holds grid point (s - W/2 + 1) mod npsi
+    ext = np.array([ca[(s - half + 1) % npsi] for s in range(npsi + W - 1)])
+    k = np.arange(kmax + 1)
+    scale = np.sum(np.abs(A[0]) + np.abs(B[0]))
+    for psi in np.concatenate([rng.uniform(0, 2 * np.pi, 40), [0.0, 2 * np.pi - 1e-12]]):
+        x = psi * npsi / (2 * np.pi)
+        p0 = int(np.floor(x)) - half + 1
+        nodes = p0 + np.arange(W)
+        w = _es((x - nodes) / half, beta)
+        got = np.dot(w, ext[nodes + half - 1])
+        ref = np.sum(A[0] * np.cos(k * psi) + B[0] * np.sin(k * psi))
+        assert abs(got - ref) <= tol * scale, psi
