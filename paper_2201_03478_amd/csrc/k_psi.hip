@@ -29,32 +29,75 @@ namespace {
 constexpr int PSI_NT = 64;  // one wave per transform
 constexpr int PSI_PT = 8;   // npsi <= 512
 
+constexpr int PSI_SLACK = 512;  // zeroed bytes after the cube (reached by the last pixel's quad reads)
+
+// Map values of one pixel pair at the lane's two orders k = tid, tid + 64: (M_2k, M_2k+1) of
+// pixel a, then of pixel b (zero past kmax and for a missing b).
+template <typename T>
+__device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t pair, int64_t npix, int ncp, int kmax,
+                                           int tid, T (&r)[8]) {
+    const int64_t a = 2 * pair;
+    const bool hb = a + 1 < npix;
+    const T *ma = maps + a * ncp, *mb = ma + (hb ? ncp : 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = tid + PSI_NT * h;
+        const bool ok = k <= kmax;
+        r[4 * h] = ok ? ma[2 * k] : (T)0;
+        r[4 * h + 1] = ok ? ma[2 * k + 1] : (T)0;
+        r[4 * h + 2] = ok && hb ? mb[2 * k] : (T)0;
+        r[4 * h + 3] = ok && hb ? mb[2 * k + 1] : (T)0;
+    }
+}
+
+// Persistent over pixel pairs; the next pair's map values are loaded before the current
+// pair's transform so that the load latency overlaps it.  Twiddles and the deconvolution
+// factors are read once per workgroup (LDS, registers): no global loads inside the transform.
 template <typename T>
 __global__ void __launch_bounds__(PSI_NT)
 k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int ncp, int kmax, int npsi, int npst,
            int W, FftPlan P, const double2 *__restrict__ tw, const double *__restrict__ gpsi) {
     __shared__ double2 buf[PSI_NT * PSI_PT];
+    __shared__ double2 twl[PSI_NT * PSI_PT];
     const int tid = threadIdx.x;
     const int half = W / 2;
     const int ext = npsi + W - 1;
-    for (int64_t pair = blockIdx.x; 2 * pair < npix; pair += gridDim.x) {
-        const int64_t a = 2 * pair, b = a + 1;
-        const bool hb = b < npix;
-        const T *ma = maps + a * ncp, *mb = maps + (hb ? b : a) * ncp;
-        for (int t = tid; t < npsi; t += PSI_NT) {
-            const int k = t <= kmax ? t : (t >= npsi - kmax ? npsi - t : -1);
-            double2 x = make_double2(0.0, 0.0);
-            if (k >= 0) {
-                const double g = k == 0 ? gpsi[0] : 0.5 * gpsi[k];
-                const double sg = t <= kmax ? 1.0 : -1.0;  // +k: M_2k - i M_2k+1; -k: its conjugate
-                const double ca = (double)ma[2 * k], sa = (double)ma[2 * k + 1];
-                const double cb = hb ? (double)mb[2 * k] : 0.0, sb = hb ? (double)mb[2 * k + 1] : 0.0;
-                x = make_double2(g * (ca + sg * sb), g * (cb - sg * sa));
+    for (int t = tid; t < npsi; t += PSI_NT) twl[t] = tw[t];
+    if (blockIdx.x == 0)
+        for (int e = tid; e < PSI_SLACK / (int)sizeof(T); e += PSI_NT) cube[npix * npst + e] = (T)0;
+    double gk[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = tid + PSI_NT * h;
+        gk[h] = k > kmax ? 0.0 : (k == 0 ? gpsi[0] : 0.5 * gpsi[k]);
+    }
+    int64_t pair = blockIdx.x;
+    T nxt[8];
+    if (2 * pair < npix) fetch_pair(maps, pair, npix, ncp, kmax, tid, nxt);
+    for (; 2 * pair < npix; pair += gridDim.x) {
+        T cur[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
+        const int64_t pn = pair + gridDim.x;
+        if (2 * pn < npix) fetch_pair(maps, pn, npix, ncp, kmax, tid, nxt);
+        for (int t = tid; t < npsi; t += PSI_NT)
+            if (t > kmax && t < npsi - kmax) buf[t] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = tid + PSI_NT * h;
+            if (k <= kmax) {
+                const double g = gk[h];
+                const double ca = (double)cur[4 * h], sa = (double)cur[4 * h + 1];
+                const double cb = (double)cur[4 * h + 2], sb = (double)cur[4 * h + 3];
+                // +k: Y_a + i Y_b with Y = g (M_2k - i M_2k+1); -k: the conjugates
+                buf[k] = make_double2(g * (ca + sb), g * (cb - sa));
+                if (k > 0) buf[npsi - k] = make_double2(g * (ca - sb), g * (cb + sa));
             }
-            buf[t] = x;
         }
         __syncthreads();
-        fft_lds<+1, PSI_NT, PSI_PT>(buf, P, tw, tid, PSI_NT);
+        fft_lds<+1, PSI_NT, PSI_PT>(buf, P, twl, tid, PSI_NT);
+        const int64_t a = 2 * pair, b = a + 1;
+        const bool hb = b < npix;
         for (int s = tid; s < npst; s += PSI_NT) {
             int j = s - half + 1;
             j = j < 0 ? j + npsi : (j >= npsi ? j - npsi : j);
@@ -122,12 +165,72 @@ k_gather_psi(const double *__restrict__ ptg, int64_t n, const T *__restrict__ cu
     }
 }
 
+// FP32 cube: each run of W psi values is read as (W + 6) / 4 aligned float4 quads from the
+// quad boundary at or below its first entry.  The weights are evaluated at the nodes of all
+// 4 NQ entries: the kernel vanishes at |z| >= 1, so the entries outside the W-point stencil
+// get weight 0 and the stencil's own weights are the same values as above.  The last quad
+// can reach past the pixel's npst entries into the next pixel (finite values, weight 0) or,
+// for the last pixel, into the zeroed slack after the cube.
+template <int W>
+__global__ void __launch_bounds__(256)
+k_gather_psi_f32(const double *__restrict__ ptg, int64_t n, const float *__restrict__ cube, float *__restrict__ tod,
+                 int cols, int npst, double beta, double inv_hth, double inv_hph, double inv_hps, int n2os, int nphi,
+                 int npsi) {
+    constexpr int half = W / 2;
+    constexpr int NQ = (W + 6) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const double th = ptg[3 * s], ph = ptg[3 * s + 1], ps = ptg[3 * s + 2];
+        double u = th * inv_hth;
+        u = fmin(fmax(u, 0.0), 0.5 * (double)n2os);
+        const int r0 = (int)floor(u) - half + 1;
+        const double v = periodic_coord(ph, inv_hph, nphi);
+        const int q0 = (int)floor(v) - half + 1;
+        const double x = periodic_coord(ps, inv_hps, npsi);
+        const int a0 = ((int)floor(x)) & ~3;  // stored index of the first psi entry, rounded down to a quad
+        float wt[W], wp[W], wq[4 * NQ];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            wt[i] = es_w<float>((float)((u - (double)(r0 + i)) / half), (float)beta);
+            wp[i] = es_w<float>((float)((v - (double)(q0 + i)) / half), (float)beta);
+        }
+#pragma unroll
+        for (int m = 0; m < 4 * NQ; ++m)  // stored entry a0 + m holds grid node a0 + m - half + 1
+            wq[m] = es_w<float>((float)((x - (double)(a0 + m - half + 1)) / half), (float)beta);
+        const float4 *base =
+            (const float4 *)(cube + ((size_t)(r0 + half - 1) * cols + (size_t)(q0 + half - 1)) * npst + a0);
+        const size_t rq = (size_t)npst / 4;
+        float acc = 0.0f;
+        for (int i = 0; i < W; ++i) {
+            float ai = 0.0f;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const float4 *c = base + ((size_t)i * cols + j) * rq;
+                float t = 0.0f;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const float4 c4 = c[q];
+                    t += wq[4 * q] * c4.x + wq[4 * q + 1] * c4.y + wq[4 * q + 2] * c4.z + wq[4 * q + 3] * c4.w;
+                }
+                ai += wp[j] * t;
+            }
+            acc += wt[i] * ai;
+        }
+        tod[s] = acc;
+    }
+}
+
 template <typename T, int W>
 void launch_gather_psi(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk) {
     const double two_pi = 6.283185307179586477;
-    hipLaunchKernelGGL((k_gather_psi<T, W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n, (const T *)p->cube,
-                       (T *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi, (double)p->nphi / two_pi,
-                       (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_gather_psi_f32<W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n,
+                           (const float *)p->cube, (float *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi,
+                           (double)p->nphi / two_pi, (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi);
+    else
+        hipLaunchKernelGGL((k_gather_psi<T, W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n, (const T *)p->cube,
+                           (T *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi, (double)p->nphi / two_pi,
+                           (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi);
 }
 
 template <typename T>
@@ -146,6 +249,7 @@ void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *t
 }  // namespace
 
 int sc_psi_max_len() { return PSI_NT * PSI_PT; }
+int sc_psi_slack_bytes() { return PSI_SLACK; }
 
 hipError_t sc_launch_psi_cube(sc_plan *p) {
     const int64_t npix = (int64_t)p->rows * p->cols;

@@ -268,6 +268,8 @@ int sc_persistent_grid(const void *kern, int block, size_t lds, int wgs_per_cu) 
     return per_cu * ncu;
 }
 
+int sc_psi_slack_bytes();  // k_psi.hip: zeroed bytes after the cube
+
 extern "C" {
 
 const char *sc_strerror(int code) {
@@ -540,7 +542,7 @@ int sc_plan_build_psi_cube(sc_plan *p, int npsi) {
         size_t tot = 0;
         int rc = alloc((void **)&p->twpsi, sizeof(double2) * npsi, &tot);
         rc = rc ? rc : alloc((void **)&p->gpsi, sizeof(double) * (p->kmax + 1), &tot);
-        rc = rc ? rc : alloc(&p->cube, bytes, &tot);
+        rc = rc ? rc : alloc(&p->cube, bytes + sc_psi_slack_bytes(), &tot);  // + the gather's zeroed slack
         if (rc) {
             free_psi(p);
             return rc;
