@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 4 per host thread)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--extras", default="", metavar="NAMES",
+                    help="comma-separated subset of the other workloads to run (default: all)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, adjoint and batched workloads (extra objects in the JSON line)")
     args = ap.parse_args()
@@ -302,6 +304,8 @@ def main():
     if not args.no_extras:
         for name, fn in (("precision_variant", extra_precision), ("adjoint", extra_adjoint),
                          ("batched", extra_batched), ("dipole", extra_dipole), ("psi_cube", extra_psi_cube)):
+            if args.extras and name not in args.extras.split(","):
+                continue
             try:
                 result[name] = fn(torch, api, W, dev, args.no_cpu_baseline)
             except Exception as exc:  # an extra must not lose the headline line

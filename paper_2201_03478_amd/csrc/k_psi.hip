@@ -171,15 +171,19 @@ k_gather_psi(const double *__restrict__ ptg, int64_t n, const T *__restrict__ cu
 // get weight 0 and the stencil's own weights are the same values as above.  The last quad
 // can reach past the pixel's npst entries into the next pixel (finite values, weight 0) or,
 // for the last pixel, into the zeroed slack after the cube.
+// With a sample order (the binning's records in anchor order), thread t takes sample
+// order[t].idx instead of t: samples that share a stencil anchor run together and reuse
+// the same cube lines from cache.  Each sample's arithmetic is unchanged.
 template <int W>
 __global__ void __launch_bounds__(256)
 k_gather_psi_f32(const double *__restrict__ ptg, int64_t n, const float *__restrict__ cube, float *__restrict__ tod,
                  int cols, int npst, double beta, double inv_hth, double inv_hph, double inv_hps, int n2os, int nphi,
-                 int npsi) {
+                 int npsi, const BinRec *__restrict__ order) {
     constexpr int half = W / 2;
     constexpr int NQ = (W + 6) / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const int64_t s = order ? (int64_t)order[t].idx : t;
         const double th = ptg[3 * s], ph = ptg[3 * s + 1], ps = ptg[3 * s + 2];
         double u = th * inv_hth;
         u = fmin(fmax(u, 0.0), 0.5 * (double)n2os);
@@ -221,12 +225,13 @@ k_gather_psi_f32(const double *__restrict__ ptg, int64_t n, const float *__restr
 }
 
 template <typename T, int W>
-void launch_gather_psi(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk) {
+void launch_gather_psi(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk,
+                       const BinRec *order) {
     const double two_pi = 6.283185307179586477;
     if constexpr (sizeof(T) == 4)
         hipLaunchKernelGGL((k_gather_psi_f32<W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n,
                            (const float *)p->cube, (float *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi,
-                           (double)p->nphi / two_pi, (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi);
+                           (double)p->nphi / two_pi, (double)p->npsi / two_pi, p->n2os, p->nphi, p->npsi, order);
     else
         hipLaunchKernelGGL((k_gather_psi<T, W>), dim3(nblk), dim3(256), 0, p->stream, ptg, n, (const T *)p->cube,
                            (T *)tod, p->cols, p->npst, p->beta, (double)p->n2os / two_pi, (double)p->nphi / two_pi,
@@ -234,15 +239,16 @@ void launch_gather_psi(const sc_plan *p, const double *ptg, int64_t n, void *tod
 }
 
 template <typename T>
-void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk) {
+void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *tod, unsigned nblk,
+                         const BinRec *order) {
     switch (p->W) {
-        case 4: launch_gather_psi<T, 4>(p, ptg, n, tod, nblk); break;
-        case 6: launch_gather_psi<T, 6>(p, ptg, n, tod, nblk); break;
-        case 8: launch_gather_psi<T, 8>(p, ptg, n, tod, nblk); break;
-        case 10: launch_gather_psi<T, 10>(p, ptg, n, tod, nblk); break;
-        case 12: launch_gather_psi<T, 12>(p, ptg, n, tod, nblk); break;
-        case 14: launch_gather_psi<T, 14>(p, ptg, n, tod, nblk); break;
-        default: launch_gather_psi<T, 16>(p, ptg, n, tod, nblk); break;
+        case 4: launch_gather_psi<T, 4>(p, ptg, n, tod, nblk, order); break;
+        case 6: launch_gather_psi<T, 6>(p, ptg, n, tod, nblk, order); break;
+        case 8: launch_gather_psi<T, 8>(p, ptg, n, tod, nblk, order); break;
+        case 10: launch_gather_psi<T, 10>(p, ptg, n, tod, nblk, order); break;
+        case 12: launch_gather_psi<T, 12>(p, ptg, n, tod, nblk, order); break;
+        case 14: launch_gather_psi<T, 14>(p, ptg, n, tod, nblk, order); break;
+        default: launch_gather_psi<T, 16>(p, ptg, n, tod, nblk, order); break;
     }
 }
 
@@ -266,13 +272,22 @@ hipError_t sc_launch_psi_cube(sc_plan *p) {
     return hipGetLastError();
 }
 
-hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+static hipError_t gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod, const BinRec *order) {
     if (n == 0) return hipSuccess;
     int64_t nb = (n + 255) / 256;
     if (nb > 65536) nb = 65536;
     if (p->prec == SC_FP64)
-        launch_gather_psi_w<double>(p, ptg, n, tod, (unsigned)nb);
+        launch_gather_psi_w<double>(p, ptg, n, tod, (unsigned)nb, nullptr);
     else
-        launch_gather_psi_w<float>(p, ptg, n, tod, (unsigned)nb);
+        launch_gather_psi_w<float>(p, ptg, n, tod, (unsigned)nb, order);
     return hipGetLastError();
+}
+
+hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+    return gather_psi(p, ptg, n, tod, nullptr);
+}
+
+// FP32 cube, samples in the order of the plan's most recent binning pass over these n pointings.
+hipError_t sc_launch_gather_psi_sorted(sc_plan *p, const double *ptg, int64_t n, void *tod) {
+    return gather_psi(p, ptg, n, tod, p->bw.sorted.rec);
 }

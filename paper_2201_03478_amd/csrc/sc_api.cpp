@@ -269,6 +269,7 @@ int sc_persistent_grid(const void *kern, int block, size_t lds, int wgs_per_cu) 
 }
 
 int sc_psi_slack_bytes();  // k_psi.hip: zeroed bytes after the cube
+hipError_t sc_launch_gather_psi_sorted(sc_plan *p, const double *ptg, int64_t n, void *tod);  // k_psi.hip
 
 extern "C" {
 
@@ -568,10 +569,24 @@ int sc_interpolate_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
     if (n == 0) return SC_OK;
     if (!p->have_cube) return fail(SC_ESTATE, "sc_interpolate_psi without a cube of the current maps");
-    const int rc = check_interp_args(p, ptg, tod);
+    int rc = check_interp_args(p, ptg, tod);
     if (rc) return rc;
-    const hipError_t e = sc_launch_gather_psi(p, ptg, n, tod);
-    return e != hipSuccess ? hip_fail(e, "psi gather launch") : SC_OK;
+    if (p->prec == SC_FP64 || !uses_binning(p)) {
+        const hipError_t e = sc_launch_gather_psi(p, ptg, n, tod);
+        return e != hipSuccess ? hip_fail(e, "psi gather launch") : SC_OK;
+    }
+    // FP32 cube: samples in anchor order (the binning of the two-dimensional gather), in passes
+    const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
+    rc = ensure_bin_work(p, pass);
+    if (rc) return rc;
+    for (int64_t off = 0; off < n; off += pass) {
+        const int64_t cnt = n - off < pass ? n - off : pass;
+        rc = bin_pass(p, ptg, off, cnt);
+        if (rc) return rc;
+        const hipError_t e = sc_launch_gather_psi_sorted(p, ptg + 3 * off, cnt, (float *)tod + off);
+        if (e != hipSuccess) return hip_fail(e, "psi gather launch");
+    }
+    return SC_OK;
 }
 
 int sc_plan_convolve(sc_plan *p, const double *alm, const double *blm, const double *ptg, int64_t n, void *tod) {
