@@ -17,7 +17,7 @@
 // point (s - W/2 + 1) mod npsi for s < npsi + W - 1 (a periodic halo, so the W
 // psi nodes of a sample are W consecutive values), zero beyond.
 //
-// Build: one wave per two pixels.  The series of a pixel is real, so its
+// Build: one wave per transform of two pixels.  The series of a pixel is real, so its
 // spectrum is Hermitian: Y(k) = g_k (M_2k - i M_2k+1) / 2 at +k, the conjugate at
 // -k, g_0 M_0 at 0.  Two pixels a, b share one complex inverse transform of
 // X = Y_a + i Y_b, whose output is c_a + i c_b.  The transform is the LDS
@@ -50,36 +50,45 @@ __device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t p
     }
 }
 
-// Persistent over pixel pairs; the next pair's map values are loaded before the current
-// pair's transform so that the load latency overlaps it.  Twiddles and the deconvolution
-// factors are read once per workgroup (LDS, registers): no global loads inside the transform.
-template <typename T>
-__global__ void __launch_bounds__(PSI_NT)
+// Persistent over pixel pairs, two waves per workgroup sharing the twiddle table: wave w
+// takes pair 2 g + w of pair group g.  The next pair's map values are loaded before the
+// current pair's transform so that the load latency overlaps it.  Twiddles and the
+// deconvolution factors are read once per workgroup (LDS, registers): no global loads inside
+// the transform.  Both waves run every group's transform (its barriers are the workgroup's);
+// a wave without a pair in the last group transforms stale values and stores nothing.
+template <typename T, typename S>
+__global__ void __launch_bounds__(2 * PSI_NT)
 k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int ncp, int kmax, int npsi, int npst,
            int W, FftPlan P, const double2 *__restrict__ tw, const double *__restrict__ gpsi) {
-    __shared__ double2 buf[PSI_NT * PSI_PT];
-    __shared__ double2 twl[PSI_NT * PSI_PT];
-    const int tid = threadIdx.x;
+    constexpr int NB = FftLen<S>::value > 0 ? FftLen<S>::value : PSI_NT * PSI_PT;  // LDS per array
+    __shared__ double2 bufs[2][NB];
+    __shared__ double2 twl[NB];
+    const int tid = threadIdx.x & (PSI_NT - 1), wv = threadIdx.x / PSI_NT;
+    double2 *buf = bufs[wv];
     const int half = W / 2;
     const int ext = npsi + W - 1;
-    for (int t = tid; t < npsi; t += PSI_NT) twl[t] = tw[t];
+    const int64_t npairs = (npix + 1) / 2;
+    for (int t = threadIdx.x; t < npsi; t += 2 * PSI_NT) twl[t] = tw[t];
     if (blockIdx.x == 0)
-        for (int e = tid; e < PSI_SLACK / (int)sizeof(T); e += PSI_NT) cube[npix * npst + e] = (T)0;
+        for (int e = threadIdx.x; e < PSI_SLACK / (int)sizeof(T); e += 2 * PSI_NT) cube[npix * npst + e] = (T)0;
     double gk[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int k = tid + PSI_NT * h;
         gk[h] = k > kmax ? 0.0 : (k == 0 ? gpsi[0] : 0.5 * gpsi[k]);
     }
-    int64_t pair = blockIdx.x;
+    int64_t grp = blockIdx.x;
     T nxt[8];
-    if (2 * pair < npix) fetch_pair(maps, pair, npix, ncp, kmax, tid, nxt);
-    for (; 2 * pair < npix; pair += gridDim.x) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) nxt[e] = (T)0;
+    if (2 * grp + wv < npairs) fetch_pair(maps, 2 * grp + wv, npix, ncp, kmax, tid, nxt);
+    for (; 2 * grp < npairs; grp += gridDim.x) {
+        const int64_t pair = 2 * grp + wv;
         T cur[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-        const int64_t pn = pair + gridDim.x;
-        if (2 * pn < npix) fetch_pair(maps, pn, npix, ncp, kmax, tid, nxt);
+        const int64_t pn = 2 * (grp + gridDim.x) + wv;
+        if (pn < npairs) fetch_pair(maps, pn, npix, ncp, kmax, tid, nxt);
         for (int t = tid; t < npsi; t += PSI_NT)
             if (t > kmax && t < npsi - kmax) buf[t] = make_double2(0.0, 0.0);
 #pragma unroll
@@ -95,15 +104,17 @@ k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int n
             }
         }
         __syncthreads();
-        fft_lds<+1, PSI_NT, PSI_PT>(buf, P, twl, tid, PSI_NT);
-        const int64_t a = 2 * pair, b = a + 1;
-        const bool hb = b < npix;
-        for (int s = tid; s < npst; s += PSI_NT) {
-            int j = s - half + 1;
-            j = j < 0 ? j + npsi : (j >= npsi ? j - npsi : j);
-            const double2 v = s < ext ? buf[j] : make_double2(0.0, 0.0);
-            cube[a * npst + s] = (T)v.x;
-            if (hb) cube[b * npst + s] = (T)v.y;
+        FftRun<+1, PSI_NT, PSI_PT, S>::run(buf, P, twl, tid, PSI_NT);
+        if (pair < npairs) {
+            const int64_t a = 2 * pair, b = a + 1;
+            const bool hb = b < npix;
+            for (int s = tid; s < npst; s += PSI_NT) {
+                int j = s - half + 1;
+                j = j < 0 ? j + npsi : (j >= npsi ? j - npsi : j);
+                const double2 v = s < ext ? buf[j] : make_double2(0.0, 0.0);
+                cube[a * npst + s] = (T)v.x;
+                if (hb) cube[b * npst + s] = (T)v.y;
+            }
         }
         __syncthreads();
     }
@@ -257,18 +268,41 @@ void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *t
 int sc_psi_max_len() { return PSI_NT * PSI_PT; }
 int sc_psi_slack_bytes() { return PSI_SLACK; }
 
+namespace {
+
+// The psi transform of kmax = 100 (npsi = 405) with its passes fixed at compile time; other
+// sizes take the runtime-planned transform.  The radix order is the one factor_fft plans, so
+// both read the same twiddle table.
+using PsiSpec405 = FftSpec<405, 9, 9, 5>;
+
+bool is_spec405(const FftPlan &P) {
+    return P.n == 405 && P.nst == 3 && P.r[0] == 9 && P.r[1] == 9 && P.r[2] == 5;
+}
+
+template <typename T, typename S>
+void launch_psi_cube(sc_plan *p, unsigned nblk, int64_t npix) {
+    hipLaunchKernelGGL((k_psi_cube<T, S>), dim3(nblk), dim3(2 * PSI_NT), 0, p->stream, (const T *)p->maps, (T *)p->cube,
+                       npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi, p->gpsi);
+}
+
+}  // namespace
+
 hipError_t sc_launch_psi_cube(sc_plan *p) {
     const int64_t npix = (int64_t)p->rows * p->cols;
-    const int64_t npairs = (npix + 1) / 2;
-    const unsigned nblk = (unsigned)(npairs < 32768 ? npairs : 32768);
-    if (p->prec == SC_FP64)
-        hipLaunchKernelGGL(k_psi_cube<double>, dim3(nblk), dim3(PSI_NT), 0, p->stream, (const double *)p->maps,
-                           (double *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi,
-                           p->gpsi);
-    else
-        hipLaunchKernelGGL(k_psi_cube<float>, dim3(nblk), dim3(PSI_NT), 0, p->stream, (const float *)p->maps,
-                           (float *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi,
-                           p->gpsi);
+    const int64_t ngroups = ((npix + 1) / 2 + 1) / 2;  // two pixel pairs per workgroup
+    const unsigned nblk = (unsigned)(ngroups < 16384 ? ngroups : 16384);
+    const bool fixed = is_spec405(p->ppsi);
+    if (p->prec == SC_FP64) {
+        if (fixed)
+            launch_psi_cube<double, PsiSpec405>(p, nblk, npix);
+        else
+            launch_psi_cube<double, FftGeneric>(p, nblk, npix);
+    } else {
+        if (fixed)
+            launch_psi_cube<float, PsiSpec405>(p, nblk, npix);
+        else
+            launch_psi_cube<float, FftGeneric>(p, nblk, npix);
+    }
     return hipGetLastError();
 }
 
