@@ -149,8 +149,11 @@ int sc_plan_build_psi_cube(sc_plan *plan, int npsi);
  * phi and psi with the same kernel (W^3 cube values per sample).  It
  * approximates the same quantity as sc_interpolate, with the kernel's error
  * in psi added.  ptg: device float64 [n][3]; tod: device float64/float32 [n]
- * (the map type).  Without a cube of the current maps: SC_ESTATE; host memory
- * or misaligned pointers: SC_EINVAL.  n = 0 is a no-op.
+ * (the map type).  FP32 plans with W = 8 first bin the samples by stencil
+ * anchor in the plan's binning workspace (as sc_interpolate does, in passes of
+ * at most 2^27 samples); only the order in which samples are processed
+ * changes, not their values.  Without a cube of the current maps: SC_ESTATE;
+ * host memory or misaligned pointers: SC_EINVAL.  n = 0 is a no-op.
  */
 int sc_interpolate_psi(sc_plan *plan, const double *ptg, int64_t n, void *tod);
 
