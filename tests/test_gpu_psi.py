@@ -171,3 +171,22 @@ def test_psi_binned_order_is_bit_identical(env, oracle_lib, passmax):
     idx = np.linspace(0, n - 1, 64).astype(np.int64)
     ref = oracle_lib.convolve(a, b, L, K, ptg[torch.as_tensor(idx, device=dev)].cpu().numpy())
     assert _rel_l2(binned[idx].astype(np.float64), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("width", [4, 6, 10, 12, 16])
+def test_psi_fp32_other_widths(env, oracle_lib, width):
+    """FP32 cube at other kernel widths (2 to 5 quads per psi run, unbinned order): its error
+    against the oracle stays at the level of the two-dimensional gather of the same width, the
+    psi axis adding an error of the same kind as theta and phi."""
+    torch, api, dev = env
+    L, K, n = 48, 10, 3000
+    a, b, plan = _setup(api, torch, dev, L, K, "f64maps_f32gather", 76, width=width)
+    ptg = _edge_pointings(n, W.config_seed(77, width))
+    pt = torch.from_numpy(ptg).to(dev)
+    plan.build_psi_cube()
+    got = plan.interpolate_psi(pt).double().cpu().numpy()
+    two_d = plan.interpolate(pt).double().cpu().numpy()
+    ref = oracle_lib.convolve(a, b, L, K, ptg)
+    e3, e2 = _rel_l2(got, ref), _rel_l2(two_d, ref)
+    print("psi cube FP32 W=%d: rel-L2 %.3e (2-D gather %.3e)" % (width, e3, e2))
+    assert e3 <= 3.0 * e2 + 1e-6
