@@ -84,9 +84,12 @@ enum sc_precision {
 
 /*
  * Create a plan for one (lmax, kmax, precision).
- *   lmax          >= 0, band limit of sky and beam.
- *   kmax          0 <= kmax <= lmax, beam azimuthal truncation (kmax = 0 is the
- *                 axisymmetric case, a spin-0 transform only; Sec. 2.1).
+ *   lmax          0 <= lmax <= 2303, band limit of sky and beam (the theta and
+ *                 phi transforms, of about 4 lmax points, are held in LDS, at
+ *                 most 9216 points); larger: SC_EINVAL.
+ *   kmax          0 <= kmax <= min(lmax, 127), beam azimuthal truncation
+ *                 (kmax = 0 is the axisymmetric case, a spin-0 transform only;
+ *                 Sec. 2.1).
  *   precision     an sc_precision value.
  *   kernel_width  interpolation kernel width W in grid cells (even, 4..16), or
  *                 0 for the default (8 for SC_F64MAPS_F32GATHER, 14 for SC_FP64).
@@ -189,7 +192,10 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax,
  *   alm_grad  device complex128, alm layout (overwritten).
  * The scatter accumulates with floating-point atomics, so the last bits vary
  * between runs.  Uses (and overwrites) the plan's transform buffers; the maps
- * made by sc_set_sky_beam are kept.
+ * made by sc_set_sky_beam are kept.  The adjoint recursion holds every ring of
+ * a (k, m) column in one workgroup, which limits it to lmax <= 2047 (at most
+ * 2048 rings); plans above that return SC_EINVAL here and in
+ * sc_convolve_adjoint_beam.
  */
 int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
                         double *alm_grad);

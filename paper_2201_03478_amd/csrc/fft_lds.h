@@ -26,7 +26,7 @@
 #define SC_FFT_NT_BIG 512
 #define SC_FFT_PT 9
 #define SC_FFT_NT_HUGE 1024
-#define SC_FFT_PT_HUGE 8
+#define SC_FFT_PT_HUGE 9
 
 // ---------------------------------------------------------------------------
 // Compile-time cos / sin of 2 pi a / R (constants of the register sub-transforms):

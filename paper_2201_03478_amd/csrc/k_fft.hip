@@ -383,7 +383,7 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
 }  // namespace
 
 // Size class of a transform of length n: 0 = (256 threads, 9 points each),
-// 1 = (512, 9), 2 = (1024, 8); the longest supported transform is 8192 points.
+// 1 = (512, 9), 2 = (1024, 9); the longest supported transform is 9216 points.
 static inline int fft_class(int n) {
     return n <= SC_FFT_NT * SC_FFT_PT ? 0 : n <= SC_FFT_NT_BIG * SC_FFT_PT ? 1 : 2;
 }

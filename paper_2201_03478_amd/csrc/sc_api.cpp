@@ -81,7 +81,7 @@ static int radix_passes(int a, int b, int c, int *out) {
 bool factor_fft(int n, FftPlan *P) {
     P->n = n;
     P->nst = 0;
-    if (n < 2 || n > 16 * 512) return false;  // longest transform the LDS kernels handle
+    if (n < 2 || n > 1024 * 9) return false;  // longest LDS transform: 1024 threads x 9 points
     int m = n, a = 0, b = 0, c = 0;
     while (m % 2 == 0) { m /= 2; ++a; }
     while (m % 3 == 0) { m /= 3; ++b; }
@@ -343,7 +343,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     sc_choose_ring_layout_mixed(p->nring, &p->rpt_mx, &p->ngroups_mx);
     if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
         delete p;
-        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 8192 points (not supported)", lmax);
+        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 9216 points (not supported)", lmax);
     }
 
     const size_t nm = 2 * (size_t)lmax + 1;
@@ -726,6 +726,9 @@ static int check_adjoint_args(sc_plan *p, const double *coefs, const double *ptg
                               double *grad) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
     if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
+    if (p->nring > 2048)  // the adjoint recursion's workgroup holds a column's rings: 8 waves x 4 per lane
+        return fail(SC_EINVAL, "adjoint: lmax = %d has %d rings, above the 2048 the adjoint supports (lmax <= 2047)",
+                    p->lmax, p->nring);
     if (!is_device_ptr(coefs)) return fail(SC_EINVAL, "coefficients are not device memory");
     if (!is_device_ptr(grad)) return fail(SC_EINVAL, "gradient output is not device memory");
     if (n > 0 && (!is_device_ptr(ptg) || !is_device_ptr(tod_grad)))

@@ -4,7 +4,8 @@ The band limits below give theta, upsampled-theta and phi transform lengths
 whose radix plans together use every pass radix (2, 3, 4, 5, 6, 8, 9, 10, 12,
 15, 16), in the forward (theta analysis) and inverse (upsampling, phi
 synthesis) directions, and lmax 1800 needs 7290- and 7500-point transforms
-(the 1024-thread class); lmax 256, 512 and 1024 run the compile-time plans of
+(the 1024-thread class), lmax 2100 8640-point and lmax 2303 (the largest plan) 9216-point
+ones (9 points per thread); lmax 256, 512 and 1024 run the compile-time plans of
 540/1080, 1080/2160 and 2160/4320 points.  The FP64 form (W = 14) reaches the convolution of
 Eq. 2 (Galloway et al. 2022, Sec. 2.1) to ~1e-13, so any wrong twiddle, index
 or pass order shows as an O(1) error against the oracle.  The adjoint at the
@@ -32,7 +33,7 @@ def _to(torch, dev, x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
 
 
-@pytest.mark.parametrize("L", [6, 10, 13, 15, 24, 32, 40, 64, 100, 256, 512, 1024, 1800])
+@pytest.mark.parametrize("L", [6, 10, 13, 15, 24, 32, 40, 64, 100, 256, 512, 1024, 1800, 2100, 2303])
 def test_fp64_form_across_transform_lengths(env, oracle_lib, L):
     torch, api, dev = env
     K = min(2, L)
@@ -71,3 +72,24 @@ def test_adjoint_dot_product_largest_lengths(env, prec, tol):
     e = abs(lhs - rhs) / abs(lhs)
     print("dot test %s L=%d: %.3e" % (prec, L, e))
     assert e <= tol
+
+
+def test_adjoint_rejects_lmax_above_2047(env):
+    """The adjoint recursion holds a column's rings in one workgroup (at most 2048 rings): plans
+    above lmax 2047 reject both adjoints with SC_EINVAL before any launch; the forward path runs."""
+    torch, api, dev = env
+    from paper_2201_03478_amd import _native as N
+    lib = N.load()
+    L, K, n = 2100, 1, 16
+    a = _to(torch, dev, W.sky_alm(L, 5400))
+    b = _to(torch, dev, W.beam_alm(L, K, 5401))
+    p = _to(torch, dev, W.uniform_pointings(n, 5402))
+    plan = api.Plan(L, K, "fp64")
+    plan.set_sky_beam(a, b)
+    tod = plan.interpolate(p)
+    grad = torch.zeros_like(a)
+    assert lib.sc_convolve_adjoint(plan._p, b.data_ptr(), p.data_ptr(), tod.data_ptr(), n,
+                                   grad.data_ptr()) == N.SC_EINVAL
+    gb = torch.zeros_like(b)
+    assert lib.sc_convolve_adjoint_beam(plan._p, a.data_ptr(), p.data_ptr(), tod.data_ptr(), n,
+                                        gb.data_ptr()) == N.SC_EINVAL
