@@ -461,6 +461,34 @@ def extra_psi_cube(torch, api, W, dev, no_oracle):
     if not no_oracle:
         res["rel_err_vs_oracle"] = _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, out, 16, W.config_seed(2, 8))
     plan.close()
+    del ptg, out, exact
+    torch.cuda.empty_cache()
+    res["many_samples"] = _psi_many_samples(torch, api, W, dev, no_oracle)
+    return res
+
+
+def _psi_many_samples(torch, api, W, dev, no_oracle):
+    """lmax 1024, kmax 16, 1e8 scan samples: many samples per map set and a small kmax, where the cube's
+    W^3 + W^2 + W = 584 FMA per sample undercut the k-sum's (2 kmax + 1) W^2 = 2112."""
+    cfg = W.CONFIGS["precision-lmax1024-kmax16"]
+    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    a_np, b_np = W.sky_alm(L, W.config_seed(3, 1)), W.beam_alm(L, K, W.config_seed(3, 2))
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    plan.set_sky_beam(torch.from_numpy(a_np).to(dev), torch.from_numpy(b_np).to(dev))
+    ptg = W.scan_pointings(n, device=dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    exact = torch.empty(n, dtype=torch.float32, device=dev)
+    cube_ms = _event_ms(torch, lambda: plan.build_psi_cube(), 3)
+    gather_ms = _event_ms(torch, lambda: plan.interpolate_psi(ptg, out=out), 3)
+    ksum_ms = _event_ms(torch, lambda: plan.interpolate(ptg, out=exact), 3)
+    d = float(torch.linalg.vector_norm((out - exact).double()) / torch.linalg.vector_norm(exact.double()))
+    res = {"workload": "psi-cube-lmax1024-kmax16-scan1e8", "n_samples": n,
+           "npsi": _next_smooth(max(2 * (2 * K + 1), 16)), "cube_build_ms": cube_ms, "gather_ms": gather_ms,
+           "ksum_gather_ms": ksum_ms, "cube_plus_gather_ms": cube_ms + gather_ms,
+           "value": n / ((cube_ms + gather_ms) * 1e-3), "unit": "samples/s", "rel_l2_vs_ksum_path": d}
+    if not no_oracle:
+        res["rel_err_vs_oracle"] = _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, out, 8, W.config_seed(3, 8))
+    plan.close()
     return res
 
 
