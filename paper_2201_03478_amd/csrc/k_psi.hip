@@ -31,17 +31,18 @@ constexpr int PSI_PT = 8;   // npsi <= 512
 
 constexpr int PSI_SLACK = 512;  // zeroed bytes after the cube (reached by the last pixel's quad reads)
 
-// Map values of one pixel pair at the lane's two orders k = tid, tid + 64: (M_2k, M_2k+1) of
-// pixel a, then of pixel b (zero past kmax and for a missing b).
-template <typename T>
+// Map values of one pixel pair at a lane's two orders k = tg, tg + NTS (tg: the lane's index
+// among the NTS lanes of its transform): (M_2k, M_2k+1) of pixel a, then of pixel b (zero past
+// kmax and for a missing b).  Two orders per lane suffice: kmax + 1 <= npsi / 4 <= 2 NTS.
+template <typename T, int NTS>
 __device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t pair, int64_t npix, int ncp, int kmax,
-                                           int tid, T (&r)[8]) {
+                                           int tg, T (&r)[8]) {
     const int64_t a = 2 * pair;
     const bool hb = a + 1 < npix;
     const T *ma = maps + a * ncp, *mb = ma + (hb ? ncp : 0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int k = tid + PSI_NT * h;
+        const int k = tg + NTS * h;
         const bool ok = k <= kmax;
         r[4 * h] = ok ? ma[2 * k] : (T)0;
         r[4 * h + 1] = ok ? ma[2 * k + 1] : (T)0;
@@ -50,21 +51,27 @@ __device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t p
     }
 }
 
-// Persistent over pixel pairs, two waves per workgroup sharing the twiddle table: wave w
-// takes pair 2 g + w of pair group g.  The next pair's map values are loaded before the
-// current pair's transform so that the load latency overlaps it.  Twiddles and the
+// Persistent over pixel pairs, two waves per workgroup sharing the twiddle table; each wave
+// runs G transforms side by side (NTS = 64 / G lanes each, G = 1 for lengths above 128), so
+// short psi grids still fill the wave.  Iteration it of a workgroup covers pairs
+// (2 it + w) G + g for wave w and transform g.  The next pairs' map values are loaded before
+// the current transforms so that the load latency overlaps them.  Twiddles and the
 // deconvolution factors are read once per workgroup (LDS, registers): no global loads inside
-// the transform.  Both waves run every group's transform (its barriers are the workgroup's);
-// a wave without a pair in the last group transforms stale values and stores nothing.
-template <typename T, typename S>
+// the transform.  Every transform runs in every iteration (its barriers are the workgroup's);
+// one without a pair in the last iteration transforms stale values and stores nothing.
+template <typename T, typename S, int G>
 __global__ void __launch_bounds__(2 * PSI_NT)
 k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int ncp, int kmax, int npsi, int npst,
            int W, FftPlan P, const double2 *__restrict__ tw, const double *__restrict__ gpsi) {
-    constexpr int NB = FftLen<S>::value > 0 ? FftLen<S>::value : PSI_NT * PSI_PT;  // LDS per array
-    __shared__ double2 bufs[2][NB];
+    constexpr int NTS = PSI_NT / G;   // lanes per transform
+    constexpr int PTS = PSI_PT * G;   // points per lane: NTS PTS = 512
+    constexpr int NB = FftLen<S>::value > 0 ? FftLen<S>::value : PSI_NT * PSI_PT / G;  // LDS per transform
+    static_assert(G == 1 || FftLen<S>::value > 0, "several transforms per wave need a compile-time plan");
+    __shared__ double2 bufs[2][G][NB];
     __shared__ double2 twl[NB];
-    const int tid = threadIdx.x & (PSI_NT - 1), wv = threadIdx.x / PSI_NT;
-    double2 *buf = bufs[wv];
+    const int lane = threadIdx.x & (PSI_NT - 1), wv = threadIdx.x / PSI_NT;
+    const int g = lane / NTS, tg = lane - g * NTS;
+    double2 *buf = bufs[wv][g];
     const int half = W / 2;
     const int ext = npsi + W - 1;
     const int64_t npairs = (npix + 1) / 2;
@@ -74,46 +81,46 @@ k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int n
     double gk[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int k = tid + PSI_NT * h;
+        const int k = tg + NTS * h;
         gk[h] = k > kmax ? 0.0 : (k == 0 ? gpsi[0] : 0.5 * gpsi[k]);
     }
-    int64_t grp = blockIdx.x;
+    int64_t it = blockIdx.x;
     T nxt[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) nxt[e] = (T)0;
-    if (2 * grp + wv < npairs) fetch_pair(maps, 2 * grp + wv, npix, ncp, kmax, tid, nxt);
-    for (; 2 * grp < npairs; grp += gridDim.x) {
-        const int64_t pair = 2 * grp + wv;
+    if ((2 * it + wv) * G + g < npairs) fetch_pair<T, NTS>(maps, (2 * it + wv) * G + g, npix, ncp, kmax, tg, nxt);
+    for (; 2 * it * G < npairs; it += gridDim.x) {
+        const int64_t pair = (2 * it + wv) * G + g;
         T cur[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-        const int64_t pn = 2 * (grp + gridDim.x) + wv;
-        if (pn < npairs) fetch_pair(maps, pn, npix, ncp, kmax, tid, nxt);
-        for (int t = tid; t < npsi; t += PSI_NT)
+        const int64_t pn = (2 * (it + gridDim.x) + wv) * G + g;
+        if (pn < npairs) fetch_pair<T, NTS>(maps, pn, npix, ncp, kmax, tg, nxt);
+        for (int t = tg; t < npsi; t += NTS)
             if (t > kmax && t < npsi - kmax) buf[t] = make_double2(0.0, 0.0);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int k = tid + PSI_NT * h;
+            const int k = tg + NTS * h;
             if (k <= kmax) {
-                const double g = gk[h];
+                const double gg = gk[h];
                 const double ca = (double)cur[4 * h], sa = (double)cur[4 * h + 1];
                 const double cb = (double)cur[4 * h + 2], sb = (double)cur[4 * h + 3];
                 // +k: Y_a + i Y_b with Y = g (M_2k - i M_2k+1); -k: the conjugates
-                buf[k] = make_double2(g * (ca + sb), g * (cb - sa));
-                if (k > 0) buf[npsi - k] = make_double2(g * (ca - sb), g * (cb + sa));
+                buf[k] = make_double2(gg * (ca + sb), gg * (cb - sa));
+                if (k > 0) buf[npsi - k] = make_double2(gg * (ca - sb), gg * (cb + sa));
             }
         }
         __syncthreads();
-        FftRun<+1, PSI_NT, PSI_PT, S>::run(buf, P, twl, tid, PSI_NT);
+        FftRun<+1, NTS, PTS, S>::run(buf, P, twl, tg, NTS);
         if (pair < npairs) {
             const int64_t a = 2 * pair, b = a + 1;
             const bool hb = b < npix;
-            for (int s = tid; s < npst; s += PSI_NT) {
-                int j = s - half + 1;
+            for (int s2 = tg; s2 < npst; s2 += NTS) {
+                int j = s2 - half + 1;
                 j = j < 0 ? j + npsi : (j >= npsi ? j - npsi : j);
-                const double2 v = s < ext ? buf[j] : make_double2(0.0, 0.0);
-                cube[a * npst + s] = (T)v.x;
-                if (hb) cube[b * npst + s] = (T)v.y;
+                const double2 v = s2 < ext ? buf[j] : make_double2(0.0, 0.0);
+                cube[a * npst + s2] = (T)v.x;
+                if (hb) cube[b * npst + s2] = (T)v.y;
             }
         }
         __syncthreads();
@@ -263,46 +270,49 @@ void launch_gather_psi_w(const sc_plan *p, const double *ptg, int64_t n, void *t
     }
 }
 
+// psi transforms with their passes fixed at compile time, for kmax = 100, 32 and 16 (npsi = 405,
+// 135, 72); the shorter ones run 2 and 4 transforms per wave.  Other lengths take the
+// runtime-planned transform, one per wave.  The radix orders are the ones factor_fft plans,
+// so both forms read the same twiddle table.
+using PsiSpec405 = FftSpec<405, 9, 9, 5>;
+using PsiSpec135 = FftSpec<135, 9, 15>;
+using PsiSpec72 = FftSpec<72, 9, 8>;
+
+bool plan_is(const FftPlan &P, int n, int r0, int r1, int r2) {
+    return P.n == n && P.nst == (r2 ? 3 : 2) && P.r[0] == r0 && P.r[1] == r1 && (!r2 || P.r[2] == r2);
+}
+
+template <typename T, typename S, int G>
+void launch_psi_cube(sc_plan *p, int64_t npix) {
+    const int64_t iters = ((npix + 1) / 2 + 2 * G - 1) / (2 * G);  // 2 G pixel pairs per workgroup iteration
+    const unsigned nblk = (unsigned)(iters < 16384 ? iters : 16384);
+    hipLaunchKernelGGL((k_psi_cube<T, S, G>), dim3(nblk), dim3(2 * PSI_NT), 0, p->stream, (const T *)p->maps,
+                       (T *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi, p->gpsi);
+}
+
+template <typename T>
+void launch_psi_cube_any(sc_plan *p, int64_t npix) {
+    if (plan_is(p->ppsi, 405, 9, 9, 5))
+        launch_psi_cube<T, PsiSpec405, 1>(p, npix);
+    else if (plan_is(p->ppsi, 135, 9, 15, 0))
+        launch_psi_cube<T, PsiSpec135, 2>(p, npix);
+    else if (plan_is(p->ppsi, 72, 9, 8, 0))
+        launch_psi_cube<T, PsiSpec72, 4>(p, npix);
+    else
+        launch_psi_cube<T, FftGeneric, 1>(p, npix);
+}
+
 }  // namespace
 
 int sc_psi_max_len() { return PSI_NT * PSI_PT; }
 int sc_psi_slack_bytes() { return PSI_SLACK; }
 
-namespace {
-
-// The psi transform of kmax = 100 (npsi = 405) with its passes fixed at compile time; other
-// sizes take the runtime-planned transform.  The radix order is the one factor_fft plans, so
-// both read the same twiddle table.
-using PsiSpec405 = FftSpec<405, 9, 9, 5>;
-
-bool is_spec405(const FftPlan &P) {
-    return P.n == 405 && P.nst == 3 && P.r[0] == 9 && P.r[1] == 9 && P.r[2] == 5;
-}
-
-template <typename T, typename S>
-void launch_psi_cube(sc_plan *p, unsigned nblk, int64_t npix) {
-    hipLaunchKernelGGL((k_psi_cube<T, S>), dim3(nblk), dim3(2 * PSI_NT), 0, p->stream, (const T *)p->maps, (T *)p->cube,
-                       npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi, p->gpsi);
-}
-
-}  // namespace
-
 hipError_t sc_launch_psi_cube(sc_plan *p) {
     const int64_t npix = (int64_t)p->rows * p->cols;
-    const int64_t ngroups = ((npix + 1) / 2 + 1) / 2;  // two pixel pairs per workgroup
-    const unsigned nblk = (unsigned)(ngroups < 16384 ? ngroups : 16384);
-    const bool fixed = is_spec405(p->ppsi);
-    if (p->prec == SC_FP64) {
-        if (fixed)
-            launch_psi_cube<double, PsiSpec405>(p, nblk, npix);
-        else
-            launch_psi_cube<double, FftGeneric>(p, nblk, npix);
-    } else {
-        if (fixed)
-            launch_psi_cube<float, PsiSpec405>(p, nblk, npix);
-        else
-            launch_psi_cube<float, FftGeneric>(p, nblk, npix);
-    }
+    if (p->prec == SC_FP64)
+        launch_psi_cube_any<double>(p, npix);
+    else
+        launch_psi_cube_any<float>(p, npix);
     return hipGetLastError();
 }
 

@@ -57,8 +57,12 @@ def _edge_pointings(n, seed):
 @pytest.mark.parametrize("L,K,prec,n,bar", [(32, 4, "fp64", 1500, 1e-12), (20, 20, "fp64", 700, 1e-12),
                                             (8, 0, "fp64", 300, 1e-12), (64, 8, "f64maps_f32gather", 3000, 1e-6),
                                             (40, 17, "f64maps_f32gather", 2000, 1e-6),
-                                            (1, 1, "f64maps_f32gather", 200, 1e-6)])
+                                            (1, 1, "f64maps_f32gather", 200, 1e-6),
+                                            (40, 17, "fp64", 800, 1e-12), (64, 32, "fp64", 800, 1e-12),
+                                            (64, 32, "f64maps_f32gather", 2000, 1e-6)])
 def test_psi_cube_matches_oracle(env, oracle_lib, L, K, prec, n, bar):
+    """Default psi grids: 30, 36, 90 points (runtime-planned transform, one per wave), 72 and 135
+    (compile-time plans, four and two transforms per wave), 16."""
     torch, api, dev = env
     a, b, plan = _setup(api, torch, dev, L, K, prec, 70 + L + K)
     ptg = _edge_pointings(n, W.config_seed(71, n))
