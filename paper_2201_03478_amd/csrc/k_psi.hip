@@ -17,7 +17,8 @@
 // point (s - W/2 + 1) mod npsi for s < npsi + W - 1 (a periodic halo, so the W
 // psi nodes of a sample are W consecutive values), zero beyond.
 //
-// Build: one wave per transform of two pixels.  The series of a pixel is real, so its
+// Build: one transform per two pixels (a wave, or 16 or 32 lanes of one for short psi
+// grids).  The series of a pixel is real, so its
 // spectrum is Hermitian: Y(k) = g_k (M_2k - i M_2k+1) / 2 at +k, the conjugate at
 // -k, g_0 M_0 at 0.  Two pixels a, b share one complex inverse transform of
 // X = Y_a + i Y_b, whose output is c_a + i c_b.  The transform is the LDS
@@ -26,7 +27,7 @@
 
 namespace {
 
-constexpr int PSI_NT = 64;  // one wave per transform
+constexpr int PSI_NT = 64;  // lanes per wave, shared by G transforms
 constexpr int PSI_PT = 8;   // npsi <= 512
 
 constexpr int PSI_SLACK = 512;  // zeroed bytes after the cube (reached by the last pixel's quad reads)
