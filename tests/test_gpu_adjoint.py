@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import assert_parity, coef_hash, load_golden, place_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -47,9 +48,7 @@ def test_adjoint_matches_oracle(env, oracle_lib, prec, tol, L, K, n):
     yt = _to(torch, dev, y).to(plan.tod_dtype)
     g = plan.adjoint(_to(torch, dev, b), _to(torch, dev, p), yt).cpu().numpy()
     ref = oracle_lib.adjoint(b, L, K, p, yt.double().cpu().numpy())
-    e = _rel(g, ref)
-    print("adjoint %s L=%d K=%d rel %.3e" % (prec, L, K, e))
-    assert e <= tol
+    assert_parity(g, ref, tol, "adjoint %s L=%d K=%d" % (prec, L, K))
     assert np.all(g[:L + 1].imag == 0)
 
 
@@ -102,7 +101,24 @@ def test_autograd_function(env, oracle_lib):
     (tod * y).sum().backward()
     ref = oracle_lib.adjoint(b, L, K, pn, y.cpu().numpy())
     assert alm.grad is not None and alm.grad.dtype == torch.complex128
-    assert _rel(alm.grad.cpu().numpy(), ref) <= 1e-10
+    assert_parity(alm.grad.cpu().numpy(), ref, 1e-10, "autograd gradient")
+
+
+def test_adjoint_workload_forward_against_stored_oracle(env):
+    """The forward convolution of the adjoint workload (lmax 512, kmax 32, 1e8 scan
+    samples): 200 stored oracle samples, eight of them edge pointings."""
+    torch, api, dev = env
+    (g,) = load_golden("adjoint-lmax512-kmax32-scan1e8")
+    L, K, n = g["lmax"], g["kmax"], g["n"]
+    a = W.sky_alm(L, W.config_seed(5, 1))
+    b = W.beam_alm(L, K, W.config_seed(5, 2))
+    assert coef_hash(a, b) == g["coef_sha"]
+    ptg = W.scan_pointings(n, device=dev)
+    it = place_golden(torch, ptg, g)
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    tod = plan.convolve(_to(torch, dev, a), _to(torch, dev, b), ptg)
+    torch.cuda.synchronize()
+    assert_parity(tod[it].double().cpu().numpy(), g["c"], 1e-6, "adjoint workload forward")
 
 
 def test_adjoint_workload_full_size(env):
@@ -157,9 +173,7 @@ def test_beam_adjoint_matches_oracle(env, oracle_lib, prec, tol, L, K, n):
     yt = _to(torch, dev, y).to(plan.tod_dtype)
     h = plan.adjoint_beam(_to(torch, dev, a), _to(torch, dev, p), yt).cpu().numpy()
     ref = oracle_lib.beam_adjoint(a, L, K, p, yt.double().cpu().numpy())
-    e = _rel(h, ref)
-    print("beam adjoint %s L=%d K=%d rel %.3e" % (prec, L, K, e))
-    assert e <= tol
+    assert_parity(h, ref, tol, "beam adjoint %s L=%d K=%d" % (prec, L, K))
     assert np.all(h[:L + 1].imag == 0)
 
 
