@@ -37,8 +37,16 @@
  *
  * Streams, ordering, threads
  *   Every call enqueues work on the plan's HIP stream and returns without
- *   synchronising the device.  A plan is not thread-safe: use one plan per
- *   stream.  Inputs must stay valid until the stream reaches the work.
+ *   synchronising the device.  Changing a plan's stream (sc_plan_set_stream,
+ *   or a cached one-shot plan called with another stream) makes the new
+ *   stream wait for everything already queued on the old one, so the plan's
+ *   workspace is never used by two streams at once.  A plan is not
+ *   thread-safe: do not call it from two host threads at once.  Inputs must
+ *   stay valid until the stream reaches the work.  Workspace that grows on
+ *   demand (the pointing-binning buffers, the psi cube) is allocated and
+ *   released in stream order (hipMallocAsync / hipFreeAsync), so no call
+ *   after sc_plan_create waits for the device, except sc_plan_destroy,
+ *   sc_plan_stage_times and sc_batch_create/destroy, which say so.
  *
  * Errors
  *   Every entry point returns SC_OK or a negative code and never aborts or
@@ -102,7 +110,8 @@ int sc_plan_create(sc_plan **plan, int lmax, int kmax, int precision, int kernel
 /* Release a plan and its workspace (synchronises its stream first). NULL is a no-op. */
 int sc_plan_destroy(sc_plan *plan);
 
-/* Change the stream a plan enqueues on. */
+/* Change the stream a plan enqueues on.  The new stream first waits (an event,
+   no host wait) for all work queued on the old one. */
 int sc_plan_set_stream(sc_plan *plan, void *stream);
 
 /*
@@ -173,11 +182,17 @@ int sc_plan_convolve(sc_plan *plan, const double *alm, const double *blm, const 
 
 /*
  * One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod: creates (or
- * reuses a cached) plan for (lmax, kmax, precision, default W) on the stream,
- * and runs sc_plan_convolve on it.  Same layouts as above.
+ * reuses a cached) plan for (lmax, kmax, precision, default W) on the current
+ * device, moves it to `stream` (ordered after its previous stream, as
+ * sc_plan_set_stream does) and runs sc_plan_convolve on it.  Same layouts as
+ * above.  Calls from several host threads are serialised.  Cached plans keep
+ * their workspace until sc_convolve_release_cache.
  */
 int sc_convolve(const double *alm, const double *blm, int lmax, int kmax,
                 const double *ptg, int64_t n, void *tod, int precision, void *stream);
+
+/* Destroy every plan cached by sc_convolve (waits for their streams). */
+int sc_convolve_release_cache(void);
 
 /*
  * Adjoint of the convolution with respect to the sky coefficients (the
@@ -341,6 +356,10 @@ int sc_batch_run(sc_batch *batch, const double *alm_sky, int use_graph);
    batch-wide (the single gather launch). */
 int sc_batch_set_param(sc_batch *batch, int det, int param, int64_t value);
 int sc_batch_get_param(const sc_batch *batch, int det, int param, int64_t *value);
+
+/* Change the stream a batch enqueues and replays on; the new stream first waits
+   for all work queued on the old one. */
+int sc_batch_set_stream(sc_batch *batch, void *stream);
 
 /* The plan of detector det (owned by the batch; for inspection and timing). */
 int sc_batch_plan(sc_batch *batch, int det, sc_plan **plan);

@@ -22,9 +22,9 @@ SC_MMA_FP32, SC_MMA_SPLIT16 = 0, 1
 
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",
-    "sc_interpolate", "sc_plan_build_psi_cube", "sc_interpolate_psi", "sc_plan_convolve", "sc_convolve", "sc_dipole_response", "sc_convolve_adjoint", "sc_convolve_adjoint_beam", "sc_debug_copy_stage", "sc_plan_enable_timing",
+    "sc_interpolate", "sc_plan_build_psi_cube", "sc_interpolate_psi", "sc_plan_convolve", "sc_convolve", "sc_convolve_release_cache", "sc_dipole_response", "sc_convolve_adjoint", "sc_convolve_adjoint_beam", "sc_debug_copy_stage", "sc_plan_enable_timing",
     "sc_plan_stage_times", "sc_plan_set_param", "sc_plan_get_param", "sc_batch_create", "sc_batch_run",
-    "sc_batch_set_param", "sc_batch_get_param", "sc_batch_plan", "sc_batch_destroy", "sc_strerror",
+    "sc_batch_set_param", "sc_batch_get_param", "sc_batch_set_stream", "sc_batch_plan", "sc_batch_destroy", "sc_strerror",
     "sc_last_error",
 )
 
@@ -66,6 +66,7 @@ def load():
     f64 = ctypes.c_double
     lib.sc_dipole_response.argtypes = [vp, i32, i32, vp, i64, vp, i64, f64, f64, vp, vp]
     lib.sc_convolve.argtypes = [vp, vp, i32, i32, vp, i64, vp, i32, vp]
+    lib.sc_convolve_release_cache.argtypes = []
     lib.sc_convolve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.sc_convolve_adjoint_beam.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.sc_debug_copy_stage.argtypes = [vp, i32, vp, i64]
@@ -78,6 +79,7 @@ def load():
     lib.sc_batch_run.argtypes = [vp, vp, i32]
     lib.sc_batch_set_param.argtypes = [vp, i32, i32, i64]
     lib.sc_batch_get_param.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    lib.sc_batch_set_stream.argtypes = [vp, vp]
     lib.sc_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.sc_batch_destroy.argtypes = [vp]
     lib.sc_strerror.argtypes = [i32]

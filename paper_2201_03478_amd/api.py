@@ -32,6 +32,23 @@ def _stream_handle(stream=None) -> int:
     return s.cuda_stream
 
 
+def _ptg_rows(ptg) -> int:
+    """Number of pointings of a [n, 3] tensor (ValueError for any other shape)."""
+    if not isinstance(ptg, torch.Tensor):
+        raise TypeError("ptg must be a tensor")
+    if ptg.dim() != 2 or ptg.shape[1] != 3:
+        raise ValueError("ptg must be [n, 3], got %s" % (tuple(ptg.shape),))
+    return ptg.shape[0]
+
+
+def _numel(t, name: str, want: int):
+    """Size check before any device access: the C side cannot see tensor sizes."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
+    if t.numel() != want:
+        raise ValueError("%s has %d entries, need %d" % (name, t.numel(), want))
+
+
 def _dev(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a CUDA (HIP) tensor" % name)
@@ -95,24 +112,22 @@ class Plan:
         return dict(zip(INFO_KEYS, list(out)))
 
     def set_sky_beam(self, alm: torch.Tensor, blm: torch.Tensor):
+        _numel(alm, "alm", n_alm(self.get_param("sky_lmax")))
+        _numel(blm, "blm", n_alm(self.lmax, self.kmax))
         _dev(alm, "alm", torch.complex128)
         _dev(blm, "blm", torch.complex128)
-        if alm.numel() != n_alm(self.get_param("sky_lmax")) or blm.numel() != n_alm(self.lmax, self.kmax):
-            raise ValueError("alm/blm sizes do not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
         self.set_stream()
         N.check(self._lib.sc_set_sky_beam(self._p, alm.data_ptr(), blm.data_ptr()), "sc_set_sky_beam")
         self._keep = (alm, blm)
 
     def interpolate(self, ptg: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = _ptg_rows(ptg)
+        if out is not None:
+            _numel(out, "tod", n)
         _dev(ptg, "ptg", torch.float64)
-        if ptg.dim() != 2 or ptg.shape[1] != 3:
-            raise ValueError("ptg must be [n, 3]")
-        n = ptg.shape[0]
         if out is None:
             out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
         _dev(out, "tod", self.tod_dtype)
-        if out.numel() != n:
-            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
         self.set_stream()
         if n:
             N.check(self._lib.sc_interpolate(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate")
@@ -126,15 +141,13 @@ class Plan:
 
     def interpolate_psi(self, ptg: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """The convolution at ptg by three-dimensional interpolation of the cube."""
+        n = _ptg_rows(ptg)
+        if out is not None:
+            _numel(out, "tod", n)
         _dev(ptg, "ptg", torch.float64)
-        if ptg.dim() != 2 or ptg.shape[1] != 3:
-            raise ValueError("ptg must be [n, 3]")
-        n = ptg.shape[0]
         if out is None:
             out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
         _dev(out, "tod", self.tod_dtype)
-        if out.numel() != n:
-            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
         self.set_stream()
         if n:
             N.check(self._lib.sc_interpolate_psi(self._p, ptg.data_ptr(), n, out.data_ptr()), "sc_interpolate_psi")
@@ -144,19 +157,17 @@ class Plan:
                  out: torch.Tensor | None = None) -> torch.Tensor:
         """set_sky_beam + interpolate in one call (sc_plan_convolve: the pointing
         binning overlaps the map synthesis on a side stream)."""
+        _numel(alm, "alm", n_alm(self.get_param("sky_lmax")))
+        _numel(blm, "blm", n_alm(self.lmax, self.kmax))
+        n = _ptg_rows(ptg)
+        if out is not None:
+            _numel(out, "tod", n)
         _dev(alm, "alm", torch.complex128)
         _dev(blm, "blm", torch.complex128)
-        if alm.numel() != n_alm(self.get_param("sky_lmax")) or blm.numel() != n_alm(self.lmax, self.kmax):
-            raise ValueError("alm/blm sizes do not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
         _dev(ptg, "ptg", torch.float64)
-        if ptg.dim() != 2 or ptg.shape[1] != 3:
-            raise ValueError("ptg must be [n, 3]")
-        n = ptg.shape[0]
         if out is None:
             out = torch.empty(n, dtype=self.tod_dtype, device=ptg.device)
         _dev(out, "tod", self.tod_dtype)
-        if out.numel() != n:
-            raise ValueError("tod has %d entries, need %d" % (out.numel(), n))
         self.set_stream()
         N.check(self._lib.sc_plan_convolve(self._p, alm.data_ptr(), blm.data_ptr(), ptg.data_ptr(), n,
                                            out.data_ptr()), "sc_plan_convolve")
@@ -165,15 +176,16 @@ class Plan:
 
     def adjoint(self, blm: torch.Tensor, ptg: torch.Tensor, tod_grad: torch.Tensor,
                 out: torch.Tensor | None = None) -> torch.Tensor:
-        """sc_convolve_adjoint: g_lm = dL/dRe a_lm + i dL/dIm a_lm of L = sum_t y_t c_t (complex128)."""
+        """sc_convolve_adjoint: g_lm = dL/dRe a_lm + i dL/dIm a_lm of L = sum_t y_t c_t (complex128,
+        the lmax layout of the plan, not the sky layout of a larger shared sky)."""
+        _numel(blm, "blm", n_alm(self.lmax, self.kmax))
+        n = _ptg_rows(ptg)
+        _numel(tod_grad, "tod_grad", n)
+        if out is not None:
+            _numel(out, "alm_grad", n_alm(self.lmax))
         _dev(blm, "blm", torch.complex128)
         _dev(ptg, "ptg", torch.float64)
         _dev(tod_grad, "tod_grad", self.tod_dtype)
-        if blm.numel() != n_alm(self.lmax, self.kmax):
-            raise ValueError("blm size does not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
-        n = ptg.shape[0]
-        if tod_grad.numel() != n:
-            raise ValueError("tod_grad has %d entries, need %d" % (tod_grad.numel(), n))
         if out is None:
             out = torch.empty(n_alm(self.lmax), dtype=torch.complex128, device=ptg.device)
         _dev(out, "alm_grad", torch.complex128)
@@ -185,19 +197,17 @@ class Plan:
     def adjoint_beam(self, alm: torch.Tensor, ptg: torch.Tensor, tod_grad: torch.Tensor,
                      out: torch.Tensor | None = None) -> torch.Tensor:
         """sc_convolve_adjoint_beam: h_lk = dL/dRe b_lk + i dL/dIm b_lk of L = sum_t y_t c_t (complex128)."""
+        _numel(alm, "alm", n_alm(self.get_param("sky_lmax")))
+        n = _ptg_rows(ptg)
+        _numel(tod_grad, "tod_grad", n)
+        if out is not None:
+            _numel(out, "blm_grad", n_alm(self.lmax, self.kmax))
         _dev(alm, "alm", torch.complex128)
         _dev(ptg, "ptg", torch.float64)
         _dev(tod_grad, "tod_grad", self.tod_dtype)
-        if alm.numel() != n_alm(self.get_param("sky_lmax")):
-            raise ValueError("alm size does not match the plan's sky layout")
-        n = ptg.shape[0]
-        if tod_grad.numel() != n:
-            raise ValueError("tod_grad has %d entries, need %d" % (tod_grad.numel(), n))
         if out is None:
             out = torch.empty(n_alm(self.lmax, self.kmax), dtype=torch.complex128, device=ptg.device)
         _dev(out, "blm_grad", torch.complex128)
-        if out.numel() != n_alm(self.lmax, self.kmax):
-            raise ValueError("blm_grad size does not match lmax=%d kmax=%d" % (self.lmax, self.kmax))
         self.set_stream()
         N.check(self._lib.sc_convolve_adjoint_beam(self._p, alm.data_ptr(), ptg.data_ptr(), tod_grad.data_ptr(), n,
                                                    out.data_ptr()), "sc_convolve_adjoint_beam")
@@ -238,14 +248,23 @@ class Plan:
 
 def convolve(alm: torch.Tensor, blm: torch.Tensor, lmax: int, kmax: int, ptg: torch.Tensor,
              precision="f64maps_f32gather", out: torch.Tensor | None = None) -> torch.Tensor:
-    """One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod (sc_convolve)."""
+    """One-shot convolve(alm, blm, lmax, kmax, pointings) -> tod (sc_convolve).
+
+    The library caches one plan per (lmax, kmax, precision, device); release_cache()
+    frees them."""
+    if not (0 <= int(kmax) <= int(lmax)):
+        raise ValueError("need 0 <= kmax <= lmax, got lmax=%d kmax=%d" % (lmax, kmax))
+    _numel(alm, "alm", n_alm(int(lmax)))
+    _numel(blm, "blm", n_alm(int(lmax), int(kmax)))
+    n = _ptg_rows(ptg)
+    if out is not None:
+        _numel(out, "tod", n)
     lib = N.load()
     _dev(alm, "alm", torch.complex128)
     _dev(blm, "blm", torch.complex128)
     _dev(ptg, "ptg", torch.float64)
     p = _prec(precision)
     dt = torch.float64 if p == N.SC_FP64 else torch.float32
-    n = ptg.shape[0]
     if out is None:
         out = torch.empty(n, dtype=dt, device=ptg.device)
     _dev(out, "tod", dt)
@@ -254,22 +273,28 @@ def convolve(alm: torch.Tensor, blm: torch.Tensor, lmax: int, kmax: int, ptg: to
     return out
 
 
+def release_cache():
+    """Free the plans cached by the one-shot convolve (sc_convolve_release_cache)."""
+    N.check(N.load().sc_convolve_release_cache(), "sc_convolve_release_cache")
+
+
 def dipole_response(blm: torch.Tensor, lmax: int, kmax: int, ptg: torch.Tensor, beta: torch.Tensor,
                     samples_per_period: int, T0: float, q: float, out: torch.Tensor | None = None) -> torch.Tensor:
     """Orbital dipole + quadrupole through the full beam (sc_dipole_response).
 
     beta: float64 [ceil(n / samples_per_period), 3], v / c per pointing period."""
+    n = _ptg_rows(ptg)
+    _numel(blm, "blm", n_alm(lmax, kmax))
+    if samples_per_period < 1:
+        raise ValueError("samples_per_period must be >= 1")
+    if beta.numel() < 3 * ((n + samples_per_period - 1) // samples_per_period):
+        raise ValueError("beta holds too few pointing periods")
+    if out is not None:
+        _numel(out, "out", n)
     lib = N.load()
     _dev(blm, "blm", torch.complex128)
     _dev(ptg, "ptg", torch.float64)
     _dev(beta, "beta", torch.float64)
-    n = ptg.shape[0]
-    if ptg.dim() != 2 or ptg.shape[1] != 3:
-        raise ValueError("ptg must be [n, 3]")
-    if blm.numel() != n_alm(lmax, kmax):
-        raise ValueError("blm size does not match lmax=%d kmax=%d" % (lmax, kmax))
-    if beta.numel() < 3 * ((n + samples_per_period - 1) // samples_per_period):
-        raise ValueError("beta holds too few pointing periods")
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=ptg.device)
     _dev(out, "out", torch.float64)
@@ -338,10 +363,13 @@ class Batch:
         N.check(lib.sc_batch_create(ctypes.byref(self._b), arr, len(dets), self.lmax_sky, self.precision,
                                     ctypes.c_void_p(_stream_handle(stream))), "sc_batch_create")
 
-    def run(self, alm_sky: torch.Tensor, use_graph: bool = True):
+    def run(self, alm_sky: torch.Tensor, use_graph: bool = True, stream=None):
+        """Enqueue the batch (or replay its graph) on `stream` (default: torch's current
+        stream), ordered after the batch's earlier work."""
+        _numel(alm_sky, "alm_sky", n_alm(self.lmax_sky))
         _dev(alm_sky, "alm_sky", torch.complex128)
-        if alm_sky.numel() != n_alm(self.lmax_sky):
-            raise ValueError("alm_sky size does not match lmax_sky=%d" % self.lmax_sky)
+        N.check(self._lib.sc_batch_set_stream(self._b, ctypes.c_void_p(_stream_handle(stream))),
+                "sc_batch_set_stream")
         self._sky = alm_sky
         N.check(self._lib.sc_batch_run(self._b, alm_sky.data_ptr(), 1 if use_graph else 0), "sc_batch_run")
         return [d["tod"] for d in self.dets]

@@ -854,13 +854,18 @@ hipError_t launch_mfma_any(sc_plan *p, void *tod) {
 }
 }  // namespace
 
-// W = 8 only; the FP64 staging of 208+ components would exceed the 160 KiB of LDS.
+// FP32 maps: W = 8.  FP64 maps: every even width (k_gather64.hip stages the block
+// in component chunks); the VALU form above is kept for W = 8 as a comparison
+// (env SC_GATHER_PATH=valu).
 bool sc_gather_binned_supported(const sc_plan *p) {
-    return p->W == 8 && p->ncomp <= (p->prec == SC_FP64 ? 208 : 256);
+    if (p->prec == SC_FP64) return sc_gather_mfma64_supported(p->W) && p->ncomp <= 256;
+    return p->W == 8 && p->ncomp <= 256;
 }
 
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod) {
-    if (p->prec == SC_FP64) return launch_binned_t<double>(p, tod);
+    if (p->prec == SC_FP64)
+        return p->gather_valu && p->W == 8 && p->ncomp <= 208 ? launch_binned_t<double>(p, tod)
+                                                             : sc_launch_gather_mfma64(p, tod);
     if (p->gather_valu) return launch_binned_t<float>(p, tod);
     return launch_mfma_any(p, tod);
 }

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <new>
@@ -138,42 +139,46 @@ void timing_end(sc_plan *p, int slot) {
     if (slot >= 0) (void)hipEventRecord(p->tl[slot].b, p->stream);
 }
 
-void free_bin_work(BinWork &w) {
+// Stream-ordered release: the buffers stay valid for everything already queued
+// on `s` and return to the pool when `s` reaches this point (no host wait).
+void free_bin_work(BinWork &w, hipStream_t s) {
     void *bufs[] = {w.count, w.offs, w.sums, w.totals, w.key, w.rank, w.sorted.rec, w.items};
     for (void *b : bufs)
-        if (b) (void)hipFree(b);
+        if (b) (void)hipFreeAsync(b, s);
     std::memset(&w, 0, sizeof(w));
 }
 
 int alloc(void **dst, size_t bytes, size_t *total);
+int alloc_async(void **dst, size_t bytes, size_t *total, hipStream_t s);
 
-// Binning workspace for passes of up to `need` samples (grown on demand).
+// Binning workspace for passes of up to `need` samples (grown on demand).  The
+// old buffers are released and the new ones allocated in the order of the plan's
+// stream, so work already queued keeps reading the old ones and the host never
+// waits for the device here.
 int ensure_bin_work(sc_plan *p, int64_t need) {
     BinWork &w = p->bw;
     if (w.cap >= need) return SC_OK;
     if (p->bin_fixed)
         return fail(SC_ESTATE, "plan belongs to a batch: %lld samples exceed its %lld-sample buffers",
                     (long long)need, (long long)w.cap);
-    // buffers are in use by earlier work on the stream until it completes
-    hipError_t e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return fail(SC_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     p->ws_bytes -= w.bytes;
-    free_bin_work(w);
+    free_bin_work(w, p->stream);
     const BinGeom g = sc_bin_geom(p);
     const int64_t nkeys = (int64_t)g.nkr * g.nkc;
     const int64_t nblk = (nkeys + 4095) / 4096;
     size_t tot = 0;
     int rc = SC_OK;
-    rc = rc ? rc : alloc((void **)&w.count, sizeof(int) * nkeys, &tot);
-    rc = rc ? rc : alloc((void **)&w.offs, sizeof(int2) * nkeys, &tot);
-    rc = rc ? rc : alloc((void **)&w.sums, sizeof(int2) * nblk, &tot);
-    rc = rc ? rc : alloc((void **)&w.totals, sizeof(int) * 4, &tot);
-    rc = rc ? rc : alloc((void **)&w.key, sizeof(int) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.rank, sizeof(int) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.sorted.rec, sizeof(BinRec) * need, &tot);
-    rc = rc ? rc : alloc((void **)&w.items, sizeof(int4) * need, &tot);
+    hipStream_t s = p->stream;
+    rc = rc ? rc : alloc_async((void **)&w.count, sizeof(int) * nkeys, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.offs, sizeof(int2) * nkeys, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.sums, sizeof(int2) * nblk, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.totals, sizeof(int) * 4, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.key, sizeof(int) * need, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.rank, sizeof(int) * need, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.sorted.rec, sizeof(BinRec) * need, &tot, s);
+    rc = rc ? rc : alloc_async((void **)&w.items, sizeof(int4) * need, &tot, s);
     if (rc) {
-        free_bin_work(w);
+        free_bin_work(w, s);
         return rc;
     }
     w.cap = need;
@@ -183,8 +188,18 @@ int ensure_bin_work(sc_plan *p, int64_t need) {
     return SC_OK;
 }
 
+// Release every buffer of a plan (the caller has synchronised its stream; the
+// stream-ordered ones are returned on the stream, which the caller then waits for).
 void free_plan_buffers(sc_plan *p) {
-    free_bin_work(p->bw);
+    free_bin_work(p->bw, p->stream);
+    {
+        void *pool[] = {p->twpsi, p->gpsi, p->cube};
+        for (void *b : pool)
+            if (b) (void)hipFreeAsync(b, p->stream);
+        p->twpsi = nullptr;
+        p->gpsi = nullptr;
+        p->cube = nullptr;
+    }
     if (p->gmaps) (void)hipFree(p->gmaps);
     if (p->GA) (void)hipFree(p->GA);
     if (p->GB) (void)hipFree(p->GB);
@@ -199,19 +214,57 @@ void free_plan_buffers(sc_plan *p) {
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
     void *bufs[] = {p->F, p->G, p->maps, p->rroot, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
-                    p->phase, p->dphi, p->glx, p->glw, p->twpsi, p->gpsi, p->cube};
+                    p->phase, p->dphi, p->glx, p->glw};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
 
+// Test hook: SC_FAIL_ALLOC_AFTER=k makes every allocation after the first k of the
+// process fail (read once), so tests can check that a failed allocation returns
+// SC_ENOMEM and releases what was already allocated.
+bool injected_alloc_failure() {
+    static const long long limit = [] {
+        const char *v = std::getenv("SC_FAIL_ALLOC_AFTER");
+        return v ? std::atoll(v) : -1LL;
+    }();
+    static std::atomic<long long> count{0};
+    return limit >= 0 && count.fetch_add(1) >= limit;
+}
+
 int alloc(void **dst, size_t bytes, size_t *total) {
-    hipError_t e = hipMalloc(dst, bytes);
+    hipError_t e = injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(dst, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *dst = nullptr;
         return fail(SC_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
     *total += bytes;
+    return SC_OK;
+}
+
+// Stream-ordered allocation (usable by work queued on `s` after this call, and by
+// other streams ordered after it).
+int alloc_async(void **dst, size_t bytes, size_t *total, hipStream_t s) {
+    hipError_t e = injected_alloc_failure() ? hipErrorOutOfMemory : hipMallocAsync(dst, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return fail(SC_ENOMEM, "hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    *total += bytes;
+    return SC_OK;
+}
+
+// Make `next` wait for everything queued so far on the plan's stream, then enqueue
+// the plan's later work on `next`.
+int switch_stream(sc_plan *p, hipStream_t next) {
+    if (next == p->stream) return SC_OK;
+    hipError_t e = hipSuccess;
+    if (!p->ev_stream) e = hipEventCreateWithFlags(&p->ev_stream, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_stream, p->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, p->ev_stream, 0);
+    if (e != hipSuccess) return hip_fail(e, "ordering the new stream after the plan's stream");
+    p->stream = next;
     return SC_OK;
 }
 
@@ -407,16 +460,19 @@ int sc_plan_destroy(sc_plan *p) {
     }
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->ev_stream) (void)hipEventDestroy(p->ev_stream);
     free_plan_buffers(p);
+    const hipError_t ef = hipStreamSynchronize(p->stream);  // the stream-ordered frees
+    if (e == hipSuccess) e = ef;
     delete p;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in sc_plan_destroy");
     return SC_OK;
 }
 
 int sc_plan_set_stream(sc_plan *p, void *stream) {
+    g_msg[0] = 0;
     if (!p) return fail(SC_EINVAL, "plan is NULL");
-    p->stream = (hipStream_t)stream;
-    return SC_OK;
+    return switch_stream(p, (hipStream_t)stream);
 }
 
 int sc_plan_info(const sc_plan *p, int64_t *out, int nout) {
@@ -463,6 +519,23 @@ static int check_interp_args(sc_plan *p, const double *ptg, void *tod) {
 }
 
 static bool uses_binning(const sc_plan *p) { return !p->gather_direct && sc_gather_binned_supported(p); }
+
+}  // extern "C"
+
+// Library-internal helpers for the other host sources.
+int sc_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+int sc_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+void sc_clear_error() { g_msg[0] = 0; }
+int sc_check_interp_args(sc_plan *p, const double *ptg, void *tod) { return check_interp_args(p, ptg, tod); }
+bool sc_uses_binning(const sc_plan *p) { return uses_binning(p); }
+
+extern "C" {
 
 // Binning pass of samples [off, off + cnt) on the plan's current stream.
 static int bin_pass(sc_plan *p, const double *ptg, int64_t off, int64_t cnt) {
@@ -511,11 +584,12 @@ int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     return interpolate_passes(p, ptg, n, tod, false);
 }
 
-// Free the psi cube and its tables (kept until the grid size changes).
+// Free the psi cube and its tables (kept until the grid size changes), in the
+// order of the plan's stream: earlier work may still read them.
 static void free_psi(sc_plan *p) {
     void *bufs[] = {p->twpsi, p->gpsi, p->cube};
     for (void *b : bufs)
-        if (b) (void)hipFree(b);
+        if (b) (void)hipFreeAsync(b, p->stream);
     p->twpsi = nullptr;
     p->gpsi = nullptr;
     p->cube = nullptr;
@@ -533,17 +607,15 @@ int sc_plan_build_psi_cube(sc_plan *p, int npsi) {
     if (npsi < lo || npsi > sc_psi_max_len() || !is_smooth(npsi))
         return fail(SC_EINVAL, "npsi = %d: needs a product of 2, 3, 5 in [%d, %d]", npsi, lo, sc_psi_max_len());
     if (npsi != p->npsi) {
-        const hipError_t es = hipStreamSynchronize(p->stream);  // a previous cube may still be read
-        if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize before the cube reallocation");
         free_psi(p);
         FftPlan P;
         if (!factor_fft(npsi, &P)) return fail(SC_EINVAL, "npsi = %d has no transform plan", npsi);
         const int npst = (npsi + p->W - 1 + 3) & ~3;
         const size_t bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * npst;
         size_t tot = 0;
-        int rc = alloc((void **)&p->twpsi, sizeof(double2) * npsi, &tot);
-        rc = rc ? rc : alloc((void **)&p->gpsi, sizeof(double) * (p->kmax + 1), &tot);
-        rc = rc ? rc : alloc(&p->cube, bytes + sc_psi_slack_bytes(), &tot);  // + the gather's zeroed slack
+        int rc = alloc_async((void **)&p->twpsi, sizeof(double2) * npsi, &tot, p->stream);
+        rc = rc ? rc : alloc_async((void **)&p->gpsi, sizeof(double) * (p->kmax + 1), &tot, p->stream);
+        rc = rc ? rc : alloc_async(&p->cube, bytes + sc_psi_slack_bytes(), &tot, p->stream);  // + the gather's zeroed slack
         if (rc) {
             free_psi(p);
             return rc;
@@ -647,9 +719,24 @@ int sc_convolve(const double *alm, const double *blm, int lmax, int kmax, const 
         pc.plans[key] = p;
     } else {
         p = it->second;
-        p->stream = (hipStream_t)stream;
+        // the cached plan's buffers may still be in use by work on another stream
+        const int rc = switch_stream(p, (hipStream_t)stream);
+        if (rc) return rc;
     }
     return sc_plan_convolve(p, alm, blm, ptg, n, tod);
+}
+
+int sc_convolve_release_cache(void) {
+    g_msg[0] = 0;
+    PlanCache &pc = plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    int rc = SC_OK;
+    for (auto &kv : pc.plans) {
+        const int r = sc_plan_destroy(kv.second);
+        if (r && rc == SC_OK) rc = r;
+    }
+    pc.plans.clear();
+    return rc;
 }
 
 int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
@@ -913,6 +1000,7 @@ struct sc_batch {
     hipGraphExec_t exec;
     const double *graph_alm;
     hipStream_t cap_stream;  // private stream for capture (the legacy null stream cannot be captured)
+    hipEvent_t ev_stream;    // orders a new stream after the old one (sc_batch_set_stream)
 };
 
 namespace {
@@ -953,6 +1041,7 @@ int sc_batch_destroy(sc_batch *b) {
     hipError_t e = hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ev_stream) (void)hipEventDestroy(b->ev_stream);
     for (sc_plan *p : b->plans) sc_plan_destroy(p);
     if (b->dets_dev) (void)hipFree(b->dets_dev);
     if (b->cursor) (void)hipFree(b->cursor);
@@ -1121,6 +1210,21 @@ int sc_batch_run(sc_batch *b, const double *alm_sky, int use_graph) {
     b->graph_alm = alm_sky;
     e = hipGraphLaunch(b->exec, b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SC_OK;
+}
+
+int sc_batch_set_stream(sc_batch *b, void *stream) {
+    g_msg[0] = 0;
+    if (!b) return fail(SC_EINVAL, "batch is NULL");
+    hipStream_t next = (hipStream_t)stream;
+    if (next == b->stream) return SC_OK;
+    hipError_t e = hipSuccess;
+    if (!b->ev_stream) e = hipEventCreateWithFlags(&b->ev_stream, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_stream, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, b->ev_stream, 0);
+    if (e != hipSuccess) return hip_fail(e, "ordering the new stream after the batch's stream");
+    b->stream = next;
+    for (sc_plan *p : b->plans) p->stream = next;
     return SC_OK;
 }
 

@@ -100,6 +100,7 @@ struct sc_plan {
     hipStream_t stream;
     hipStream_t side;             // sc_plan_convolve: binning beside the map synthesis
     hipEvent_t ev_fork, ev_join;  // (created on first use)
+    hipEvent_t ev_stream;         // orders a new stream after the old one (sc_plan_set_stream)
 
     FftPlan p2, p2os, pphi;
 
@@ -119,7 +120,7 @@ struct sc_plan {
 
     int have_maps;
     size_t ws_bytes;
-    BinWork bw;
+    BinWork bw;        // stream-ordered allocations (hipMallocAsync / hipFreeAsync on the plan's stream)
     void *gmaps;       // adjoint: gradient maps, same layout as maps (allocated on first use)
     double2 *GA;       // adjoint: per-k gradient contributions [kmax+1][n_alm]
     double2 *GB;       // beam adjoint: per-m gradient contributions [lmax+1][n_blm] (allocated on first use)
@@ -140,7 +141,7 @@ struct sc_plan {
     FftPlan ppsi;
     double2 *twpsi;        // pass-major twiddles of the npsi-point transform
     double *gpsi;          // [kmax+1] 1 / hhat_psi(k)
-    void *cube;
+    void *cube;        // twpsi, gpsi and cube: stream-ordered allocations like bw
     int have_cube;
     int timing;
     struct TimedLaunch *tl;  // pool of event pairs
@@ -182,6 +183,8 @@ hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
 hipError_t sc_launch_dipole(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
                             int64_t spp, double T0, double q, double *out, hipStream_t stream);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
+bool sc_gather_mfma64_supported(int W);
+hipError_t sc_launch_gather_mfma64(sc_plan *p, void *tod);
 GatherDet sc_gather_det(const sc_plan *p, void *tod);
 hipError_t sc_launch_gather_batch(const GatherDet *dets_dev, int ndet, int max_ct, int *cursor, int wgs_per_cu, int waves,
                                   int mma, hipStream_t stream);
@@ -198,6 +201,14 @@ static inline BinGeom sc_bin_geom(const sc_plan *p) {
     g.nkc = p->nphi;
     return g;
 }
+
+// Host-side helpers of sc_api.cpp: the calling thread's error message (sc_last_error),
+// and the argument checks and path choice of an interpolation.
+int sc_error(int code, const char *fmt, ...);
+int sc_hip_error(hipError_t e, const char *what);
+void sc_clear_error();
+int sc_check_interp_args(sc_plan *p, const double *ptg, void *tod);
+bool sc_uses_binning(const sc_plan *p);
 
 // Set a kernel's dynamic-LDS limit once (cached; safe to call while a stream is
 // being captured into a graph, since a cached call makes no runtime call).

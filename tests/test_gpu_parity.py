@@ -5,7 +5,10 @@ Every input is seeded (workloads/); the oracle computes the plain sum of Eq. 2
   * ring sums (FP64 recursion): 1e-12 relative to the column maximum;
   * FP64 plan, W = 14: rel-L2 <= 1e-12 (interpolation error ~4e-14 + rounding);
   * FP32-gather plan, W = 8: rel-L2 <= 1e-6, the stated target (kernel error
-    ~3e-8, FP32 map rounding ~1e-7).
+    ~3e-8, FP32 map rounding ~1e-7);
+  * every TOD comparison also bounds max|d| / max|c| by ten times its rel-L2 bar.
+The headline workload (lmax 512, kmax 100, 1e7 scan samples) is compared on the
+2,000 samples stored in tests/golden/ by the oracle.
 """
 import math
 
@@ -13,6 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import assert_parity, coef_hash, load_golden, place_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -90,9 +94,7 @@ def test_end_to_end_fp64_tiny_workload(torch_dev, api, oracle_lib):
     torch.cuda.synchronize()
     got = tod.cpu().numpy()
     ref = oracle_lib.convolve(a, b, L, K, p)
-    e = _rel_l2(got, ref)
-    print("fp64 tiny rel-L2 %.3e max %.3e" % (e, np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
-    assert e <= 1e-12
+    assert_parity(got, ref, 1e-12, "fp64 tiny (all 1e5 samples)")
 
 
 @pytest.mark.parametrize("L,K,n", [(16, 3, 777), (48, 10, 5000), (100, 100, 300)])
@@ -106,30 +108,37 @@ def test_end_to_end_f32_small(torch_dev, api, oracle_lib, L, K, n):
     torch.cuda.synchronize()
     got = tod.cpu().numpy().astype(np.float64)
     ref = oracle_lib.convolve(a, b, L, K, p)
-    e = _rel_l2(got, ref)
-    print("f32 L=%d K=%d rel-L2 %.3e" % (L, K, e))
-    assert e <= 1e-6
+    assert_parity(got, ref, 1e-6, "f32 L=%d K=%d" % (L, K))
 
 
-def test_end_to_end_sidelobe_workload_sampled(torch_dev, api, oracle_lib):
-    """lmax 512, kmax 100, 1e7 scan samples (the benchmarked configuration): sampled outputs vs oracle."""
+@pytest.mark.parametrize("prec,width,bar", [("f64maps_f32gather", 8, 1e-6), ("fp64", 8, 1e-6),
+                                             ("fp64", 14, 1e-12)])
+def test_sidelobe_workload_against_stored_oracle(torch_dev, api, prec, width, bar):
+    """lmax 512, kmax 100, 1e7 scan samples in the benchmark's launch configuration
+    (one sc_plan_convolve): 2,000 stored oracle samples, eight of them edge pointings
+    (poles, phi and psi next to 2 pi), compared element by element.  The FP64 form
+    at W = 8 is the benchmark's comparison form (1e-6 target); at W = 14 it is the
+    1e-12 form."""
     torch, dev = torch_dev
-    cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
-    L, K, n = cfg["lmax"], cfg["kmax"], cfg["n"]
+    (g,) = load_golden("sidelobe-lmax512-kmax100-scan1e7")
+    L, K, n = g["lmax"], g["kmax"], g["n"]
     a, b = _inputs(L, K, 2)
+    assert coef_hash(a, b) == g["coef_sha"]
     ptg = W.scan_pointings(n, device=dev)
-    plan = api.Plan(L, K, "f64maps_f32gather")
-    plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
-    tod = plan.interpolate(ptg)
+    it = torch.as_tensor(g["idx"], device=dev)
+    # the stored pointings are the scan's own (apart from the edge ones)
+    scan = ptg[it].cpu().numpy()
+    plain = np.ones(len(it), dtype=bool)
+    plain[1:9] = False
+    d = np.abs(scan[plain] - g["ptg"][plain])
+    d[:, 1:] = np.minimum(d[:, 1:], 2 * math.pi - d[:, 1:])  # phi, psi wrap at 2 pi
+    assert np.max(d) <= 1e-9
+    place_golden(torch, ptg, g)
+    plan = api.Plan(L, K, prec, kernel_width=width)
+    tod = plan.convolve(_to(torch, dev, a), _to(torch, dev, b), ptg)
     torch.cuda.synchronize()
-    idx = np.sort(np.random.default_rng(W.config_seed(2, 6)).choice(n, 24, replace=False))
-    idx[0], idx[-1] = 0, n - 1
-    sub = ptg[torch.as_tensor(idx, device=dev)].cpu().numpy()
-    got = tod[torch.as_tensor(idx, device=dev)].cpu().numpy().astype(np.float64)
-    ref = oracle_lib.convolve(a, b, L, K, sub)
-    e = _rel_l2(got, ref)
-    print("sidelobe sampled rel-L2 %.3e" % e)
-    assert e <= 1e-6
+    got = tod[it].double().cpu().numpy()
+    assert_parity(got, g["c"], bar, "sidelobe %s W=%d vs stored oracle" % (prec, width))
 
 
 @pytest.mark.parametrize("L,kind,n", [(64, "scan", 2_000_000), (512, "scan", 2_000_000),
@@ -245,8 +254,8 @@ def test_binned_gather_edge_cases(torch_dev, api, oracle_lib, prec):
     tol_same = 1e-6 if prec != "fp64" else 1e-13
     assert np.max(np.abs(binned - direct)) <= tol_same * np.max(np.abs(ref))
     assert np.max(np.abs(valu - direct)) <= tol_same * np.max(np.abs(ref))
-    for got in (binned, direct, valu):
-        assert _rel_l2(got, ref) <= (1e-6 if prec != "fp64" else 1e-7)
+    for name, got in (("binned", binned), ("direct", direct), ("valu", valu)):
+        assert_parity(got, ref, 1e-6 if prec != "fp64" else 1e-7, "%s edge cases %s" % (prec, name))
 
 
 @pytest.mark.parametrize("L,K", [(64, 20), (128, 100)])
@@ -268,7 +277,7 @@ def test_gather_workgroup_shapes_agree(torch_dev, api, oracle_lib, L, K):
     idx = torch.arange(0, 30000, 3001, device=dev)
     ref = oracle_lib.convolve(a, b, L, K, p[idx].cpu().numpy())
     got = out[8][idx].double().cpu().numpy()
-    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
+    assert_parity(got, ref, 1e-6, "8-wave FP32 products L=%d K=%d" % (L, K))
 
 
 @pytest.mark.parametrize("L,K,n", [(64, 20, 30000), (512, 100, 300000)])
@@ -295,11 +304,11 @@ def test_gather_product_forms_agree(torch_dev, api, oracle_lib, L, K, n):
     mx = float(d.abs().max() / out[api.N.SC_MMA_FP32].abs().max())
     print("L=%d K=%d split vs fp32 products: rel-L2 %.3e max %.3e" % (L, K, rel, mx))
     assert rel <= 5e-7 and mx <= 5e-6
-    idx = torch.arange(0, n, n // 40, device=dev)
+    idx = torch.arange(0, n, n // (200 if L < 256 else 60), device=dev)
     ref = oracle_lib.convolve(a, b, L, K, p[idx].cpu().numpy())
     for mma, o in out.items():
         got = o[idx].cpu().numpy()
-        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6, mma
+        assert_parity(got, ref, 1e-6, "product form %d L=%d K=%d" % (mma, L, K))
 
 
 @pytest.mark.parametrize("e", [-80, 80])
@@ -317,3 +326,72 @@ def test_split_form_power_of_two_scaling(torch_dev, api, e):
     scaled = plan.interpolate(p).clone()
     torch.cuda.synchronize()
     assert torch.equal(scaled, base * 2.0 ** e)
+
+
+def test_two_streams_share_a_plan_safely(torch_dev, api):
+    """A plan (and the one-shot call's cached plan) used on two torch streams in turn: each
+    call waits for the other stream's earlier work on the shared workspace (maps, binning
+    buffers, which the second call also grows), so the TOD equals a one-stream run bit for
+    bit."""
+    torch, dev = torch_dev
+    L, K = 128, 16
+    a1, b = _inputs(L, K, 41)
+    a2 = W.sky_alm(L, 42)
+    at1, at2, bt = _to(torch, dev, a1), _to(torch, dev, a2), _to(torch, dev, b)
+    p1 = W.scan_pointings(300_000, device=dev)
+    p2 = W.scan_pointings(700_000, start=5_000_000, device=dev)
+
+    def serial(run):
+        t1 = run(at1, p1).clone()
+        t2 = run(at2, p2).clone()
+        torch.cuda.synchronize()
+        return t1, t2
+
+    def two_streams(run):
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        s1.wait_stream(torch.cuda.current_stream())
+        s2.wait_stream(torch.cuda.current_stream())
+        outs = []
+        for rep in range(3):
+            with torch.cuda.stream(s1):
+                t1 = run(at1, p1)
+            with torch.cuda.stream(s2):
+                t2 = run(at2, p2)
+            outs.append((t1, t2))
+        torch.cuda.synchronize()
+        return outs
+
+    plan = api.Plan(L, K, "f64maps_f32gather")
+    r1, r2 = serial(lambda a, p: plan.convolve(a, bt, p))
+    plan2 = api.Plan(L, K, "f64maps_f32gather")
+    for t1, t2 in two_streams(lambda a, p: plan2.convolve(a, bt, p)):
+        assert torch.equal(t1, r1) and torch.equal(t2, r2)
+    api.release_cache()
+    o1, o2 = serial(lambda a, p: api.convolve(a, bt, L, K, p))
+    assert torch.equal(o1, r1) and torch.equal(o2, r2)
+    api.release_cache()
+    for t1, t2 in two_streams(lambda a, p: api.convolve(a, bt, L, K, p)):
+        assert torch.equal(t1, r1) and torch.equal(t2, r2)
+    api.release_cache()
+
+
+def test_batch_on_another_stream(torch_dev, api):
+    """A batch created on one stream and run on another waits for its earlier work."""
+    torch, dev = torch_dev
+    sky = _to(torch, dev, W.sky_alm(64, 43))
+    dets = [dict(lmax=64, kmax=8, blm=_to(torch, dev, W.beam_alm(64, 8, 44)),
+                 ptg=W.scan_pointings(200_000, device=dev)),
+            dict(lmax=32, kmax=4, blm=_to(torch, dev, W.beam_alm(32, 4, 45)),
+                 ptg=W.scan_pointings(100_000, start=77, device=dev))]
+    bt = api.Batch(dets, 64)
+    ref = [t.clone() for t in bt.run(sky, use_graph=False)]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for use_graph in (False, True, True):
+            outs = [t.clone() for t in bt.run(sky, use_graph=use_graph)]
+            for o, r in zip(outs, ref):
+                assert torch.equal(o, r)
+    torch.cuda.synchronize()
+    bt.close()
