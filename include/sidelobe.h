@@ -142,6 +142,23 @@ int sc_set_sky_beam(sc_plan *plan, const double *alm, const double *blm);
 int sc_interpolate(sc_plan *plan, const double *ptg, int64_t n, void *tod);
 
 /*
+ * sc_interpolate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * result from the same kernels, with the binning workspace in a fixed 256 MiB
+ * device array that the library holds on each GPU it runs on until the process
+ * ends, instead of plan workspace.  Samples are binned in passes of what the
+ * array holds beside the plan's anchor tables (12 bytes per interpolation
+ * anchor, 56 bytes per sample), so n is not limited; a grid whose anchor
+ * tables leave no room for 4096 samples (lmax above about 1400) returns
+ * SC_EINVAL.  Calls no hipMalloc, hipFree or other allocating routine (the
+ * array's device address is looked up on the first call on each device).
+ * Every call on one GPU shares that GPU's array: calls that overlap on a GPU
+ * (other streams, plans or threads) race, so the caller orders them.  Same
+ * arguments, layouts, stream and errors as sc_interpolate.
+ */
+int sc_interpolate_noalloc(sc_plan *plan, const double *ptg, int64_t n, void *tod);
+
+/*
  * The second step of the two-step algorithm (Sec. 2.1): the Fourier series over
  * k of the plan's current component maps, evaluated on a grid of npsi points in
  * psi at every (theta, phi) grid point and divided by the interpolation

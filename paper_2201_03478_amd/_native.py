@@ -22,7 +22,7 @@ SC_MMA_FP32, SC_MMA_SPLIT16 = 0, 1
 
 EXPORTS = (
     "sc_plan_create", "sc_plan_destroy", "sc_plan_set_stream", "sc_plan_info", "sc_set_sky_beam",
-    "sc_interpolate", "sc_plan_build_psi_cube", "sc_interpolate_psi", "sc_plan_convolve", "sc_convolve", "sc_convolve_release_cache", "sc_dipole_response", "sc_convolve_adjoint", "sc_convolve_adjoint_beam", "sc_debug_copy_stage", "sc_plan_enable_timing",
+    "sc_interpolate", "sc_interpolate_noalloc", "sc_plan_build_psi_cube", "sc_interpolate_psi", "sc_plan_convolve", "sc_convolve", "sc_convolve_release_cache", "sc_dipole_response", "sc_convolve_adjoint", "sc_convolve_adjoint_beam", "sc_debug_copy_stage", "sc_plan_enable_timing",
     "sc_plan_stage_times", "sc_plan_set_param", "sc_plan_get_param", "sc_batch_create", "sc_batch_run",
     "sc_batch_set_param", "sc_batch_get_param", "sc_batch_set_stream", "sc_batch_plan", "sc_batch_destroy", "sc_strerror",
     "sc_last_error",
@@ -60,6 +60,7 @@ def load():
     lib.sc_plan_info.argtypes = [vp, ctypes.POINTER(i64), i32]
     lib.sc_set_sky_beam.argtypes = [vp, vp, vp]
     lib.sc_interpolate.argtypes = [vp, vp, i64, vp]
+    lib.sc_interpolate_noalloc.argtypes = [vp, vp, i64, vp]
     lib.sc_plan_convolve.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.sc_plan_build_psi_cube.argtypes = [vp, i32]
     lib.sc_interpolate_psi.argtypes = [vp, vp, i64, vp]
