@@ -78,7 +78,9 @@ static ld sqrt_binom(int l, int n)
 {
     int a = l + iabs_(n); /* C(2l, l+|n|) = C(2l, l-|n|) */
     ld c = 1.0L;
-    for (int i = 1; i <= 2 * l - a; ++i) c = c * (ld)(a + i) / (ld)i;
+    /* each factor (a + i) / i is formed first, so the running product never exceeds
+       C(2l, a) itself (about 1e4930 at l = 8192, inside the long double range) */
+    for (int i = 1; i <= 2 * l - a; ++i) c *= (ld)(a + i) / (ld)i;
     return sqrtl(c);
 }
 
@@ -110,24 +112,45 @@ static ld d_start(int m, int k, ld c, ld s)
     return sg * sqrt_binom(l, m) * ipow_(c, l - m) * ipow_(s, l + m);
 }
 
-/* d[l] = d^l_{mk}(theta) for 0 <= l <= lmax (zero below l0). */
+/* d[l] = d^l_{mk}(theta) for 0 <= l <= lmax (zero below l0), 0 <= theta <= pi/2. */
+static void d_column_north(int lmax, int m, int k, ld theta, ld *d);
+
+/* d[l] = d^l_{mk}(theta) for 0 <= l <= lmax (zero below l0).  Past the equator the
+   column comes from d^l_{mk}(theta) = (-1)^{l+k} d^l_{-m,k}(pi - theta), so the
+   recursion always runs at an angle whose 1 - cos is small near the nearer pole
+   and keeps its full relative precision there. */
 static void d_column(int lmax, int m, int k, ld theta, ld *d)
+{
+    const ld pi = 3.141592653589793238462643383279502884L;
+    if (theta <= 0.5L * pi) {
+        d_column_north(lmax, m, k, theta, d);
+        return;
+    }
+    d_column_north(lmax, -m, k, pi - theta, d);
+    for (int l = 0; l <= lmax; ++l)
+        if ((l + k) & 1) d[l] = -d[l];
+}
+
+static void d_column_north(int lmax, int m, int k, ld theta, ld *d)
 {
     int l0 = imax_(iabs_(m), iabs_(k));
     for (int l = 0; l <= lmax && l < l0; ++l) d[l] = 0.0L;
     if (l0 > lmax) return;
-    ld x = cosl(theta);
     ld c = cosl(0.5L * theta), s = sinl(0.5L * theta);
+    /* 1 - cos(theta) = 2 sin^2(theta/2) at full relative precision: the coefficient
+       l(l+1) cos(theta) - m k is evaluated as (l(l+1) - m k) - l(l+1) y, so near the
+       poles the rounding of cos(theta) does not move the effective angle */
+    ld y = 2.0L * s * s;
     ld dl = d_start(m, k, c, s), dm = 0.0L;
     d[l0] = dl;
     ld mm = (ld)m * m, kk = (ld)k * k, mk = (ld)m * k;
     for (int l = l0; l < lmax; ++l) {
         ld dn;
         if (l == 0) {
-            dn = x * dl; /* m = k = 0: d^1_00 = cos(theta) */
+            dn = (1.0L - y) * dl; /* m = k = 0: d^1_00 = cos(theta) */
         } else {
             ld L = (ld)l, L1 = (ld)(l + 1);
-            ld num1 = (2.0L * L + 1.0L) * (L * L1 * x - mk);
+            ld num1 = (2.0L * L + 1.0L) * ((L * L1 - mk) - L * L1 * y);
             ld num2 = L1 * sqrtl((L * L - mm) * (L * L - kk));
             ld den = L * sqrtl((L1 * L1 - mm) * (L1 * L1 - kk));
             dn = (num1 * dl - num2 * dm) / den;

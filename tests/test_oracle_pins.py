@@ -73,6 +73,22 @@ def test_P2_unitarity_to_l1024(oracle_lib):
             assert np.max(np.abs(s[ok] - 1.0)) < 1e-12, (theta, k)
 
 
+@pytest.mark.parametrize("theta", [0.5 * math.pi / 8640, 1.1, math.pi - 2.5 * math.pi / 8640])
+def test_P2_unitarity_at_l8192(oracle_lib, theta):
+    """sum_m d^L_mk(theta)^2 = 1 at L = 8192 (the largest band limit), on the rings next to
+    the poles where the start values are below 1e-30000, read through the ring sums of a sky
+    and a beam that are 1 at l = L only: F_k(theta, m) = a_Lm d^L_mk(theta) with |a_Lm| = 1."""
+    L, K = 8192, 2
+    a = np.zeros(oracle_lib.n_alm(L), complex)
+    a[[oracle_lib.alm_index(L, L, m) for m in range(L + 1)]] = 1.0
+    for k0 in (0, 2):
+        b = np.zeros(oracle_lib.n_alm(L, K), complex)
+        b[oracle_lib.alm_index(L, L, k0)] = 1.0
+        F = oracle_lib.ring_sums(a, b, L, K, [theta])[k0, 0]  # [m + L]
+        assert np.all(np.isfinite(F))
+        assert abs(np.sum(np.abs(F) ** 2) - 1.0) < 1e-12, (theta, k0)
+
+
 def test_P2b_gauss_legendre_orthogonality(oracle_lib):
     """sum_j w_j d^l_mk(theta_j) d^l'_mk(theta_j) = 2/(2l+1) delta_ll' (exact quadrature)."""
     L, K = 40, 5
