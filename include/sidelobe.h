@@ -68,6 +68,9 @@ extern "C" {
 
 typedef struct sc_plan sc_plan;
 
+/* Largest supported band limit. */
+#define SC_LMAX_MAX 8192
+
 enum sc_status {
     SC_OK = 0,
     SC_EINVAL = -1,
@@ -92,9 +95,12 @@ enum sc_precision {
 
 /*
  * Create a plan for one (lmax, kmax, precision).
- *   lmax          0 <= lmax <= 2303, band limit of sky and beam (the theta and
- *                 phi transforms, of about 4 lmax points, are held in LDS, at
- *                 most 9216 points); larger: SC_EINVAL.
+ *   lmax          0 <= lmax <= SC_LMAX_MAX (8192), band limit of sky and beam.
+ *                 The theta and phi transforms (about 2 lmax and 4 lmax
+ *                 points) run in one workgroup's LDS up to 9216 points; above
+ *                 that (lmax > 2303) each runs as several LDS transforms through
+ *                 an extra (kmax + 1)(2 lmax + 1)^2 complex128 plan buffer.
+ *                 Larger lmax: SC_EINVAL.
  *   kmax          0 <= kmax <= min(lmax, 127), beam azimuthal truncation
  *                 (kmax = 0 is the axisymmetric case, a spin-0 transform only;
  *                 Sec. 2.1).
@@ -224,10 +230,10 @@ int sc_convolve_release_cache(void);
  *   alm_grad  device complex128, alm layout (overwritten).
  * The scatter accumulates with floating-point atomics, so the last bits vary
  * between runs.  Uses (and overwrites) the plan's transform buffers; the maps
- * made by sc_set_sky_beam are kept.  The adjoint recursion holds every ring of
- * a (k, m) column in one workgroup, which limits it to lmax <= 2047 (at most
- * 2048 rings); plans above that return SC_EINVAL here and in
- * sc_convolve_adjoint_beam.
+ * made by sc_set_sky_beam are kept.  The adjoint recursion sums over rings in
+ * workgroups of at most 2048 rings; longer columns (lmax >= 2048) are split
+ * into ring slabs whose partial gradients are added in a fixed order, so the
+ * gradient workspace grows by the slab count (ceil(rings / 2048)).
  */
 int sc_convolve_adjoint(sc_plan *plan, const double *blm, const double *ptg, const void *tod_grad, int64_t n,
                         double *alm_grad);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libsidelobe.so")
-SOURCES = ["sc_api.cpp", "k_tables.hip", "k_synth.hip", "k_synth_adj.hip", "k_synth_mixed.hip", "k_fft.hip", "k_bin.hip",
+SOURCES = ["sc_api.cpp", "k_tables.hip", "k_synth.hip", "k_synth_adj.hip", "k_synth_mixed.hip", "k_fft.hip", "k_fft_big.hip", "k_bin.hip",
            "k_gather.hip", "k_gather64.hip", "k_scatter.hip", "k_dipole.hip", "k_psi.hip", "sc_noalloc.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -448,6 +448,7 @@ using F2160 = FftSpec<2160, SC_PLAN_2160>;
 using F4320 = FftSpec<4320, SC_PLAN_4320>;
 
 hipError_t sc_launch_theta_upsample(sc_plan *p) {
+    if (p->big) return sc_launch_theta_upsample_big(p);
     if (p->n2 == 540 && p->n2os == 1080) return theta_up<128, 9, F540, F1080>(p);
     if (p->n2 == 1080 && p->n2os == 2160) return theta_up<SC_FFT_NT, SC_FFT_PT, F1080, F2160>(p);
     if (p->n2 == 2160 && p->n2os == 4320) return theta_up<SC_FFT_NT_BIG, SC_FFT_PT, F2160, F4320>(p);
@@ -471,6 +472,7 @@ static hipError_t phi_syn_any(sc_plan *p) {
 }
 
 hipError_t sc_launch_phi_synthesis(sc_plan *p) {
+    if (p->big) return sc_launch_phi_synthesis_big(p);
     return p->prec == SC_FP64 ? phi_syn_any<double>(p) : phi_syn_any<float>(p);
 }
 
@@ -484,10 +486,12 @@ static hipError_t phi_adj_any(sc_plan *p, const void *gmaps) {
 }
 
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {
+    if (p->big) return sc_launch_phi_adjoint_big(p, gmaps);
     return p->prec == SC_FP64 ? phi_adj_any<double>(p, gmaps) : phi_adj_any<float>(p, gmaps);
 }
 
 hipError_t sc_launch_theta_adjoint(sc_plan *p) {
+    if (p->big) return sc_launch_theta_adjoint_big(p);
     if (p->n2 == 540 && p->n2os == 1080) return theta_adj<128, 9, F540, F1080>(p);
     if (p->n2 == 1080 && p->n2os == 2160) return theta_adj<SC_FFT_NT, SC_FFT_PT, F1080, F2160>(p);
     if (p->n2 == 2160 && p->n2os == 4320) return theta_adj<SC_FFT_NT_BIG, SC_FFT_PT, F2160, F4320>(p);

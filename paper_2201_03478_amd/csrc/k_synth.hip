@@ -11,7 +11,9 @@
 // are placed symmetrically, theta_{nring-1-j} = pi - theta_j.
 //
 // d^l_mk(theta) comes from the three-term recursion in l,
-//   d^{l+1} = (alpha_l cos(theta) - beta_l) d^l - gamma_l d^{l-1},
+//   d^{l+1} = (alpha_l cos(theta) - beta_l) d^l - gamma_l d^{l-1}
+//           = ((alpha_l - beta_l) - alpha_l y) d^l - gamma_l d^{l-1},  y = 1 - cos(theta)
+// (the second form is evaluated, with y = 2 sin^2(theta/2) at full relative precision),
 //   alpha_l = (2l+1)(l+1) / sqrt(((l+1)^2-m^2)((l+1)^2-k^2)),
 //   beta_l  = alpha_l m k / (l(l+1)),
 //   gamma_l = (l+1)/l sqrt((l^2-m^2)(l^2-k^2)) / sqrt(((l+1)^2-m^2)((l+1)^2-k^2)),
@@ -30,7 +32,7 @@
 //   u^{l+1} = (a_l cos(theta) - b_l) u^l - u^{l-1},  a_l = alpha_l S_l / S_{l+1},
 //   b_l = beta_l S_l / S_{l+1},
 // and folds S_l into the contraction weights: per d value one FMA forms
-// a_l cos(theta) - b_l, one FMA advances u and four FMAs contract it (both signs
+// (a_l - b_l) - a_l y, one FMA advances u and four FMAs contract it (both signs
 // of m, real and imaginary parts).  S_l is O(1) (gamma_l -> 1; the alternating
 // products of gamma telescope to about sqrt(l0 / l)), so u stays as well
 // conditioned as d.  Every ring accumulates its scaled u unconditionally: while
@@ -41,18 +43,34 @@
 // (|d| <= 1, |u| = O(1) from then on) the loop runs without it.  Both loops
 // cost the same six FMAs per d value.
 //
-// Layout: one 64-lane wave per (m, k, ring group); each lane carries RPT
-// rings.  Recursion coefficients and weights for 64 consecutive l are built
-// cooperatively in LDS (one l per lane, the square roots of alpha_l and gamma_l
-// from a per-plan table of sqrt((l+1)^2 - x^2); S_l by a product scan over the
-// lanes of each parity) and read as broadcasts.
+// Every recursion runs on a northern ring (theta_j <= pi/2), where y is small
+// next to the pole and exact in relative terms; the southern rings come from the
+// reflection d^l_mk(pi - theta) = (-1)^{l+k} d^l_{-m,k}(theta).  So for m > 0 the
+// column (m, k) runs two recursions per northern ring j:
+//   R+ (the column (m, k)):  F_k(theta_j, m) and, mirrored, F_k(pi - theta_j, -m);
+//   R- (the column (-m, k)): F_k(theta_j, -m) = sum_l (-1)^m conj(a_lm) conj(b_lk) d^l_{-m,k}
+//                           and F_k(pi - theta_j, m) = sum_l (-1)^{l+k} a_lm conj(b_lk) d^l_{-m,k}.
+// R- has beta_l of the opposite sign (alpha_l + beta_l in place of alpha_l - beta_l),
+// the same gamma_l (so the same S_l) and the start value with the exponents of
+// c and s exchanged and no sign.  For m = 0 the two coincide and R+ alone, with
+// its mirror, covers every ring.  Rings past the equator are never recursed, so
+// the rounding of cos(theta) next to the south pole cannot move the angle.
+//
+// Layout: one 64-lane wave per (m, k, ring group); lanes 0-31 run R+ and lanes
+// 32-63 run R- on the same northern rings, RPT rings per lane.  Recursion
+// coefficients and weights for 64 consecutive l are built cooperatively in LDS
+// (one l per lane, the square roots of alpha_l and gamma_l from a per-plan table of
+// sqrt((l+1)^2 - x^2); S_l by a product scan over the lanes of each parity) for
+// both recursions; a step reads alpha_l as a broadcast and the rest from the
+// lane's half (two addresses per read, one instruction as before).
 #include "wigner_rec.h"
 
 namespace {
 
 using namespace wrec;
 
-// Coefficients and weights of one step (l -> l+1), read from LDS.
+// Coefficients and weights of one step (l -> l+1) for the lane's recursion (R+ or
+// R-, tp = 0 or 1), read from LDS: a = a_l, b = a_l -+ b_l.
 struct RecCoef {
     double a, b;
     double2 wp, wm;
@@ -60,7 +78,8 @@ struct RecCoef {
 
 __device__ __forceinline__ RecCoef rec_load(int t, const double *cA, const double *cB, const double2 *cWp,
                                             const double2 *cWm) {
-    return RecCoef{cA[t], cB[t], cWp[t], cWm[t]};
+    // cB, cWp, cWm already point at the lane's half: entry (t, tp) at 2 t + tp
+    return RecCoef{cA[t], cB[2 * t], cWp[2 * t], cWm[2 * t]};
 }
 
 // One recursion step for every ring of the lane: contract u^l (true value
@@ -74,7 +93,7 @@ __device__ __forceinline__ void rec_step(const RecCoef &c, const double *x, doub
         fp[r].y = fma(c.wp.y, u[r], fp[r].y);
         fm[r].x = fma(c.wm.x, u[r], fm[r].x);
         fm[r].y = fma(c.wm.y, u[r], fm[r].y);
-        const double un = fma(fma(c.a, x[r], -c.b), u[r], -up[r]);
+        const double un = fma(fma(-c.a, x[r], c.b), u[r], -up[r]);  // x holds y = 1 - cos(theta)
         up[r] = u[r];
         u[r] = un;
     }
@@ -114,8 +133,8 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
             const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
-    __shared__ double cA[64], cB[64];
-    __shared__ double2 cWp[64], cWm[64];
+    __shared__ double cA[64], cB[64 * 2];
+    __shared__ double2 cWp[64 * 2], cWm[64 * 2];
 
     int b = blockIdx.x;
     const int g = b % ngroups;
@@ -123,9 +142,11 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     const int k = b % (kmax + 1);
     const int m = b / (kmax + 1);
     const int lane = threadIdx.x;
+    const int tp = lane >> 5, sub = lane & 31;  // recursion R+ (0) or R- (1); northern ring slot
     const int l0 = m > k ? m : k;
     const int mn = m < k ? m : k;
     const int nm = 2 * lmax + 1;
+    const int nh = (nring + 1) / 2;  // northern rings, theta_j <= pi/2
 
     double x[RPT], u[RPT], up[RPT];
     int e[RPT];
@@ -136,12 +157,15 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     bool scaled = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int j = (g * RPT + r) * 64 + lane;
+        const int j = (g * RPT + r) * 32 + sub;
+        // R- has no work for m = 0 (R+ mirrors onto every ring) or on the equator ring of
+        // an odd ring count (R+ writes both of its values)
+        const bool on = j < nh && (tp == 0 || (m > 0 && j != nring - 1 - j));
         fp[r] = make_double2(0.0, 0.0);
         fm[r] = make_double2(0.0, 0.0);
         up[r] = 0.0;
-        if (j < nring) {
-            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], u[r], e[r]);
+        if (on) {
+            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], u[r], e[r], tp == 1);
         } else {
             x[r] = 0.0;
             u[r] = 0.0;
@@ -157,12 +181,14 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     double s_prev = 1.0, s_cur = 1.0;  // S_{lc-1}, S_{lc} (S_{l0-1} := 1 only seeds the scan)
     for (int lc = l0; lc <= lmax; lc += 64) {
         const int l = lc + lane;
-        double A = 1.0, B = 0.0, C = 1.0;
+        double A = 1.0, B = 0.0, Bn = 0.0, C = 1.0;  // B, Bn: alpha_l - beta_l, alpha_l + beta_l
         double2 wp = make_double2(0.0, 0.0), wm = make_double2(0.0, 0.0);
+        double2 wpn = make_double2(0.0, 0.0), wmn = make_double2(0.0, 0.0);  // R- weights
         if (l <= lmax) {
             if (l == 0) {
                 A = 1.0;
-                B = 0.0;
+                B = 1.0;
+                Bn = 1.0;
                 C = 0.0;
             } else {
                 // alpha_l, beta_l, gamma_l from the root table: q = r(m, l) r(k, l) with
@@ -173,7 +199,8 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
                 const double rq = tm.y * tk.y;
                 const double inv = 1.0 / (L * L1);
                 A = (2.0 * L + 1.0) * L1 * rq;
-                B = A * mk * inv;
+                B = A * ((L * L1 - mk) * inv);   // alpha - beta, the integer difference exact
+                Bn = A * ((L * L1 + mk) * inv);  // alpha + beta
                 C = L1 * L1 * inv * (pm.x * pk.x) * rq;
             }
             double2 a = alm[aoff + l];
@@ -182,7 +209,10 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
             if (k == 0) bb.y = 0.0;
             wp = cmul(a, cconj(bb));
             const double s = ((l + k + m) & 1) ? -1.0 : 1.0;
-            wm = cscale(cmul(cconj(a), cconj(bb)), s);
+            const double2 cacb = cmul(cconj(a), cconj(bb));
+            wm = cscale(cacb, s);
+            wpn = cscale(cacb, (m & 1) ? -1.0 : 1.0);          // (-1)^m conj(a) conj(b)
+            wmn = cscale(wp, ((l + k) & 1) ? -1.0 : 1.0);      // (-1)^{l+k} a conj(b)
         }
         if (l == l0) C = 1.0;  // S_{l0+1} := 1 (gamma_{l0} = 0)
         // T = S_{l+1} = gamma_l S_{l-1}: inclusive product over the lanes of this
@@ -201,13 +231,18 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         const double ratio = Sl / T;
         __syncthreads();  // previous chunk's coefficients are consumed
         cA[lane] = A * ratio;
-        cB[lane] = B * ratio;
-        cWp[lane] = cscale(wp, Sl);
-        cWm[lane] = cscale(wm, Sl);
+        cB[2 * lane] = B * ratio;
+        cB[2 * lane + 1] = Bn * ratio;
+        cWp[2 * lane] = cscale(wp, Sl);
+        cWp[2 * lane + 1] = cscale(wpn, Sl);
+        cWm[2 * lane] = cscale(wm, Sl);
+        cWm[2 * lane + 1] = cscale(wmn, Sl);
         __syncthreads();
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
+        const double *cBt = cB + tp;
+        const double2 *cWpt = cWp + tp, *cWmt = cWm + tp;
         if (fast) {
-            rec_steps<RPT>(0, nl, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            rec_steps<RPT>(0, nl, cA, cBt, cWpt, cWmt, x, u, up, fp, fm);
             continue;
         }
         // Rescaling is checked once per 32 steps: one step grows |u| by at most
@@ -216,7 +251,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         // 2^{-600 + 352}) is dropped harmlessly with the scaled sums.
         for (int t0 = 0; t0 < nl; t0 += 32) {
             const int t1 = t0 + 32 < nl ? t0 + 32 : nl;
-            rec_steps<RPT>(t0, t1, cA, cB, cWp, cWm, x, u, up, fp, fm);
+            rec_steps<RPT>(t0, t1, cA, cBt, cWpt, cWmt, x, u, up, fp, fm);
             if (fast) continue;
             bool low = false;
 #pragma unroll
@@ -238,14 +273,20 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int j = (g * RPT + r) * 64 + lane;
+        const int j = (g * RPT + r) * 32 + sub;
+        const int js = nring - 1 - j;  // the reflected (southern) ring
         if (e[r] != 0) {  // never in range: the true sums are below 2^-600
             fp[r] = make_double2(0.0, 0.0);
             fm[r] = make_double2(0.0, 0.0);
         }
-        if (j < nring) {
-            F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
-            if (m > 0) F[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)] = fm[r];
+        if (j < nh) {
+            if (tp == 0) {  // F_k(theta_j, m); F_k(pi - theta_j, -m) (for m = 0: -m = m, skip the equator)
+                F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
+                if (m > 0 || js != j) F[((size_t)k * nm + (lmax - m)) * nring + js] = fm[r];
+            } else if (m > 0 && js != j) {  // F_k(theta_j, -m); F_k(pi - theta_j, m)
+                F[((size_t)k * nm + (lmax - m)) * nring + j] = fp[r];
+                F[((size_t)k * nm + (m + lmax)) * nring + js] = fm[r];
+            }
         }
     }
 }
@@ -272,11 +313,17 @@ hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm)
 }
 
 // Rings per lane: the fewest wasted lane slots with at most 4 rings per lane
-// (more rings per lane spill registers).
+// (more rings per lane spill registers).  A wave covers 32 RPT northern rings with
+// each of the two recursions.
+int sc_ring_groups(int nring, int rpt) {
+    const int nh = (nring + 1) / 2;
+    return (nh + 32 * rpt - 1) / (32 * rpt);
+}
+
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups) {
-    int best_r = 1, best_g = (nring + 63) / 64, best_w = 1 << 30;
+    int best_r = 1, best_g = sc_ring_groups(nring, 1), best_w = 1 << 30;
     for (int r = 4; r >= 1; --r) {
-        const int g = (nring + 64 * r - 1) / (64 * r);
+        const int g = sc_ring_groups(nring, r);
         const int waste = g * 64 * r - nring;
         if (waste < best_w) {
             best_w = waste;

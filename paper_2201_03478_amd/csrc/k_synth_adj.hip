@@ -10,14 +10,25 @@
 //     Q-(l) = sum_j d^l_mk(theta_j) F_adj_k(pi - theta_j, -m),
 //     g_lm  = sum_k [ Q+ b_lk + (-1)^{l+k+m} conj(Q- b_lk) ]      (m > 0),
 //     g_l0  = sum_k Re(Q+ b_lk)                                  (m = 0).
-// The d values come from the same recursion and start values as the forward
-// kernel.  The sums over rings are reductions across lanes for every l: each
+// The d values come from the same recursions and start values as the forward
+// kernel, on northern rings only: lanes 0-31 run the column (m, k) (R+) for the
+// rings theta_j <= pi/2, lanes 32-63 the column (-m, k) (R-) on the same rings,
+// which by d^l_mk(pi - theta) = (-1)^{l+k} d^l_{-m,k}(theta) gives the southern
+// rings.  R- runs on (-1)^l d^l_{-m,k}, whose recursion has the coefficient
+// -((alpha + beta) - alpha y) and the same gamma, so that its products with the
+// ring-sum gradients (times (-1)^k, folded into them at load) add to the same
+// per-l sums as R+'s:
+//     Q+(l) = sum_{j north} [d^l_mk(theta_j) F_adj(theta_j, m) + (-1)^k dt F_adj(pi - theta_j, m)],
+//     Q-(l) = sum_{j north} [d^l_mk(theta_j) F_adj(pi - theta_j, -m) + (-1)^k dt F_adj(theta_j, -m)],
+// dt = (-1)^l d^l_{-m,k}(theta_j).  The sums over rings are reductions across lanes for every l: each
 // lane adds its rings' products, writes the 4 real partials of each l to a
 // padded LDS buffer, and every 8 l the buffer is reduced by reading it
 // transposed (two lanes per (l, value) row).  One wave per ring group; the
 // waves of a workgroup are the groups of one (k, m) and are combined in LDS.
 // Per-k contributions go to GA[k][alm index]; a second kernel sums over k in a
-// fixed order (deterministic).
+// fixed order (deterministic).  Columns with more than 2048 rings are split into
+// slabs of rings, one workgroup each, whose partial sums go to separate copies of
+// GA and are added by the same fixed-order reduction (no atomics).
 //
 // The same Q+- give the gradient with respect to the beam (BEAM = true): the
 // TOD is bilinear, and with the sky gradient above L = Re sum conj(g_lm) a_lm
@@ -40,18 +51,22 @@ template <int RPT, bool BEAM>
 __global__ void __launch_bounds__(1024)
 k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ coefs, double2 *__restrict__ GA,
                     const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
-                    const double *__restrict__ rtab, int lmax, int kmax, int nring, int alm_lmax) {
+                    const double *__restrict__ rtab, int lmax, int kmax, int nring, int alm_lmax, int nslab,
+                    int per) {
     // coefs: the beam b_lk (sky gradient into GA[k]) or, with BEAM, the sky a_lm
     // in the alm_lmax layout (beam gradient into GA[m], blm layout)
     extern __shared__ __attribute__((aligned(16))) double adj_smem[];
     const int nw = blockDim.x >> 6;
-    double *cA = adj_smem, *cB = cA + 64, *cC = cB + 64;                   // [64]
-    double *Qw = cC + 64;                                                  // [nw][64][4]
+    double *cA = adj_smem, *cB = cA + 128, *cC = cB + 128;  // [64][2] per recursion, [64]
+    double *Qw = cC + 64;                                    // [nw][64][4]
     double *PB = Qw + nw * 64 * 4;                                          // [nw][4][FLUSH][ROW]
-    const int b = blockIdx.x;
+    const int slab = blockIdx.x % nslab;  // rings [slab per, slab per + per)
+    const int b = blockIdx.x / nslab;
     const int k = b % (kmax + 1);
     const int m = b / (kmax + 1);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tp = lane >> 5, sub = lane & 31;  // recursion R+ (0) or R- (1); northern ring slot
+    const int nh = (nring + 1) / 2;
     const int l0 = m > k ? m : k;
     const int mn = m < k ? m : k;
     const int nm = 2 * lmax + 1;
@@ -60,7 +75,8 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     const size_t nblm = (size_t)(kmax + 1) * (2 * lmax + 2 - kmax) / 2;
     // output column: (l, m) of GA[k] for the sky gradient, (l, k) of GA[m] for the beam
-    double2 *gk = BEAM ? GA + (size_t)m * nblm + boff : GA + (size_t)k * nalm + aoff;
+    double2 *gk = BEAM ? GA + ((size_t)slab * (lmax + 1) + m) * nblm + boff
+                       : GA + ((size_t)slab * (kmax + 1) + k) * nalm + aoff;
     // orders below l0 have no d^l_mk: their contribution is zero
     for (int l = (BEAM ? k : m) + tid; l < l0 && l <= lmax; l += blockDim.x) gk[l] = make_double2(0.0, 0.0);
     if (l0 > lmax) return;
@@ -70,16 +86,24 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     double2 fap[RPT], fam[RPT];
     const XN pref = {sbin_m[l0 * (kmax + 1) + mn], sbin_e[l0 * (kmax + 1) + mn]};
     const double pfe = (double)pref.e, pfm = log2(pref.m);  // log2 of the start prefactor
+    const double sk = (k & 1) ? -1.0 : 1.0;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int j = (w * RPT + r) * 64 + lane;
+        const int jl = (w * RPT + r) * 32 + sub;  // northern ring within the slab
+        const int j = slab * per + jl, js = nring - 1 - j;
         dp[r] = 0.0;
         fap[r] = make_double2(0.0, 0.0);
         fam[r] = make_double2(0.0, 0.0);
-        if (j < nring) {
-            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], d[r], e[r]);
-            fap[r] = FA[((size_t)k * nm + (m + lmax)) * nring + j];
-            if (m > 0) fam[r] = FA[((size_t)k * nm + (lmax - m)) * nring + (nring - 1 - j)];
+        if (jl < per && j < nh && (tp == 0 || js != j)) {  // R- skips the equator ring of an odd count
+            start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], d[r], e[r], tp == 1);
+            if (tp == 0) {
+                fap[r] = FA[((size_t)k * nm + (m + lmax)) * nring + j];
+                if (m > 0) fam[r] = FA[((size_t)k * nm + (lmax - m)) * nring + js];
+            } else {
+                if (l0 & 1) d[r] = -d[r];  // (-1)^l d^l_{-m,k} at l = l0
+                fap[r] = cscale(FA[((size_t)k * nm + (m + lmax)) * nring + js], sk);
+                if (m > 0) fam[r] = cscale(FA[((size_t)k * nm + (lmax - m)) * nring + j], sk);
+            }
         } else {
             x[r] = 0.0;
             d[r] = 0.0;
@@ -92,10 +116,13 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     for (int lc = l0; lc <= lmax; lc += 64) {
         __syncthreads();  // previous chunk's coefficients and Qw are consumed
         if (tid < 64 && lc + tid <= lmax) {
-            double A, B, C;
-            rec_coefs(lc + tid, mm, kk, mk, A, B, C);
-            cA[tid] = A;
-            cB[tid] = B;
+            double A, B, C, Bn, Cn;
+            rec_coefs(lc + tid, mm, kk, mk, A, B, C);      // B = alpha - beta
+            rec_coefs(lc + tid, mm, kk, -mk, A, Bn, Cn);   // Bn = alpha + beta (the column (-m, k))
+            cA[2 * tid] = -A;  // R+: (alpha - beta) - alpha y
+            cB[2 * tid] = B;
+            cA[2 * tid + 1] = A;  // R- on (-1)^l d: -((alpha + beta) - alpha y)
+            cB[2 * tid + 1] = -Bn;
             cC[tid] = C;
         }
         __syncthreads();
@@ -103,7 +130,7 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
         for (int t0 = 0; t0 < nl; t0 += ADJ_FLUSH) {
             const int t1 = t0 + ADJ_FLUSH < nl ? t0 + ADJ_FLUSH : nl;
             for (int t = t0; t < t1; ++t) {
-                const double A = cA[t], B = cB[t], C = cC[t];
+                const double A = cA[2 * t + tp], B = cB[2 * t + tp], C = cC[t];
                 double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
@@ -112,7 +139,7 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
                     p1 = fma(dd, fap[r].y, p1);
                     p2 = fma(dd, fam[r].x, p2);
                     p3 = fma(dd, fam[r].y, p3);
-                    const double dn = fma(fma(A, x[r], -B), d[r], -C * dp[r]);
+                    const double dn = fma(fma(A, x[r], B), d[r], -C * dp[r]);  // x: 1 - cos theta
                     dp[r] = d[r];
                     d[r] = dn;
                 }
@@ -182,14 +209,15 @@ k_ring_sums_adjoint(const double2 *__restrict__ FA, const double2 *__restrict__ 
     }
 }
 
-// grad[i] = sum_m GB[m][i] in increasing m over the blm layout; the k = 0
-// column (entries i <= lmax) is real.
-__global__ void k_reduce_over_m(const double2 *__restrict__ GB, double2 *__restrict__ grad, int64_t nblm, int lmax) {
+// grad[i] = sum over slabs and m of GB[slab][m][i], in that fixed order, over the blm
+// layout; the k = 0 column (entries i <= lmax) is real.
+__global__ void k_reduce_over_m(const double2 *__restrict__ GB, double2 *__restrict__ grad, int64_t nblm, int lmax,
+                                int nslab) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nblm) return;
     double2 s = make_double2(0.0, 0.0);
-    for (int m = 0; m <= lmax; ++m) {
-        const double2 v = GB[(size_t)m * nblm + i];
+    for (int q = 0; q < nslab * (lmax + 1); ++q) {
+        const double2 v = GB[(size_t)q * nblm + i];
         s.x += v.x;
         s.y += v.y;
     }
@@ -197,14 +225,15 @@ __global__ void k_reduce_over_m(const double2 *__restrict__ GB, double2 *__restr
     grad[i] = s;
 }
 
-// grad[i] = sum_k GA[k][i] in increasing k (entries with k > l are zero).
+// grad[i] = sum over slabs and k of GA[slab][k][i] in that fixed order (entries with
+// k > l are zero).
 __global__ void k_reduce_over_k(const double2 *__restrict__ GA, double2 *__restrict__ grad, int64_t nalm,
-                                int kmax) {
+                                int kmax, int nslab) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nalm) return;
     double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k <= kmax; ++k) {
-        const double2 v = GA[(size_t)k * nalm + i];
+    for (int q = 0; q < nslab * (kmax + 1); ++q) {
+        const double2 v = GA[(size_t)q * nalm + i];
         s.x += v.x;
         s.y += v.y;
     }
@@ -215,18 +244,22 @@ __global__ void k_reduce_over_k(const double2 *__restrict__ GA, double2 *__restr
 
 // LDS bytes of an adjoint workgroup with nw waves.
 static size_t adj_lds_bytes(int nw) {
-    return sizeof(double) * (3 * 64 + (size_t)nw * 64 * 4 + (size_t)nw * 4 * ADJ_FLUSH * ADJ_ROW);
+    return sizeof(double) * (5 * 64 + (size_t)nw * 64 * 4 + (size_t)nw * 4 * ADJ_FLUSH * ADJ_ROW);
 }
 
-// Waves per (k, m) workgroup and rings per lane for the adjoint: the fewest idle
-// ring slots among layouts whose LDS fits one CU (at most 8 waves; 4 rings per
-// lane then cover nring <= 2048, i.e. transforms up to 8192 points).
-static void adj_layout(int nring, int *rpt, int *nw) {
-    int best_r = 4, best_w = (nring + 255) / 256, best_waste = 1 << 30;
+// Ring slabs per (k, m) column, northern rings per slab, waves per workgroup and
+// rings per lane for the adjoint: a workgroup holds at most 1024 northern rings
+// (8 waves, 32 rings per recursion and 4 per lane; its LDS fits one CU), so longer
+// columns are split into equal slabs; per slab, the fewest idle ring slots.
+static void adj_layout(int nring, int *rpt, int *nw, int *nslab, int *per) {
+    const int nh = (nring + 1) / 2;
+    const int ns = (nh + 1023) / 1024;
+    const int pr = (nh + ns - 1) / ns;
+    int best_r = 4, best_w = (pr + 127) / 128, best_waste = 1 << 30;
     for (int r = 4; r >= 1; --r) {
-        const int waves = (nring + 64 * r - 1) / (64 * r);
-        if (adj_lds_bytes(waves) > 160 * 1024) continue;
-        const int waste = waves * 64 * r - nring;
+        const int waves = (pr + 32 * r - 1) / (32 * r);
+        if (waves > 8 || adj_lds_bytes(waves) > 160 * 1024) continue;
+        const int waste = waves * 32 * r - pr;
         if (waste < best_waste) {
             best_waste = waste;
             best_r = r;
@@ -235,7 +268,11 @@ static void adj_layout(int nring, int *rpt, int *nw) {
     }
     *rpt = best_r;
     *nw = best_w;
+    *nslab = ns;
+    *per = pr;
 }
+
+int sc_adjoint_slabs(const sc_plan *p) { return ((p->nring + 1) / 2 + 1023) / 1024; }
 
 #define SC_ADJ_CASE(R)                                                                                       \
     case R: {                                                                                                \
@@ -243,13 +280,13 @@ static void adj_layout(int nring, int *rpt, int *nw) {
         e = sc_set_lds_attr((const void *)kern, lds);                                                        \
         if (e != hipSuccess) return e;                                                                       \
         hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, p->stream, p->F, (const double2 *)coefs,    \
-                           out, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring, p->alm_lmax);     \
+                           out, p->sbin_m, p->sbin_e, p->rtab, p->lmax, p->kmax, p->nring, p->alm_lmax, nslab, per); \
     } break;
 
 static hipError_t ring_sums_adjoint(sc_plan *p, const double *coefs, double2 *out, bool beam) {
-    int rpt, nw;
-    adj_layout(p->nring, &rpt, &nw);
-    const int nblk = (p->lmax + 1) * (p->kmax + 1);
+    int rpt, nw, nslab, per;
+    adj_layout(p->nring, &rpt, &nw, &nslab, &per);
+    const int nblk = (p->lmax + 1) * (p->kmax + 1) * nslab;
     const size_t lds = adj_lds_bytes(nw);
     hipError_t e = hipSuccess;
     switch (rpt) {
@@ -267,7 +304,7 @@ hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *gr
     if (e != hipSuccess) return e;
     const int64_t nalm = (int64_t)(p->lmax + 1) * (p->lmax + 2) / 2;
     hipLaunchKernelGGL(k_reduce_over_k, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, p->stream, p->GA,
-                       (double2 *)grad, nalm, p->kmax);
+                       (double2 *)grad, nalm, p->kmax, sc_adjoint_slabs(p));
     return hipGetLastError();
 }
 
@@ -276,6 +313,6 @@ hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, doubl
     if (e != hipSuccess) return e;
     const int64_t nblm = (int64_t)(p->kmax + 1) * (2 * p->lmax + 2 - p->kmax) / 2;
     hipLaunchKernelGGL(k_reduce_over_m, dim3((unsigned)((nblm + 255) / 256)), dim3(256), 0, p->stream, p->GB,
-                       (double2 *)grad, nblm, p->lmax);
+                       (double2 *)grad, nblm, p->lmax, sc_adjoint_slabs(p));
     return hipGetLastError();
 }

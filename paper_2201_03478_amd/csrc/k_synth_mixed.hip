@@ -106,7 +106,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
             const double s = ((l + k + m) & 1) ? -1.0 : 1.0;
             const double2 wm = m > 0 ? cscale(cmul(cconj(a), cconj(bb)), s) : make_double2(0.0, 0.0);
             cA[lane] = (float)A;
-            cB[lane] = (float)(A - B);  // alpha - beta in FP64
+            cB[lane] = (float)B;  // alpha - beta, formed in FP64 by rec_coefs
             cC[lane] = (float)C;
             cW[lane][0] = (float)wp.x;
             cW[lane][1] = (float)wp.y;

@@ -156,9 +156,10 @@ __global__ void k_sqrt_binom(double *sm, int *se, int lmax, int kmax) {
 
 hipError_t sc_launch_tables(sc_plan *p) {
     const int bs = 256;
-    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->n2 + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2, p->p2);
-    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->n2os + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2os, p->p2os);
-    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->nphi + bs - 1) / bs), dim3(bs), 0, p->stream, p->twphi, p->pphi);
+    // (sub-)transform lengths: the full lengths unless a transform is split
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->p2.n + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2, p->p2);
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->p2os.n + bs - 1) / bs), dim3(bs), 0, p->stream, p->tw2os, p->p2os);
+    hipLaunchKernelGGL(k_pass_twiddles, dim3((p->pphi.n + bs - 1) / bs), dim3(bs), 0, p->stream, p->twphi, p->pphi);
     hipLaunchKernelGGL(k_gauss_legendre, dim3((p->nq + 63) / 64), dim3(64), 0, p->stream, p->glx, p->glw, p->nq);
     const int nt = 2 * p->lmax + 1;
     hipLaunchKernelGGL(k_deconv, dim3((nt + 63) / 64), dim3(64), 0, p->stream, p->phase, p->dphi, p->lmax, p->n2,

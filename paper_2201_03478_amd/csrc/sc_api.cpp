@@ -115,6 +115,17 @@ bool factor_fft(int n, FftPlan *P) {
     return true;
 }
 
+// A transform of length n as P sub-transforms of length n / P that fit one workgroup
+// (smallest such P <= 16; P = 1 when the whole transform fits).
+bool split_fft(int n, int *P, FftPlan *Q) {
+    for (int q = 1; q <= 16; ++q)
+        if (n % q == 0 && n / q <= 1024 * 9 && factor_fft(n / q, Q)) {
+            *P = q;
+            return true;
+        }
+    return false;
+}
+
 // Record the start event of a timed launch; returns the slot or -1.
 int timing_begin(sc_plan *p, int stage) {
     if (!p->timing) return -1;
@@ -214,7 +225,7 @@ void free_plan_buffers(sc_plan *p) {
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
     void *bufs[] = {p->F, p->G, p->maps, p->rroot, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
-                    p->phase, p->dphi, p->glx, p->glw};
+                    p->phase, p->dphi, p->glx, p->glw, p->S};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -344,6 +355,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     if (!out) return fail(SC_EINVAL, "plan output pointer is NULL");
     *out = nullptr;
     if (lmax < 0) return fail(SC_EINVAL, "lmax = %d < 0", lmax);
+    if (lmax > SC_LMAX_MAX) return fail(SC_EINVAL, "lmax = %d above the supported %d", lmax, SC_LMAX_MAX);
     if (kmax < 0 || kmax > lmax) return fail(SC_EINVAL, "kmax = %d outside [0, lmax = %d]", kmax, lmax);
     if (kmax > 127) return fail(SC_EINVAL, "kmax = %d above the supported 127", kmax);
     if (precision != SC_FP64 && precision != SC_F64MAPS_F32GATHER && precision != SC_MIXED)
@@ -394,10 +406,13 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     }
     sc_choose_ring_layout(p->nring, &p->rpt, &p->ngroups);
     sc_choose_ring_layout_mixed(p->nring, &p->rpt_mx, &p->ngroups_mx);
-    if (!factor_fft(p->n2, &p->p2) || !factor_fft(p->n2os, &p->p2os) || !factor_fft(p->nphi, &p->pphi)) {
+    if (!split_fft(p->n2, &p->sp2, &p->p2) || !split_fft(p->n2os, &p->spos, &p->p2os) ||
+        !split_fft(p->nphi, &p->spphi, &p->pphi)) {
         delete p;
-        return fail(SC_EINVAL, "lmax = %d needs transforms longer than 9216 points (not supported)", lmax);
+        return fail(SC_EINVAL, "lmax = %d: no transform plan for lengths %d, %d, %d", lmax, p->n2, p->n2os, p->nphi);
     }
+    p->big = p->sp2 > 1 || p->spos > 1 || p->spphi > 1;
+    p->spad = (2 * lmax + 1 + 63) & ~63;
 
     const size_t nm = 2 * (size_t)lmax + 1;
     size_t tot = 0;
@@ -409,9 +424,10 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     rc = rc ? rc : alloc((void **)&p->sbin_m, sizeof(double) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_e, sizeof(int) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->rtab, sizeof(double) * 5 * p->nring, &tot);
-    rc = rc ? rc : alloc((void **)&p->tw2, sizeof(double2) * p->n2, &tot);
-    rc = rc ? rc : alloc((void **)&p->tw2os, sizeof(double2) * p->n2os, &tot);
-    rc = rc ? rc : alloc((void **)&p->twphi, sizeof(double2) * p->nphi, &tot);
+    rc = rc ? rc : alloc((void **)&p->tw2, sizeof(double2) * p->p2.n, &tot);
+    rc = rc ? rc : alloc((void **)&p->tw2os, sizeof(double2) * p->p2os.n, &tot);
+    rc = rc ? rc : alloc((void **)&p->twphi, sizeof(double2) * p->pphi.n, &tot);
+    if (p->big) rc = rc ? rc : alloc((void **)&p->S, sizeof(double2) * (kmax + 1) * nm * (size_t)p->spad, &tot);
     rc = rc ? rc : alloc((void **)&p->phase, sizeof(double2) * nm, &tot);
     rc = rc ? rc : alloc((void **)&p->dphi, sizeof(double) * (lmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->glx, sizeof(double) * p->nq, &tot);
@@ -426,13 +442,16 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, p->stream);
     if (e == hipSuccess) e = sc_launch_tables(p);
     if (e == hipSuccess) {
-        // ring table in extended host precision: theta_j = (j + 1/2) pi / nring
+        // ring table in extended host precision: theta_j = (j + 1/2) pi / nring;
+        // 1 - cos(theta_j) as 2 sin^2(theta_j / 2), which keeps its full relative
+        // precision next to the poles
         std::vector<double> rt(5 * (size_t)p->nring);
         const long double pi = 3.141592653589793238462643383279502884L;
         for (int j = 0; j < p->nring; ++j) {
             const long double th = ((long double)j + 0.5L) * pi / (long double)p->nring;
             const long double lc = log2l(cosl(0.5L * th)), ls = log2l(sinl(0.5L * th));
-            rt[5 * j] = (double)cosl(th);
+            const long double sh = sinl(0.5L * th);
+            rt[5 * j] = (double)(2.0L * sh * sh);
             rt[5 * j + 1] = (double)lc;
             rt[5 * j + 2] = (double)(lc - (long double)(double)lc);
             rt[5 * j + 3] = (double)ls;
@@ -764,7 +783,7 @@ static int adjoint_to_rings(sc_plan *p, const double *ptg, const void *tod_grad,
     if (!p->gmaps) {
         size_t tot = 0;
         int rc = alloc(&p->gmaps, map_bytes, &tot);
-        if (!rc) rc = alloc((void **)&p->GA, sizeof(double2) * (p->kmax + 1) * nalm, &tot);
+        if (!rc) rc = alloc((void **)&p->GA, sizeof(double2) * (p->kmax + 1) * nalm * sc_adjoint_slabs(p), &tot);
         if (rc) {
             if (p->gmaps) (void)hipFree(p->gmaps);
             p->gmaps = nullptr;
@@ -813,9 +832,6 @@ static int check_adjoint_args(sc_plan *p, const double *coefs, const double *ptg
                               double *grad) {
     if (!p) return fail(SC_EINVAL, "plan is NULL");
     if (n < 0) return fail(SC_EINVAL, "n = %lld < 0", (long long)n);
-    if (p->nring > 2048)  // the adjoint recursion's workgroup holds a column's rings: 8 waves x 4 per lane
-        return fail(SC_EINVAL, "adjoint: lmax = %d has %d rings, above the 2048 the adjoint supports (lmax <= 2047)",
-                    p->lmax, p->nring);
     if (!is_device_ptr(coefs)) return fail(SC_EINVAL, "coefficients are not device memory");
     if (!is_device_ptr(grad)) return fail(SC_EINVAL, "gradient output is not device memory");
     if (n > 0 && (!is_device_ptr(ptg) || !is_device_ptr(tod_grad)))
@@ -848,7 +864,7 @@ int sc_convolve_adjoint_beam(sc_plan *p, const double *alm, const double *ptg, c
     if (!p->GB) {
         const size_t nblm = (size_t)(p->kmax + 1) * (2 * p->lmax + 2 - p->kmax) / 2;
         size_t tot = 0;
-        rc = alloc((void **)&p->GB, sizeof(double2) * (size_t)(p->lmax + 1) * nblm, &tot);
+        rc = alloc((void **)&p->GB, sizeof(double2) * (size_t)(p->lmax + 1) * nblm * sc_adjoint_slabs(p), &tot);
         if (rc) return rc;
         p->adj_bytes += tot;
         p->ws_bytes += tot;
@@ -884,13 +900,12 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
         case SC_PARAM_RING_RPT: {
             const int vmax = p->prec == SC_MIXED ? 8 : 4;
             if (v < 1 || v > vmax) return fail(SC_EINVAL, "rings per lane %lld outside [1, %d]", (long long)v, vmax);
-            const int g = (p->nring + 64 * (int)v - 1) / (64 * (int)v);
             if (p->prec == SC_MIXED) {
                 p->rpt_mx = (int)v;
-                p->ngroups_mx = g;
+                p->ngroups_mx = (p->nring + 64 * (int)v - 1) / (64 * (int)v);
             } else {
                 p->rpt = (int)v;
-                p->ngroups = g;
+                p->ngroups = sc_ring_groups(p->nring, (int)v);
             }
             return SC_OK;
         }

@@ -102,7 +102,14 @@ struct sc_plan {
     hipEvent_t ev_fork, ev_join;  // (created on first use)
     hipEvent_t ev_stream;         // orders a new stream after the old one (sc_plan_set_stream)
 
+    // Transform plans.  A transform longer than one workgroup's LDS (9216 points) runs as
+    // sp* sub-transforms of length n / sp* (k_fft_big.hip); the plans and twiddle tables
+    // below are those of the (sub-)transform length, n2, n2os and nphi the full lengths.
     FftPlan p2, p2os, pphi;
+    int sp2, spos, spphi;
+    int big;           // some transform is split: the k_fft_big.hip stages run
+    double2 *S;        // big plans: theta spectra, [kmax+1][2 lmax+1][spad]
+    int spad;          // padded row length of S (>= 2 lmax + 1)
 
     // device buffers
     double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums
@@ -111,7 +118,7 @@ struct sc_plan {
     double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
     double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
     int *sbin_e;       // [lmax+1][kmax+1] binary exponent
-    double *rtab;      // [nring][5] cos(theta_j); log2 cos(theta_j / 2), log2 sin(theta_j / 2) as (hi, lo) pairs
+    double *rtab;      // [nring][5] 1 - cos(theta_j); log2 cos(theta_j / 2), log2 sin(theta_j / 2) as (hi, lo) pairs
     double2 *tw2, *tw2os, *twphi;  // e^{-2 pi i t / N}
     double2 *phase;    // [2 lmax+1] e^{-i n pi / n2} / (n2 hhat_theta(n))
     double *dphi;      // [lmax+1] 1 / hhat_phi(m)
@@ -166,13 +173,19 @@ hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *
 int sc_psi_max_len();
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
+int sc_ring_groups(int nring, int rpt);  // ring groups of the FP64 ring-sum kernel
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm);
 void sc_choose_ring_layout_mixed(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_theta_upsample(sc_plan *p);
+hipError_t sc_launch_theta_upsample_big(sc_plan *p);
+hipError_t sc_launch_phi_synthesis_big(sc_plan *p);
+hipError_t sc_launch_phi_adjoint_big(sc_plan *p, const void *gmaps);
+hipError_t sc_launch_theta_adjoint_big(sc_plan *p);
 hipError_t sc_launch_phi_synthesis(sc_plan *p);
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps);
 hipError_t sc_launch_theta_adjoint(sc_plan *p);
 hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *grad);
+int sc_adjoint_slabs(const sc_plan *p);  // ring slabs per column of the adjoint recursion
 hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, double *grad);
 hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps);
 hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps);

@@ -35,18 +35,22 @@ __device__ __forceinline__ double rec_down(double v) { return ldexp(v, -REC_STEP
 // mantissa), log2 c and log2 s given per ring as double-double pairs (rt[1..4]),
 // every product and sum carried with its rounding error (|log2 d| reaches 10^4
 // at lmax 1800), then one exp2 of the fractional part: relative error ~1e-15.
-// rt[0] = cos(theta_j).
+// rt[0] = y = 1 - cos(theta_j) (returned in y).
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;
     const double bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
+// With neg, the start value of the column (-m, k) instead (m, k >= 0):
+//   d^l_{-l,k} = sqrt(C(2l, l-k)) c^{l-k} s^{l+k}   (m >= k),
+//   d^l_{-m,l} = sqrt(C(2l, l-m)) c^{l-m} s^{l+m}   (m <  k),
+// the same binomial with the exponents of c and s exchanged and no sign.
 __device__ __forceinline__ void start_value(const double *__restrict__ rt, int m, int k, double pe, double pm,
-                                            double &x, double &d, int &e) {
+                                            double &y, double &d, int &e, bool neg = false) {
     const int l0 = m > k ? m : k, mn = m < k ? m : k;
-    const double sgn = (m >= k && ((m - k) & 1)) ? -1.0 : 1.0;
-    x = rt[0];
-    const double P = (double)(l0 + mn), Q = (double)(l0 - mn);
+    const double sgn = (!neg && m >= k && ((m - k) & 1)) ? -1.0 : 1.0;
+    y = rt[0];
+    const double P = (double)(neg ? l0 - mn : l0 + mn), Q = (double)(neg ? l0 + mn : l0 - mn);
     const double p1 = P * rt[1], q1 = Q * rt[3];
     const double p1e = fma(P, rt[1], -p1) + P * rt[2];
     const double q1e = fma(Q, rt[3], -q1) + Q * rt[4];
@@ -64,18 +68,23 @@ __device__ __forceinline__ void start_value(const double *__restrict__ rt, int m
 }
 
 // Recursion coefficients for the step l -> l+1:
-//   d^{l+1} = (A cos(theta) - B) d^l - C d^{l-1}.
-__device__ __forceinline__ void rec_coefs(int l, double mm, double kk, double mk, double &A, double &B, double &C) {
+//   d^{l+1} = (A cos(theta) - B) d^l - C d^{l-1} = ((A - B) - A y) d^l - C d^{l-1},
+// y = 1 - cos(theta).  The second form is the one evaluated: y keeps its full relative
+// precision next to the poles, where cos(theta) rounded to FP64 would move the
+// effective angle by up to 1e-16 / theta and the values at l by ~l^2 1e-16.
+// A - B = A (l(l+1) - m k) / (l(l+1)) with the integer difference exact in FP64.
+__device__ __forceinline__ void rec_coefs(int l, double mm, double kk, double mk, double &A, double &AmB,
+                                          double &C) {
     if (l == 0) {
         A = 1.0;
-        B = 0.0;
+        AmB = 1.0;
         C = 0.0;
         return;
     }
     const double L = l, L1 = l + 1.0;
     const double q = sqrt((L1 * L1 - mm) * (L1 * L1 - kk));
     A = (2.0 * L + 1.0) * L1 / q;
-    B = A * mk / (L * L1);
+    AmB = A * ((L * L1 - mk) / (L * L1));
     C = L1 / L * sqrt((L * L - mm) * (L * L - kk)) / q;
 }
 

@@ -43,7 +43,7 @@ def test_plan_create_rejects_bad_arguments_without_device(lib):
     from paper_2201_03478_amd import _native as N
     p = ctypes.c_void_p()
     cases = [(-1, 0, 0, 0), (10, -1, 0, 0), (10, 11, 0, 0), (10, 2, 7, 0), (10, 2, 3, 0), (10, 2, 0, 5), (10, 2, 0, 18),
-             (10, 2, 0, 3), (5000, 2, 0, 0), (2304, 2, 0, 0), (2500, 100, 1, 0)]
+             (10, 2, 0, 3), (8193, 2, 0, 0), (20000, 2, 0, 0), (500, 128, 1, 0)]
     for lmax, kmax, prec, w in cases:
         rc = lib.sc_plan_create(ctypes.byref(p), lmax, kmax, prec, w, None)
         assert rc == N.SC_EINVAL, (lmax, kmax, prec, w)

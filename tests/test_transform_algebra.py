@@ -210,3 +210,75 @@ def test_psi_interpolation_reproduces_series(W, tol):
         got = np.dot(w, ext[nodes + half - 1])
         ref = np.sum(A[0] * np.cos(k * psi) + B[0] * np.sin(k * psi))
         assert abs(got - ref) <= tol * scale, psi
+
+
+# ---------------------------------------------------------------------------
+# Split transforms (band limits whose transforms exceed one workgroup's LDS): a
+# length n = P N transform as P length-N transforms of folded, twiddled inputs,
+#   X[P k + s] = sum_j w_N^{j k} y_s[j],  y_s[j] = w_n^{j s} sum_q x[j + N q] w_P^{q s},
+# for both signs of the exponent; and the single-column theta stage built from them
+# against the column-by-column reference above, with its adjoint.
+
+def _split_dft(x, P, sign):
+    n = x.size
+    N = n // P
+    out = np.empty(n, complex)
+    j = np.arange(N)
+    for s in range(P):
+        fold = sum(x[j + N * q] * np.exp(sign * 2j * np.pi * q * s / P) for q in range(P))
+        y = fold * np.exp(sign * 2j * np.pi * j * s / n)
+        out[s::P] = np.fft.fft(y) if sign < 0 else np.fft.ifft(y) * N
+    return out
+
+
+@pytest.mark.parametrize("n,P", [(12, 2), (30, 3), (40, 4), (90, 5), (72, 8), (17280, 2), (34560, 4)])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_split_transform_identity(n, P, sign):
+    x = np.random.default_rng(n + P).standard_normal(n) + 1j * np.random.default_rng(n - P).standard_normal(n)
+    ref = np.fft.fft(x) if sign < 0 else np.fft.ifft(x) * n
+    assert np.max(np.abs(_split_dft(x, P, sign) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _single_split(S, Fc, m, k, P1, P2):
+    """The single-column theta stage of the split kernels: split forward transform of the
+    extended column, d p(n) on |n| <= lmax, split inverse of the zero-padded spectrum."""
+    n2, nos, n, lmax = S["n2"], S["nos"], S["n"], S["lmax"]
+    nring = n2 // 2
+    s = -1.0 if (m - k) & 1 else 1.0
+    x = np.concatenate([Fc, s * Fc[::-1]])
+    X = _split_dft(x, P1, -1)
+    Z = np.zeros(nos, complex)
+    Z[n % nos] = X[n % n2] * S["phase"] * S["dphi"][abs(m)]
+    O = _split_dft(Z, P2, 1)
+    rows = np.arange(S["rows"]) + S["r0"]
+    return O[rows % nos]
+
+
+def _single_split_adjoint(S, Gc, m, k, P1, P2):
+    n2, nos, n = S["n2"], S["nos"], S["n"]
+    nring = n2 // 2
+    s = -1.0 if (m - k) & 1 else 1.0
+    A = np.zeros(nos, complex)
+    rows = np.arange(S["rows"]) + S["r0"]
+    np.add.at(A, rows % nos, Gc)
+    Y = _split_dft(A, P2, -1)
+    Xa = np.zeros(n2, complex)
+    Xa[n % n2] = Y[n % nos] * np.conj(S["phase"]) * S["dphi"][abs(m)]
+    xa = _split_dft(Xa, P1, 1)
+    return xa[:nring] + s * xa[n2 - 1 - np.arange(nring)]
+
+
+@pytest.mark.parametrize("m,k", [(3, 1), (-4, 2), (0, 0), (20, 5)])
+def test_split_single_column_matches_reference_and_adjoint(m, k):
+    S = _setup(lmax=20, n2=44, nos=88, W=8, seed=7)
+    rng = S["rng"]
+    Fc = rng.standard_normal(22) + 1j * rng.standard_normal(22)
+    ref = _single(S, Fc, m, k)
+    for P1, P2 in ((1, 1), (2, 2), (4, 4), (2, 8)):
+        got = _single_split(S, Fc, m, k, P1, P2)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        # <G, T F> = <T^* G, F> with <u, v> = Re sum conj(u) v
+        Gc = rng.standard_normal(S["rows"]) + 1j * rng.standard_normal(S["rows"])
+        lhs = np.real(np.vdot(Gc, got))
+        rhs = np.real(np.vdot(_single_split_adjoint(S, Gc, m, k, P1, P2), Fc))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)

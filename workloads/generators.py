@@ -6,8 +6,9 @@ Secs. 2.2 and 3) are not available, so these seeded stand-ins take their shapes:
 
 * sky a_lm: a_00 = 0 and, for l >= 1, Gaussian with C_l = 1/(l(l+1)); a_l0 real.
 * beam b_lk, 0 <= k <= min(l, kmax): a complex Gaussian (unit variance, real at
-  k = 0) times either a Gaussian-beam window exp(-l(l+1) sigma^2 / 2) or the
-  sidelobe-like envelope (1+k)^-1.5 exp(-l/200).
+  k = 0) times either a Gaussian-beam window exp(-l(l+1) sigma^2 / 2), the
+  sidelobe-like envelope (1+k)^-1.5 exp(-l/200), or (1+k)^-1.5 alone (flat in l,
+  to exercise every multipole of a high band limit).
 * pointings: uniform on the sphere with uniform psi, or a synthetic scan: the
   boresight sweeps a circle of 85 deg opening angle around a spin axis in the
   ecliptic plane at 1 rpm, sampled at 32.5 Hz, with the spin axis advancing
@@ -87,6 +88,8 @@ def beam_alm(lmax: int, kmax: int, seed: int, kind: str = "sidelobe",
         env = np.exp(-l * (l + 1.0) * sigma * sigma / 2.0)
     elif kind == "sidelobe":
         env = (1.0 + k) ** -1.5 * np.exp(-l / 200.0)
+    elif kind == "flat":  # no decay in l: every multipole up to lmax carries weight
+        env = (1.0 + k) ** -1.5 + 0.0 * l
     else:
         raise ValueError(kind)
     return (g * env).astype(np.complex128)
