@@ -86,10 +86,11 @@ enum sc_precision {
     /* FP64 recursion and transforms; maps stored in FP32; FP32 interpolation
        and k-sum (pointing reduction and psi reduction stay FP64); float32 TOD. */
     SC_F64MAPS_F32GATHER = 1,
-    /* Precision variant: FP64 start values, FP32 Wigner-d recursion, ring
-       contraction on the matrix cores (FP32 products and accumulation); FP64
-       transforms; FP32 maps, interpolation and k-sum; float32 TOD.  Its error
-       grows with lmax (~1e-6 relative at lmax 1024). */
+    /* Precision variant: the FP64 Wigner-d recursion of SC_F64MAPS_F32GATHER,
+       with the ring contraction on the matrix cores (d values and coefficient
+       products rounded to FP32, FP32 products, FP32 accumulation over 64
+       steps, then FP64 sums); FP64 transforms; FP32 maps, interpolation and
+       k-sum; float32 TOD. */
     SC_MIXED = 2
 };
 
@@ -307,7 +308,7 @@ int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage
  * package; defaults work everywhere).
  *   SC_PARAM_BIN_CHUNK          samples per gather/scatter work item, 16 .. 2^20 (default 256)
  *   SC_PARAM_GATHER_WGS_PER_CU  persistent gather/scatter workgroups per CU, 0 = as many as fit
- *   SC_PARAM_RING_RPT           rings per lane of the ring-sum kernel, 1..4 (1..8 for SC_MIXED)
+ *   SC_PARAM_RING_RPT           northern rings per lane and recursion of the ring-sum kernel, 1..4
  *   SC_PARAM_SKY_LMAX           band limit of the layout of the alm array given to
  *                               sc_set_sky_beam (>= lmax; a shared sky may have a larger one)
  *   SC_PARAM_GATHER_WAVES       waves per workgroup of the SC_MMA_FP32 gather, 4 or 8 (default 4);

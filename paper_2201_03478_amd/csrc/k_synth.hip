@@ -56,30 +56,37 @@
 // its mirror, covers every ring.  Rings past the equator are never recursed, so
 // the rounding of cos(theta) next to the south pole cannot move the angle.
 //
+// R- runs on v^l = (-1)^l u^l_{-m,k}, for which
+//   v^{l+1} = (a_l y - bn_l) v^l - v^{l-1},  bn_l = (alpha_l + beta_l) S_l / S_{l+1},
+// and its two weights are those of R+ up to the sign (-1)^{l+k} and an exchange:
+// (-1)^m conj(a) conj(b) = (-1)^{l+k} wm and (-1)^{l+k} a conj(b) = (-1)^{l+k} wp.
+// So every lane forms q = fma(a_l, y', b'_l) with y' = -y, b' = b_l (R+) or
+// y' = y, b' = -bn_l (R-), and accumulates wp v and wm v with the same weights;
+// R- lanes read their sums in exchanged order, times (-1)^k.
+//
 // Layout: one 64-lane wave per (m, k, ring group); lanes 0-31 run R+ and lanes
 // 32-63 run R- on the same northern rings, RPT rings per lane.  Recursion
 // coefficients and weights for 64 consecutive l are built cooperatively in LDS
 // (one l per lane, the square roots of alpha_l and gamma_l from a per-plan table of
-// sqrt((l+1)^2 - x^2); S_l by a product scan over the lanes of each parity) for
-// both recursions; a step reads alpha_l as a broadcast and the rest from the
-// lane's half (two addresses per read, one instruction as before).
+// sqrt((l+1)^2 - x^2); S_l by a product scan over the lanes of each parity); a
+// step reads a_l, wp and wm as broadcasts and b' from the lane's half.
 #include "wigner_rec.h"
 
 namespace {
 
 using namespace wrec;
 
-// Coefficients and weights of one step (l -> l+1) for the lane's recursion (R+ or
-// R-, tp = 0 or 1), read from LDS: a = a_l, b = a_l -+ b_l.
+// Coefficients and weights of one step (l -> l+1), read from LDS: a = a_l, b = b'
+// of the lane's recursion (R+ or R-, tp = 0 or 1), wp and wm.
 struct RecCoef {
     double a, b;
     double2 wp, wm;
 };
 
-__device__ __forceinline__ RecCoef rec_load(int t, const double *cA, const double *cB, const double2 *cWp,
+__device__ __forceinline__ RecCoef rec_load(int t, const double *cA, const double *cBt, const double2 *cWp,
                                             const double2 *cWm) {
-    // cB, cWp, cWm already point at the lane's half: entry (t, tp) at 2 t + tp
-    return RecCoef{cA[t], cB[2 * t], cWp[2 * t], cWm[2 * t]};
+    // cBt points at the lane's half of cB ([tp][64])
+    return RecCoef{cA[t], cBt[t], cWp[t], cWm[t]};
 }
 
 // One recursion step for every ring of the lane: contract u^l (true value
@@ -93,7 +100,7 @@ __device__ __forceinline__ void rec_step(const RecCoef &c, const double *x, doub
         fp[r].y = fma(c.wp.y, u[r], fp[r].y);
         fm[r].x = fma(c.wm.x, u[r], fm[r].x);
         fm[r].y = fma(c.wm.y, u[r], fm[r].y);
-        const double un = fma(fma(-c.a, x[r], c.b), u[r], -up[r]);  // x holds y = 1 - cos(theta)
+        const double un = fma(fma(c.a, x[r], c.b), u[r], -up[r]);  // x holds y' = -+(1 - cos(theta))
         up[r] = u[r];
         u[r] = un;
     }
@@ -105,36 +112,37 @@ __device__ __forceinline__ void rec_step(const RecCoef &c, const double *x, doub
 // count per iteration returns u / u_prev to the same registers, so neither the
 // loads nor the recursion need register moves.
 template <int RPT>
-__device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, const double *cB, const double2 *cWp,
+__device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, const double *cBt, const double2 *cWp,
                                           const double2 *cWm, const double *x, double *u, double *up, double2 *fp,
                                           double2 *fm) {
     const int te = t0 + ((t1 - t0) & ~3);
     if (te > t0) {
-        RecCoef a0 = rec_load(t0, cA, cB, cWp, cWm), a1 = rec_load(t0 + 1, cA, cB, cWp, cWm);
+        RecCoef a0 = rec_load(t0, cA, cBt, cWp, cWm), a1 = rec_load(t0 + 1, cA, cBt, cWp, cWm);
         for (int t = t0; t < te; t += 4) {
-            const RecCoef b0 = rec_load(t + 2, cA, cB, cWp, cWm), b1 = rec_load(t + 3, cA, cB, cWp, cWm);
+            const RecCoef b0 = rec_load(t + 2, cA, cBt, cWp, cWm), b1 = rec_load(t + 3, cA, cBt, cWp, cWm);
             __builtin_amdgcn_sched_barrier(0);
             rec_step<RPT>(a0, x, u, up, fp, fm);
             rec_step<RPT>(a1, x, u, up, fp, fm);
             const int tn = t + 4 < te ? t + 4 : t;  // last iteration: harmless re-read
-            a0 = rec_load(tn, cA, cB, cWp, cWm);
-            a1 = rec_load(tn + 1, cA, cB, cWp, cWm);
+            a0 = rec_load(tn, cA, cBt, cWp, cWm);
+            a1 = rec_load(tn + 1, cA, cBt, cWp, cWm);
             __builtin_amdgcn_sched_barrier(0);
             rec_step<RPT>(b0, x, u, up, fp, fm);
             rec_step<RPT>(b1, x, u, up, fp, fm);
         }
     }
-    for (int t = te; t < t1; ++t) rec_step<RPT>(rec_load(t, cA, cB, cWp, cWm), x, u, up, fp, fm);
+    for (int t = te; t < t1; ++t) rec_step<RPT>(rec_load(t, cA, cBt, cWp, cWm), x, u, up, fp, fm);
 }
 
+// Up to 3 rings per lane the kernel fits 168 registers: three waves per SIMD.
 template <int RPT>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RPT <= 3 ? 3 : 2)))
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
             const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
-    __shared__ double cA[64], cB[64 * 2];
-    __shared__ double2 cWp[64 * 2], cWm[64 * 2];
+    __shared__ double cA[64], cB[2 * 64];
+    __shared__ double2 cWp[64], cWm[64];
 
     int b = blockIdx.x;
     const int g = b % ngroups;
@@ -166,6 +174,10 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         up[r] = 0.0;
         if (on) {
             start_value(rtab + 5 * j, m, k, pfe, pfm, x[r], u[r], e[r], tp == 1);
+            if (tp == 0)
+                x[r] = -x[r];  // y' = -y
+            else if (l0 & 1)
+                u[r] = -u[r];  // v^{l0} = (-1)^{l0} u^{l0}_{-m,k}
         } else {
             x[r] = 0.0;
             u[r] = 0.0;
@@ -175,74 +187,24 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
     }
     bool fast = !__any(scaled);
 
-    const double mk = (double)m * k;
     const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     double s_prev = 1.0, s_cur = 1.0;  // S_{lc-1}, S_{lc} (S_{l0-1} := 1 only seeds the scan)
     for (int lc = l0; lc <= lmax; lc += 64) {
-        const int l = lc + lane;
-        double A = 1.0, B = 0.0, Bn = 0.0, C = 1.0;  // B, Bn: alpha_l - beta_l, alpha_l + beta_l
-        double2 wp = make_double2(0.0, 0.0), wm = make_double2(0.0, 0.0);
-        double2 wpn = make_double2(0.0, 0.0), wmn = make_double2(0.0, 0.0);  // R- weights
-        if (l <= lmax) {
-            if (l == 0) {
-                A = 1.0;
-                B = 1.0;
-                Bn = 1.0;
-                C = 0.0;
-            } else {
-                // alpha_l, beta_l, gamma_l from the root table: q = r(m, l) r(k, l) with
-                // r(x, l) = sqrt((l+1)^2 - x^2), and sqrt((l^2-m^2)(l^2-k^2)) = r(m, l-1) r(k, l-1)
-                const double2 tm = rroot[(size_t)m * (lmax + 1) + l], tk = rroot[(size_t)k * (lmax + 1) + l];
-                const double2 pm = rroot[(size_t)m * (lmax + 1) + l - 1], pk = rroot[(size_t)k * (lmax + 1) + l - 1];
-                const double L = (double)l, L1 = L + 1.0;
-                const double rq = tm.y * tk.y;
-                const double inv = 1.0 / (L * L1);
-                A = (2.0 * L + 1.0) * L1 * rq;
-                B = A * ((L * L1 - mk) * inv);   // alpha - beta, the integer difference exact
-                Bn = A * ((L * L1 + mk) * inv);  // alpha + beta
-                C = L1 * L1 * inv * (pm.x * pk.x) * rq;
-            }
-            double2 a = alm[aoff + l];
-            double2 bb = blm[boff + l];
-            if (m == 0) a.y = 0.0;
-            if (k == 0) bb.y = 0.0;
-            wp = cmul(a, cconj(bb));
-            const double s = ((l + k + m) & 1) ? -1.0 : 1.0;
-            const double2 cacb = cmul(cconj(a), cconj(bb));
-            wm = cscale(cacb, s);
-            wpn = cscale(cacb, (m & 1) ? -1.0 : 1.0);          // (-1)^m conj(a) conj(b)
-            wmn = cscale(wp, ((l + k) & 1) ? -1.0 : 1.0);      // (-1)^{l+k} a conj(b)
-        }
-        if (l == l0) C = 1.0;  // S_{l0+1} := 1 (gamma_{l0} = 0)
-        // T = S_{l+1} = gamma_l S_{l-1}: inclusive product over the lanes of this
-        // lane's parity, times the carried S_{lc-1} (even lanes) or S_{lc} (odd).
-        double T = C;
-#pragma unroll
-        for (int off = 2; off < 64; off <<= 1) {
-            const double v = __shfl_up(T, off);
-            if (lane >= off) T *= v;
-        }
-        T *= (lane & 1) ? s_cur : s_prev;
-        double Sl = __shfl_up(T, 1);  // S_l
-        if (lane == 0) Sl = s_cur;
-        s_prev = __shfl(T, 62);  // S_{lc+63} and S_{lc+64} for the next chunk
-        s_cur = __shfl(T, 63);
-        const double ratio = Sl / T;
+        const ChunkCoef cc = chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
         __syncthreads();  // previous chunk's coefficients are consumed
-        cA[lane] = A * ratio;
-        cB[2 * lane] = B * ratio;
-        cB[2 * lane + 1] = Bn * ratio;
-        cWp[2 * lane] = cscale(wp, Sl);
-        cWp[2 * lane + 1] = cscale(wpn, Sl);
-        cWm[2 * lane] = cscale(wm, Sl);
-        cWm[2 * lane + 1] = cscale(wmn, Sl);
+        cA[lane] = cc.a;
+        cB[lane] = cc.b;
+        cB[64 + lane] = -cc.bn;
+        chunk_weights(lc + lane, lmax, m, k, alm, blm, aoff, boff, cc.sl, [&](int which, double2 v) {
+            if (which == 0) cWp[lane] = v;
+            if (which == 1) cWm[lane] = v;  // the R- weights are these, exchanged and signed
+        });
         __syncthreads();
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
-        const double *cBt = cB + tp;
-        const double2 *cWpt = cWp + tp, *cWmt = cWm + tp;
+        const double *cBt = cB + 64 * tp;
         if (fast) {
-            rec_steps<RPT>(0, nl, cA, cBt, cWpt, cWmt, x, u, up, fp, fm);
+            rec_steps<RPT>(0, nl, cA, cBt, cWp, cWm, x, u, up, fp, fm);
             continue;
         }
         // Rescaling is checked once per 32 steps: one step grows |u| by at most
@@ -251,7 +213,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         // 2^{-600 + 352}) is dropped harmlessly with the scaled sums.
         for (int t0 = 0; t0 < nl; t0 += 32) {
             const int t1 = t0 + 32 < nl ? t0 + 32 : nl;
-            rec_steps<RPT>(t0, t1, cA, cBt, cWpt, cWmt, x, u, up, fp, fm);
+            rec_steps<RPT>(t0, t1, cA, cBt, cWp, cWm, x, u, up, fp, fm);
             if (fast) continue;
             bool low = false;
 #pragma unroll
@@ -283,9 +245,10 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
             if (tp == 0) {  // F_k(theta_j, m); F_k(pi - theta_j, -m) (for m = 0: -m = m, skip the equator)
                 F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
                 if (m > 0 || js != j) F[((size_t)k * nm + (lmax - m)) * nring + js] = fm[r];
-            } else if (m > 0 && js != j) {  // F_k(theta_j, -m); F_k(pi - theta_j, m)
-                F[((size_t)k * nm + (lmax - m)) * nring + j] = fp[r];
-                F[((size_t)k * nm + (m + lmax)) * nring + js] = fm[r];
+            } else if (m > 0 && js != j) {  // F_k(theta_j, -m) = (-1)^k sum wm v; F_k(pi - theta_j, m) = (-1)^k sum wp v
+                const double sk = (k & 1) ? -1.0 : 1.0;
+                F[((size_t)k * nm + (lmax - m)) * nring + j] = cscale(fm[r], sk);
+                F[((size_t)k * nm + (m + lmax)) * nring + js] = cscale(fp[r], sk);
             }
         }
     }
@@ -320,14 +283,28 @@ int sc_ring_groups(int nring, int rpt) {
     return (nh + 32 * rpt - 1) / (32 * rpt);
 }
 
+//
+// Measured cost per ring slot (lmax 512, kmax 100) falls with the rings per lane
+// (more independent recursions per wave hide the FMA latency) up to 3, where the
+// kernel still runs three waves per SIMD: relative costs 1.65, 1.14, 1.0, 0.97 for
+// 1 .. 4.  The layout minimises slots x cost.
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups) {
-    int best_r = 1, best_g = sc_ring_groups(nring, 1), best_w = 1 << 30;
-    for (int r = 4; r >= 1; --r) {
+    static const double cost[5] = {0.0, 1.65, 1.14, 1.0, 0.97};
+    int best_r = 3, best_g = sc_ring_groups(nring, 3);
+    double best = 1e300;
+    for (int r = 3; r >= 1; --r) {  // 3 first: ties keep the larger count
         const int g = sc_ring_groups(nring, r);
-        const int waste = g * 64 * r - nring;
-        if (waste < best_w) {
-            best_w = waste;
+        const double c = (double)g * 64 * r * cost[r];
+        if (c < best) {
+            best = c;
             best_r = r;
+            best_g = g;
+        }
+    }
+    {
+        const int g = sc_ring_groups(nring, 4);
+        if ((double)g * 64 * 4 * cost[4] < best) {
+            best_r = 4;
             best_g = g;
         }
     }

@@ -898,11 +898,10 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
             p->gather_mma = (int)v;
             return SC_OK;
         case SC_PARAM_RING_RPT: {
-            const int vmax = p->prec == SC_MIXED ? 8 : 4;
-            if (v < 1 || v > vmax) return fail(SC_EINVAL, "rings per lane %lld outside [1, %d]", (long long)v, vmax);
+            if (v < 1 || v > 4) return fail(SC_EINVAL, "rings per lane %lld outside [1, 4]", (long long)v);
             if (p->prec == SC_MIXED) {
                 p->rpt_mx = (int)v;
-                p->ngroups_mx = (p->nring + 64 * (int)v - 1) / (64 * (int)v);
+                p->ngroups_mx = sc_ring_groups(p->nring, (int)v);
             } else {
                 p->rpt = (int)v;
                 p->ngroups = sc_ring_groups(p->nring, (int)v);

@@ -88,4 +88,83 @@ __device__ __forceinline__ void rec_coefs(int l, double mm, double kk, double mk
     C = L1 / L * sqrt((L * L - mm) * (L * L - kk)) / q;
 }
 
+// Step l = lc + lane of a chunk of 64 steps of the normalised recursions on
+// u^l = d^l / S_l (S_{l0} = S_{l0+1} = 1, S_{l+1} = gamma_l S_{l-1}):
+//   u^{l+1} = (b - a y) u^l - u^{l-1},  a = alpha_l S_l / S_{l+1},
+// b = (alpha_l - beta_l) S_l / S_{l+1} for the column (m, k) (R+) and
+// bn = (alpha_l + beta_l) S_l / S_{l+1} for the column (-m, k) (R-).  alpha, beta
+// and gamma come from the plan's root table sqrt((l+1)^2 - x^2) and its
+// reciprocal; S_l from a product scan over the lanes of each parity, carried
+// across chunks in s_prev = S_{lc-1}, s_cur = S_{lc}.  Called by all 64 lanes.
+struct ChunkCoef {
+    double a, b, bn, sl;  // sl = S_l, the factor of the contraction weights
+};
+
+__device__ __forceinline__ ChunkCoef chunk_coefs(int lc, int lane, int l0, int lmax, int m, int k,
+                                                 const double2 *__restrict__ rroot, double &s_prev, double &s_cur) {
+    const int l = lc + lane;
+    const double mk = (double)m * k;
+    double A = 1.0, B = 0.0, Bn = 0.0, C = 1.0;
+    if (l <= lmax) {
+        if (l == 0) {
+            B = 1.0;
+            Bn = 1.0;
+            C = 0.0;
+        } else {
+            // q = r(m, l) r(k, l) with r(x, l) = sqrt((l+1)^2 - x^2), and
+            // sqrt((l^2-m^2)(l^2-k^2)) = r(m, l-1) r(k, l-1)
+            const double2 tm = rroot[(size_t)m * (lmax + 1) + l], tk = rroot[(size_t)k * (lmax + 1) + l];
+            const double2 pm = rroot[(size_t)m * (lmax + 1) + l - 1], pk = rroot[(size_t)k * (lmax + 1) + l - 1];
+            const double L = (double)l, L1 = L + 1.0;
+            const double rq = tm.y * tk.y;
+            const double inv = 1.0 / (L * L1);
+            A = (2.0 * L + 1.0) * L1 * rq;
+            B = A * ((L * L1 - mk) * inv);   // alpha - beta, the integer difference exact
+            Bn = A * ((L * L1 + mk) * inv);  // alpha + beta
+            C = L1 * L1 * inv * (pm.x * pk.x) * rq;
+        }
+    }
+    if (l == l0) C = 1.0;  // S_{l0+1} := 1 (gamma_{l0} = 0)
+    // T = S_{l+1} = gamma_l S_{l-1}: inclusive product over the lanes of this
+    // lane's parity, times the carried S_{lc-1} (even lanes) or S_{lc} (odd).
+    double T = C;
+#pragma unroll
+    for (int off = 2; off < 64; off <<= 1) {
+        const double v = __shfl_up(T, off);
+        if (lane >= off) T *= v;
+    }
+    T *= (lane & 1) ? s_cur : s_prev;
+    double Sl = __shfl_up(T, 1);  // S_l
+    if (lane == 0) Sl = s_cur;
+    s_prev = __shfl(T, 62);  // S_{lc+63} and S_{lc+64} for the next chunk
+    s_cur = __shfl(T, 63);
+    const double ratio = Sl / T;
+    return ChunkCoef{A * ratio, B * ratio, Bn * ratio, Sl};
+}
+
+// Contraction weights of step l (zero past lmax), each times S_l:
+//   R+: wp = a_lm conj(b_lk)                    -> F_k(theta_j, m)
+//       wm = (-1)^{l+k+m} conj(a_lm) conj(b_lk) -> F_k(pi - theta_j, -m)
+//   R-: wpn = (-1)^m conj(a_lm) conj(b_lk)      -> F_k(theta_j, -m)
+//       wmn = (-1)^{l+k} a_lm conj(b_lk)        -> F_k(pi - theta_j, m)
+// (Im a_l0 and Im b_l0 are ignored.)  `put(which, value)` receives them in that order.
+template <typename Put>
+__device__ __forceinline__ void chunk_weights(int l, int lmax, int m, int k, const double2 *__restrict__ alm,
+                                              const double2 *__restrict__ blm, size_t aoff, size_t boff, double sl,
+                                              Put put) {
+    double2 a = make_double2(0.0, 0.0), bb = a;
+    if (l <= lmax) {
+        a = alm[aoff + l];
+        bb = blm[boff + l];
+        if (m == 0) a.y = 0.0;
+        if (k == 0) bb.y = 0.0;
+    }
+    const double2 wp = cscale(cmul(a, cconj(bb)), sl);
+    put(0, wp);
+    const double2 cacb = cscale(cmul(cconj(a), cconj(bb)), sl);
+    put(1, cscale(cacb, ((l + k + m) & 1) ? -1.0 : 1.0));
+    put(2, cscale(cacb, (m & 1) ? -1.0 : 1.0));
+    put(3, cscale(wp, ((l + k) & 1) ? -1.0 : 1.0));
+}
+
 }  // namespace wrec

@@ -1,15 +1,15 @@
-"""lmax 1024 support and the mixed-precision (precision variant) path.
+"""lmax 1024 support and the mixed-precision form (the precision variant).
 
-* FP64 ring sums at lmax 1024 next to the poles (extended-exponent start values
-  down to ~1e-2900) against the oracle.
-* Mixed precision: FP32 recursion + matrix-core contraction.  Rounding the
-  recursion coefficients to FP32 perturbs each step by ~6e-8 and the error of
-  d^l grows about linearly with l.  Measured on MI355X (max error / column
-  maximum of the ring sums): 3e-7 at lmax 16, 2.7e-6 at 64, 4e-6 at 200,
-  1.8e-5 next to the poles at 1024; TOD rel-L2 1.6e-6 on the lmax 1024
-  workload.  The bars (1e-5, 1e-4, 5e-6) bound these with margin.
+* FP64 ring sums at lmax 1024 and 1300 next to the poles (extended-exponent start
+  values down to ~1e-2900) against the oracle.
+* Mixed precision: the FP64 recursion with the ring contraction on the matrix
+  cores (d values and coefficient products rounded to FP32, FP32 products and
+  accumulation over 64 steps, then FP64 sums).  Each FP32 rounding is at most
+  2^-24 relative; a 64-term FP32 partial sum can lose up to 64 2^-24 = 3.8e-6 of
+  the sum of its magnitudes, so the ring sums are held to 4e-6 of the ring's
+  largest value, and the TOD to the form's 1e-6 target.
 * The precision workload (lmax 1024, kmax 16, 1e8 scan samples) in both the
-  mixed and the FP64-recursion forms, sampled outputs against the oracle.
+  mixed and the FP64-recursion forms, against 200 stored oracle samples.
 """
 import math
 
@@ -37,7 +37,7 @@ def _rel(x, ref):
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 4e-6)])
 def test_ring_sums_start_below_range_then_emerge(env, oracle_lib, prec, tol):
     """lmax 1300: at rings near 22 and 158 degrees the start values of m ~ 430-460
     lie below 2^-600 (e < 0) and the columns grow to ~1e-5 by lmax, so every
@@ -62,7 +62,7 @@ def test_ring_sums_start_below_range_then_emerge(env, oracle_lib, prec, tol):
         assert err <= tol, js[q]
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 4e-6)])
 def test_ring_sums_lmax1024_near_poles(env, oracle_lib, prec, tol):
     torch, api, dev = env
     L, K = 1024, 16
@@ -93,13 +93,10 @@ def test_mixed_ring_sums_small(env, oracle_lib, L, K):
     ref = np.transpose(oracle_lib.ring_sums(a, b, L, K, (np.arange(nr) + 0.5) * math.pi / nr), (0, 2, 1))
     err = np.max(np.abs(F - ref)) / np.max(np.abs(ref))
     print("mixed ring sums L=%d K=%d: %.3e" % (L, K, err))
-    assert err <= 1e-5
+    assert err <= 4e-6
 
 
-@pytest.mark.parametrize("prec", [
-    pytest.param("mixed", marks=pytest.mark.xfail(reason="the FP32 recursion's drift reaches ~1.7e-6 rel-L2 at "
-                                                        "lmax 1024, above the 1e-6 target", strict=False)),
-    "f64maps_f32gather"])
+@pytest.mark.parametrize("prec", ["mixed", "f64maps_f32gather"])
 def test_precision_workload_against_stored_oracle(env, prec):
     """lmax 1024, kmax 16, 1e8 scan samples: 200 stored oracle samples (eight edge
     pointings among them), rel-L2 <= 1e-6 and max|d|/max|c| <= 1e-5."""
