@@ -536,8 +536,22 @@ def extra_batched(torch, api, W, dev, no_oracle):
     chosen = autotune.tune_batch(bt, sky, reps=2)
     eager = _event_ms(torch, lambda: bt.run(sky, use_graph=False), 3)
     graph = _event_ms(torch, lambda: bt.run(sky, use_graph=True), 3)
+    # per-stage kernel time of one eager pass, summed over the detectors (the synthesis
+    # chains overlap, so the sum can exceed the pass's wall time)
+    views = [bt.plan(d) for d in range(len(dets))]
+    for v in views:
+        v.enable_timing(True)
+    bt.run(sky, use_graph=False)
+    torch.cuda.synchronize()
+    stage_ms = {}
+    for v in views:
+        for name, (ms, cnt) in v.stage_times().items():
+            if cnt:
+                stage_ms[name] = stage_ms.get(name, 0.0) + ms
+        v.enable_timing(False)
     out = {"workload": "batched-12det-scan4e7", "n_samples": ntot, "ms_per_step_graph": graph,
            "value": ntot / (graph * 1e-3), "ms_per_step_eager": eager, "ms_per_step_eager_untuned": eager_default,
+           "synthesis_chains": 4, "stage_kernel_ms_sum": {k: round(v, 3) for k, v in stage_ms.items()},
            "tuned": [dict(det=i, lmax=d["lmax"], kmax=d["kmax"], **c) for i, (d, c) in enumerate(zip(bt.dets, chosen))]}
     bt.close()
     return out

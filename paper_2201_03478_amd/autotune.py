@@ -20,7 +20,7 @@ import torch
 
 from . import _native as N
 
-RING_RPT = {N.SC_FP64: (1, 2, 3, 4), N.SC_F64MAPS_F32GATHER: (1, 2, 3, 4), N.SC_MIXED: (1, 2, 3, 4, 6, 8)}
+RING_RPT = {N.SC_FP64: (1, 2, 3, 4), N.SC_F64MAPS_F32GATHER: (1, 2, 3, 4), N.SC_MIXED: (1, 2, 3, 4)}
 BIN_CHUNK = (128, 256, 512, 1024)
 WGS_PER_CU = (0, 1)
 GATHER_WAVES = (4, 8)

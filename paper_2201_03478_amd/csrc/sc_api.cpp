@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -1015,7 +1016,15 @@ struct sc_batch {
     const double *graph_alm;
     hipStream_t cap_stream;  // private stream for capture (the legacy null stream cannot be captured)
     hipEvent_t ev_stream;    // orders a new stream after the old one (sc_batch_set_stream)
+    // Map synthesis and binning of the detectors run as SC_BATCH_CHAINS independent
+    // chains: chain 0 on the batch's stream, the others on side streams forked from
+    // it and joined before the gather; detectors are assigned by estimated work.
+    hipStream_t side[3];
+    hipEvent_t ev_fork, ev_join[3];
+    std::vector<int> chain;  // chain of each detector
 };
+
+#define SC_BATCH_CHAINS 4
 
 namespace {
 
@@ -1027,23 +1036,61 @@ void batch_drop_graph(sc_batch *b) {
     b->graph_alm = nullptr;
 }
 
-// Enqueue one full batch pass on stream s (no host synchronisation, capture-safe).
-hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s) {
-    for (sc_plan *p : b->plans) p->stream = s;
-    hipError_t e = hipSuccess;
+// Enqueue one full batch pass on stream s (no host synchronisation, capture-safe):
+// fork the side chains from s, run each detector's map synthesis and binning on its
+// chain, join, then the one gather launch over all detectors on s.  With `timed`
+// (eager runs only, never under capture) and a plan's timing enabled, its launches
+// are timed on its chain.
+hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s, bool timed) {
+    auto tb = [timed](sc_plan *p, int stage) { return timed ? timing_begin(p, stage) : -1; };
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    for (int c = 0; c < SC_BATCH_CHAINS - 1 && e == hipSuccess; ++c) e = hipStreamWaitEvent(b->side[c], b->ev_fork, 0);
     for (int d = 0; d < b->ndet && e == hipSuccess; ++d) {
         sc_plan *p = b->plans[d];
         const sc_det_desc &D = b->dets[d];
+        p->stream = b->chain[d] == 0 ? s : b->side[b->chain[d] - 1];
+        int slot = tb(p, SC_STAGE_RING);
         e = p->prec == SC_MIXED ? sc_launch_ring_sums_mixed(p, alm, D.blm) : sc_launch_ring_sums(p, alm, D.blm);
-        if (e == hipSuccess) e = sc_launch_theta_upsample(p);
-        if (e == hipSuccess) e = sc_launch_phi_synthesis(p);
-        if (e == hipSuccess)
-            e = D.n > 0 ? sc_launch_binning(p, D.ptg, D.n) : sc_launch_zero(p->bw.totals, 4 * sizeof(int), s);
+        timing_end(p, slot);
+        if (e == hipSuccess) {
+            slot = tb(p, SC_STAGE_THETA);
+            e = sc_launch_theta_upsample(p);
+            timing_end(p, slot);
+        }
+        if (e == hipSuccess) {
+            slot = tb(p, SC_STAGE_PHI);
+            e = sc_launch_phi_synthesis(p);
+            timing_end(p, slot);
+        }
+        if (e == hipSuccess) {
+            slot = tb(p, SC_STAGE_BIN);
+            e = D.n > 0 ? sc_launch_binning(p, D.ptg, D.n) : sc_launch_zero(p->bw.totals, 4 * sizeof(int), p->stream);
+            timing_end(p, slot);
+        }
+    }
+    for (int c = 0; c < SC_BATCH_CHAINS - 1; ++c) {
+        // always join, so no side stream is left outside a capture
+        const hipError_t e1 = hipEventRecord(b->ev_join[c], b->side[c]);
+        const hipError_t e2 = hipStreamWaitEvent(s, b->ev_join[c], 0);
+        if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
     }
     if (e == hipSuccess) e = sc_launch_zero(b->cursor, sizeof(int), s);
-    if (e == hipSuccess) e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, b->waves, b->mma, s);
+    if (e == hipSuccess) {
+        sc_plan *p0 = b->plans[0];
+        p0->stream = s;
+        const int slot = tb(p0, SC_STAGE_GATHER);  // the batch's one gather, on detector 0's record
+        e = sc_launch_gather_batch(b->dets_dev, b->ndet, b->max_ct, b->cursor, b->wgs_per_cu, b->waves, b->mma, s);
+        timing_end(p0, slot);
+    }
     for (sc_plan *p : b->plans) p->stream = b->stream;
     return e;
+}
+
+// Estimated work of a detector (for the chain assignment): Wigner-d values of the
+// ring sums plus multiply-adds of the gather.
+double det_work(const sc_plan *p, int64_t n) {
+    const double L = p->lmax + 1.0, K = p->kmax + 1.0;
+    return K * L * L / 2.0 * p->nring * 6.0 + (double)n * (2.0 * p->kmax + 1.0) * p->W * p->W;
 }
 
 }  // namespace
@@ -1053,9 +1100,19 @@ extern "C" {
 int sc_batch_destroy(sc_batch *b) {
     if (!b) return SC_OK;
     hipError_t e = hipStreamSynchronize(b->stream);
+    for (int c = 0; c < SC_BATCH_CHAINS - 1; ++c)
+        if (b->side[c]) {
+            const hipError_t es = hipStreamSynchronize(b->side[c]);
+            if (e == hipSuccess) e = es;
+        }
     batch_drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->ev_stream) (void)hipEventDestroy(b->ev_stream);
+    for (int c = 0; c < SC_BATCH_CHAINS - 1; ++c) {
+        if (b->side[c]) (void)hipStreamDestroy(b->side[c]);
+        if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (sc_plan *p : b->plans) sc_plan_destroy(p);
     if (b->dets_dev) (void)hipFree(b->dets_dev);
     if (b->cursor) (void)hipFree(b->cursor);
@@ -1113,6 +1170,33 @@ int sc_batch_create(sc_batch **out, const sc_det_desc *dets, int ndet, int lmax_
     if (rc) {
         sc_batch_destroy(b);
         return rc;
+    }
+    {
+        // side streams (default priority) and events of the synthesis chains
+        hipError_t es = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        for (int c = 0; c < SC_BATCH_CHAINS - 1 && es == hipSuccess; ++c) {
+            es = hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking);
+            if (es == hipSuccess) es = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
+        }
+        if (es != hipSuccess) {
+            sc_batch_destroy(b);
+            return hip_fail(es, "batch side streams");
+        }
+        // longest-processing-time assignment of detectors to chains
+        std::vector<int> order(ndet);
+        for (int d = 0; d < ndet; ++d) order[d] = d;
+        std::vector<double> work(ndet);
+        for (int d = 0; d < ndet; ++d) work[d] = det_work(b->plans[d], dets[d].n);
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+        double load[SC_BATCH_CHAINS] = {};
+        b->chain.assign(ndet, 0);
+        for (int d : order) {
+            int best = 0;
+            for (int c = 1; c < SC_BATCH_CHAINS; ++c)
+                if (load[c] < load[best]) best = c;
+            b->chain[d] = best;
+            load[best] += work[d];
+        }
     }
     hipError_t e = hipMemcpyAsync(b->dets_dev, gd.data(), sizeof(GatherDet) * ndet, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1180,7 +1264,7 @@ int sc_batch_run(sc_batch *b, const double *alm_sky, int use_graph) {
     if (!is_device_ptr(alm_sky) || ((uintptr_t)alm_sky & 15)) return fail(SC_EINVAL, "alm_sky is not aligned device memory");
     hipError_t e = hipSuccess;
     if (!use_graph) {
-        e = batch_enqueue(b, alm_sky, b->stream);
+        e = batch_enqueue(b, alm_sky, b->stream, true);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
         return SC_OK;
     }
@@ -1192,7 +1276,7 @@ int sc_batch_run(sc_batch *b, const double *alm_sky, int use_graph) {
     if (!b->warmed) {
         // one eager pass first: kernel attributes and launch shapes get cached
         // outside the capture
-        e = batch_enqueue(b, alm_sky, b->stream);
+        e = batch_enqueue(b, alm_sky, b->stream, true);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
         b->warmed = 1;
     }
@@ -1206,7 +1290,7 @@ int sc_batch_run(sc_batch *b, const double *alm_sky, int use_graph) {
     }
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t e2 = batch_enqueue(b, alm_sky, b->cap_stream);
+    hipError_t e2 = batch_enqueue(b, alm_sky, b->cap_stream, false);
     e = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (e2 != hipSuccess) {
         batch_drop_graph(b);

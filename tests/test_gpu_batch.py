@@ -129,3 +129,30 @@ def test_batched_workload_full_size(env):
     for i, d in enumerate(b.dets):
         assert_parity(d["tod"][its[i]].double().cpu().numpy(), golden[i]["c"], 1e-6,
                       "detector %d (lmax %d kmax %d n %d)" % (i, d["lmax"], d["kmax"], d["ptg"].shape[0]))
+
+
+def test_batch_stage_timing_leaves_results(env):
+    """Stage timing on the detectors' plans (events on each synthesis chain) changes no
+    output; every detector records one launch of each synthesis stage, detector 0 the
+    batch's one gather."""
+    torch, api, dev = env
+    dets, sky = _small_batch(torch, dev)
+    b = api.Batch(dets, 80)
+    ref = [t.clone() for t in b.run(sky, use_graph=False)]
+    views = [b.plan(d) for d in range(len(SMALL))]
+    for v in views:
+        v.enable_timing(True)
+    out = [t.clone() for t in b.run(sky, use_graph=False)]
+    torch.cuda.synchronize()
+    for d, v in enumerate(views):
+        st = v.stage_times()
+        v.enable_timing(False)
+        for name in ("ring_sums", "theta_upsample", "phi_synthesis", "binning"):
+            assert st[name][1] == 1 and st[name][0] >= 0.0, (d, name, st[name])
+        assert st["gather"][1] == (1 if d == 0 else 0)
+    for x, y in zip(ref, out):
+        assert torch.equal(x, y)
+    graph = [t.clone() for t in b.run(sky, use_graph=True)]
+    torch.cuda.synchronize()
+    for x, y in zip(ref, graph):
+        assert torch.equal(x, y)
