@@ -64,14 +64,15 @@ def stage_model(info: dict, n: int, prec: int, mma: int = 1):
     nr, rows, cols, Wd = info["n_rings"], info["map_rows"], info["map_cols"], info["W"]
     nc = 2 * K + 1  # algorithmic component count (the stored zero sin 0 psi map is not counted)
     esz = 8 if prec == 0 else 4
+    csz = info["mid_bytes"]  # bytes per complex value of F and G (complex128 or complex64)
     dv = ring_dvalues(L, K, nr)
     return {
         # 2 FMA recursion (normalised three-term form) + 4 FMA contraction (both signs of m) per d value
         "ring_sums": ("alu", 12.0 * dv, "TFLOP/s", PEAK["fp64"]),
         # read F, write the upsampled spectra
-        "theta_upsample": ("hbm", 16.0 * (K + 1) * nm * (nr + rows), "GB/s", PEAK["hbm"]),
+        "theta_upsample": ("hbm", csz * (K + 1) * nm * (nr + rows), "GB/s", PEAK["hbm"]),
         # read the spectra, write the real components of the maps
-        "phi_synthesis": ("hbm", 16.0 * (K + 1) * rows * nm + esz * rows * cols * nc, "GB/s", PEAK["hbm"]),
+        "phi_synthesis": ("hbm", csz * (K + 1) * rows * nm + esz * rows * cols * nc, "GB/s", PEAK["hbm"]),
         # one FMA per (tap, component) per sample: FP64, FP32 or split matrix products
         "gather": (("mfma", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"]) if prec == 0 else
                    ("mfma", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["split"] if mma == 1 else PEAK["fp32"])),

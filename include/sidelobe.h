@@ -128,8 +128,10 @@ int sc_plan_set_stream(sc_plan *plan, void *stream);
  *   full-circle theta grid), 7 n_phi (oversampled phi grid), 8 map_rows,
  *   9 map_cols, 10 n_comp (2 kmax + 2: a cos k psi, sin k psi
  *   pair per k, the sin 0 psi slot zero), 11 n_comp_padded,
- *   12 workspace bytes.
- * Returns the number of values available (13).
+ *   12 workspace bytes, 13 bytes per complex value of the forward path's ring
+ *   sums and upsampled spectra (16; 8 in the FP32-map forms up to lmax 2303,
+ *   whose transforms fit one workgroup: computed in FP64, stored as complex64).
+ * Returns the number of values available (14).
  */
 int sc_plan_info(const sc_plan *plan, int64_t *out, int nout);
 

@@ -15,7 +15,7 @@ from . import _native as N
 
 PRECISIONS = {"fp64": N.SC_FP64, "f64maps_f32gather": N.SC_F64MAPS_F32GATHER, "mixed": N.SC_MIXED}
 INFO_KEYS = ("lmax", "kmax", "precision", "W", "n_rings", "n_fft_theta", "n_theta_fine", "n_phi",
-             "map_rows", "map_cols", "n_comp", "n_comp_padded", "workspace_bytes")
+             "map_rows", "map_cols", "n_comp", "n_comp_padded", "workspace_bytes", "mid_bytes")
 
 
 def n_alm(lmax: int, mmax: int | None = None) -> int:

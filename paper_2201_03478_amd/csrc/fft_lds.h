@@ -339,6 +339,77 @@ __device__ __forceinline__ void fft_passes_c(double2 *buf, const double2 *__rest
     if constexpr (sizeof...(Rest) > 0) fft_passes_c<DIR, NT, N, NS * R, Rest...>(buf, tw, tid);
 }
 
+// The same passes with the twiddles taken from LDS: per pass with a span NS > 1
+// only the base row w^k = e^{-2 pi i k / (R NS)}, k < NS (NS values), is stored,
+// and w^{r k} is formed by repeated multiplication (r < 16 products: a relative
+// error of a few 1e-16), so a transform needs no global loads once the bases of all
+// its passes are in LDS.
+template <int R, int DIR, int NT, int N, int NS>
+__device__ __forceinline__ void stockham_stage_l(double2 *buf, const double2 *twl, int tid) {
+    constexpr int nb = N / R;
+    constexpr int B = (nb + NT - 1) / NT;
+    double2 v[B][R];
+    int widx[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = tid + b * NT;
+        if ((b + 1) * NT <= nb || j < nb) {
+            const int g = j / NS, k = j - g * NS;
+            widx[b] = g * NS * R + k;
+            double2 w1 = make_double2(1.0, 0.0), w = w1;
+            if (NS > 1) {
+                w1 = twl[k];
+                if (DIR > 0) w1.y = -w1.y;
+                w = w1;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = buf[j + r * nb];
+                if (NS > 1 && r > 0) {
+                    x = cmul(x, w);
+                    if (r + 1 < R) w = cmul(w, w1);
+                }
+                v[b][r] = x;
+            }
+            dft_small<R, DIR>(v[b]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = tid + b * NT;
+        if ((b + 1) * NT <= nb || j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[widx[b] + r * NS] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int NT, int N, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_passes_l(double2 *buf, const double2 *twl, int tid) {
+    stockham_stage_l<R, DIR, NT, N, NS>(buf, twl, tid);
+    if constexpr (sizeof...(Rest) > 0) fft_passes_l<DIR, NT, N, NS * R, Rest...>(buf, twl + (NS > 1 ? NS : 0), tid);
+}
+
+// Number of LDS base twiddles of the passes from span NS on.
+template <int NS, int... Rs>
+struct TwCount {
+    static constexpr int value = 0;
+};
+template <int NS, int R, int... Rest>
+struct TwCount<NS, R, Rest...> {
+    static constexpr int value = (NS > 1 ? NS : 0) + TwCount<NS * R, Rest...>::value;
+};
+
+// Copy the base rows out of the pass-major global table (entry (NS - 1) + k is w^k).
+template <int NT, int NS, int R, int... Rest>
+__device__ __forceinline__ void tw_base_load(double2 *twl, const double2 *__restrict__ tw, int tid) {
+    if constexpr (NS > 1)
+        for (int k = tid; k < NS; k += NT) twl[k] = tw[(NS - 1) + k];
+    if constexpr (sizeof...(Rest) > 0) tw_base_load<NT, NS * R, Rest...>(twl + (NS > 1 ? NS : 0), tw, tid);
+}
+
 // Length of a compile-time transform, 0 for the runtime-planned one.
 template <typename S>
 struct FftLen {
@@ -354,6 +425,7 @@ struct FftRun;
 
 template <int DIR, int NT, int PT>
 struct FftRun<DIR, NT, PT, FftGeneric> {
+    static constexpr int ntw = 0;  // twiddles stay in global memory
     __device__ __forceinline__ static void run(double2 *buf, const FftPlan &P, const double2 *__restrict__ tw, int tid, int nth) {
         fft_lds<DIR, NT, PT>(buf, P, tw, tid, nth);
     }
@@ -362,7 +434,15 @@ struct FftRun<DIR, NT, PT, FftGeneric> {
 template <int DIR, int NT, int PT, int N, int... Rs>
 struct FftRun<DIR, NT, PT, FftSpec<N, Rs...>> {
     static_assert(N <= NT * PT, "size class too small for the transform");
+    static constexpr int ntw = TwCount<1, Rs...>::value;  // LDS base twiddles (run_l)
     __device__ __forceinline__ static void run(double2 *buf, const FftPlan &, const double2 *__restrict__ tw, int tid, int) {
         fft_passes_c<DIR, NT, N, 1, Rs...>(buf, tw, tid);
+    }
+    __device__ __forceinline__ static void load_tw(double2 *twl, const double2 *__restrict__ tw, int tid) {
+        tw_base_load<NT, 1, Rs...>(twl, tw, tid);
+    }
+    // twl: the bases written by load_tw (visible to all threads)
+    __device__ __forceinline__ static void run_l(double2 *buf, const double2 *twl, int tid) {
+        fft_passes_l<DIR, NT, N, 1, Rs...>(buf, twl, tid);
     }
 };

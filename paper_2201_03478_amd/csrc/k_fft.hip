@@ -59,12 +59,21 @@ __device__ inline void store_quad<double>(double *o, double a, double b, double 
 // transform of Z, O = G1 + i G2, separates as G1 = (O(r) + s1 O(-r)) / 2 and
 // G2 = (O(r) - s1 O(-r)) / (2 i) (the halves are folded into a and b).  For odd
 // nm the last column is alone (f2 = 0, d2 = d1 makes Z = d1 p H).
-template <int NT, int PT, typename S2, typename SOS>
+//
+// F and G are complex128 or complex64 (FT, GT); G rows have stride gst.  With
+// compile-time transforms (TWL) the passes take their twiddles from LDS bases that
+// the workgroup loads first, so no pass waits for a global load.  (A persistent
+// variant that walks consecutive pairs and prefetches the next pair's columns
+// measured slower at lmax 512 than one pair per workgroup.)
+template <int NT, int PT, typename S2, typename SOS, typename FT, typename GT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
-k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lmax, int nring, int rows,
+k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nring, int rows, int gst,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
                  const double2 *__restrict__ twos, const double2 *__restrict__ phase,
                  const double *__restrict__ dphi) {
+    using Fwd = FftRun<-1, NT, PT, S2>;
+    using Inv = FftRun<1, NT, PT, SOS>;
+    constexpr bool TWL = FftLen<S2>::value > 0 && FftLen<SOS>::value > 0;
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
     const int npair = lmax + 1;  // ceil(nm / 2)
@@ -75,18 +84,28 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
-    double2 *B = sbuf;  // length nos; the forward transform runs in B[0 .. n2)
+    double2 *B = sbuf;         // length nos; the forward transform runs in B[0 .. n2)
+    double2 *T2 = sbuf + nos;  // LDS twiddle bases (TWL): forward, then inverse
+    double2 *Tos = T2;
+    if constexpr (TWL) {
+        Tos = T2 + Fwd::ntw;
+        Fwd::load_tw(T2, tw2, tid);
+        Inv::load_tw(Tos, twos, tid);  // visible after the fill's barrier
+    }
 
     const double s1 = ((m - k) & 1) ? -1.0 : 1.0;
-    const double2 *col = F + ((size_t)k * nm + mi) * nring;
+    const FT *col = F + ((size_t)k * nm + mi) * nring;
     for (int j = tid; j < nring; j += nth) {
-        const double2 a = col[j];
-        const double2 b = two ? col[nring + j] : make_double2(0.0, 0.0);
-        B[j] = make_double2(a.x - b.y, a.y + b.x);                   // a + i b
+        const double2 a = ld2(col + j);
+        const double2 b = two ? ld2(col + nring + j) : make_double2(0.0, 0.0);
+        B[j] = make_double2(a.x - b.y, a.y + b.x);                         // a + i b
         B[n2 - 1 - j] = make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x));  // s1 (a - i b)
     }
     __syncthreads();
-    FftRun<-1, NT, PT, S2>::run(B, P2, tw2, tid, nth);
+    if constexpr (TWL)
+        Fwd::run_l(B, T2, tid);
+    else
+        Fwd::run(B, P2, tw2, tid, nth);
 
     // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from
     // n + n2 to n + nos (sources and targets are disjoint since nos >= n2 + lmax),
@@ -119,21 +138,39 @@ k_theta_upsample(const double2 *__restrict__ F, double2 *__restrict__ G, int lma
     }
     for (int t = lmax + 1 + tid; t < nos - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    FftRun<1, NT, PT, SOS>::run(B, Pos, twos, tid, nth);
+    if constexpr (TWL)
+        Inv::run_l(B, Tos, tid);
+    else
+        Inv::run(B, Pos, twos, tid, nth);
 
-    // Lane pairs write the two columns of a row side by side (one 32-byte run).
     const int r0 = -W / 2 + 1;
-    double2 *gk = G + (size_t)k * rows * nm + mi;
-    for (int q = tid; q < 2 * rows; q += nth) {
-        const int row = q >> 1, c = q & 1;
-        if (c && !two) continue;
-        int r = row + r0;
-        r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
-        const int rm = r == 0 ? 0 : nos - r;
-        const double2 o = B[r], om = B[rm];
-        const double2 g = c == 0 ? make_double2(o.x + s1 * om.x, o.y + s1 * om.y)
-                                 : make_double2(o.y - s1 * om.y, s1 * om.x - o.x);  // -i (o - s1 om)
-        gk[(size_t)row * nm + c] = g;
+    GT *gk = G + (size_t)k * rows * gst + mi;
+    if constexpr (sizeof(GT) == sizeof(float2)) {
+        // complex64: one thread writes both columns of a row as one 16-byte store (gst
+        // and mi are even; an odd last column is written with a zero beside it, in the
+        // padding element of the row)
+        for (int row = tid; row < rows; row += nth) {
+            int r = row + r0;
+            r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
+            const int rm = r == 0 ? 0 : nos - r;
+            const double2 o = B[r], om = B[rm];
+            const double2 g1 = make_double2(o.x + s1 * om.x, o.y + s1 * om.y);
+            const double2 g2 = two ? make_double2(o.y - s1 * om.y, s1 * om.x - o.x) : make_double2(0.0, 0.0);
+            *(float4 *)(gk + (size_t)row * gst) = make_float4((float)g1.x, (float)g1.y, (float)g2.x, (float)g2.y);
+        }
+    } else {
+        // Lane pairs write the two columns of a row side by side (one 32-byte run).
+        for (int q = tid; q < 2 * rows; q += nth) {
+            const int row = q >> 1, c = q & 1;
+            if (c && !two) continue;
+            int r = row + r0;
+            r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
+            const int rm = r == 0 ? 0 : nos - r;
+            const double2 o = B[r], om = B[rm];
+            const double2 g = c == 0 ? make_double2(o.x + s1 * om.x, o.y + s1 * om.y)
+                                     : make_double2(o.y - s1 * om.y, s1 * om.x - o.x);  // -i (o - s1 om)
+            gk[(size_t)row * gst + c] = g;
+        }
     }
 }
 
@@ -144,12 +181,12 @@ __device__ __forceinline__ double2 phi_pair(double2 v, int k) {
 
 // G row (nm spectral values) into registers; lanes past nm read a valid duplicate,
 // which phi_scatter replaces by zero.
-template <int NT, int MAXC>
-__device__ __forceinline__ void phi_load(double2 (&spec)[MAXC], const double2 *__restrict__ src, int tid, int nm) {
+template <int NT, int MAXC, typename GT>
+__device__ __forceinline__ void phi_load(double2 (&spec)[MAXC], const GT *__restrict__ src, int tid, int nm) {
 #pragma unroll
     for (int i = 0; i < MAXC; ++i) {
         const int t = tid + i * NT;
-        spec[i] = src[t < nm ? t : nm - 1];
+        spec[i] = ld2(src + (t < nm ? t : nm - 1));
     }
 }
 
@@ -174,9 +211,9 @@ __device__ __forceinline__ void phi_scatter(double2 *A, const double2 (&spec)[MA
 // loaded into registers while the first is transformed, and the first k's columns
 // wait in registers, so each lane writes both k's component pairs of a column as
 // one 16-byte store (a column's map record is contiguous in k).
-template <typename T, int NT, int PT, typename SP, int KP>
+template <typename T, int NT, int PT, typename SP, int KP, typename GT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
-k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int cols, int ncp,
+k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int gst, int cols, int ncp,
                 int W, int nk, FftPlan Pp, const double2 *__restrict__ twp) {
     static_assert(KP == 1 || KP == 2, "one or two k per workgroup");
     extern __shared__ double2 sbuf[];
@@ -190,10 +227,13 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
     const int np = Pp.n;
     double2 *A = sbuf;
     constexpr int NP = FftLen<SP>::value;  // 0: runtime-planned transform
+    using Run = FftRun<1, NT, PT, SP>;
+    double2 *Tw = sbuf + np;  // compile-time transforms: LDS twiddle bases
+    if constexpr (NP > 0) Run::load_tw(Tw, twp, tid);  // visible after the first barrier
     constexpr int MAXC = (PT + 1) / 2;                            // nm <= NT MAXC
     constexpr int MAXS = NP > 0 ? (NP + 15 + NT - 1) / NT : PT + 1;  // cols <= np + 15 <= NT MAXS
     const int q0 = -W / 2 + 1;
-    const double2 *src = G + ((size_t)k0 * rows + row) * nm;
+    const GT *src = G + ((size_t)k0 * rows + row) * gst;
     T *dst = maps + (size_t)row * cols * ncp + 2 * k0;
     double2 spec[MAXC];
     phi_load<NT, MAXC>(spec, src, tid, nm);
@@ -201,8 +241,11 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
     __syncthreads();
     T stage[KP == 2 ? MAXS : 1][2];
     if (two) {
-        phi_load<NT, MAXC>(spec, src + (size_t)rows * nm, tid, nm);
-        FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
+        phi_load<NT, MAXC>(spec, src + (size_t)rows * gst, tid, nm);
+        if constexpr (NP > 0)
+            Run::run_l(A, Tw, tid);
+        else
+            Run::run(A, Pp, twp, tid, nth);
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) {
             int col = tid + i * NT;
@@ -217,7 +260,10 @@ k_phi_synthesis(const double2 *__restrict__ G, T *__restrict__ maps, int lmax, i
         phi_scatter<NT, MAXC>(A, spec, tid, lmax, np);
         __syncthreads();
     }
-    FftRun<1, NT, PT, SP>::run(A, Pp, twp, tid, nth);
+    if constexpr (NP > 0)
+        Run::run_l(A, Tw, tid);
+    else
+        Run::run(A, Pp, twp, tid, nth);
     const int k = two ? k0 + 1 : k0;
 #pragma unroll
     for (int i = 0; i < MAXS; ++i) {
@@ -380,7 +426,18 @@ k_theta_adjoint(const double2 *__restrict__ G, double2 *__restrict__ F, int lmax
     }
 }
 
+__global__ void k_widen(const float2 *__restrict__ src, double2 *__restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = ld2(src + i);
+}
+
 }  // namespace
+
+hipError_t sc_launch_widen(const float2 *src, double2 *dst, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
 
 // Size class of a transform of length n: 0 = (256 threads, 9 points each),
 // 1 = (512, 9), 2 = (1024, 9); the longest supported transform is 9216 points.
@@ -388,16 +445,22 @@ static inline int fft_class(int n) {
     return n <= SC_FFT_NT * SC_FFT_PT ? 0 : n <= SC_FFT_NT_BIG * SC_FFT_PT ? 1 : 2;
 }
 
-template <int NT, int PT, typename S2 = FftGeneric, typename SOS = FftGeneric>
-static hipError_t theta_up(sc_plan *p) {
+template <int NT, int PT, typename S2, typename SOS, typename CT>
+static hipError_t theta_up_t(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (p->lmax + 1);  // column pairs
-    const size_t lds = sizeof(double2) * (size_t)p->n2os;
-    auto kern = k_theta_upsample<NT, PT, S2, SOS>;
+    const int ntw = FftRun<-1, NT, PT, S2>::ntw + FftRun<1, NT, PT, SOS>::ntw;  // zero unless both are compile-time
+    const size_t lds = sizeof(double2) * ((size_t)p->n2os + ntw);
+    auto kern = k_theta_upsample<NT, PT, S2, SOS, CT, CT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->F, p->G, p->lmax, p->nring, p->rows, p->W,
-                       p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const CT *)p->F, (CT *)p->G, p->lmax, p->nring,
+                       p->rows, p->gst, p->W, p->p2, p->p2os, p->tw2, p->tw2os, p->phase, p->dphi);
     return hipGetLastError();
+}
+
+template <int NT, int PT, typename S2 = FftGeneric, typename SOS = FftGeneric>
+static hipError_t theta_up(sc_plan *p) {
+    return p->mid32 ? theta_up_t<NT, PT, S2, SOS, float2>(p) : theta_up_t<NT, PT, S2, SOS, double2>(p);
 }
 
 template <typename T, int NT, int PT, typename SP = FftGeneric>
@@ -407,12 +470,20 @@ static hipError_t phi_syn(sc_plan *p) {
     constexpr int KP = sizeof(T) == 4 && FftLen<SP>::value > 0 ? 2 : 1;
     const int nk = p->kmax + 1;
     const int nblk = (nk + KP - 1) / KP * p->rows;
-    const size_t lds = sizeof(double2) * (size_t)p->nphi;
-    auto kern = k_phi_synthesis<T, NT, PT, SP, KP>;
-    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, p->G, (T *)p->maps, p->lmax,
-                       p->rows, p->cols, p->ncp, p->W, nk, p->pphi, p->twphi);
+    const size_t lds = sizeof(double2) * ((size_t)p->nphi + FftRun<1, NT, PT, SP>::ntw);
+    if (p->mid32) {
+        auto kern = k_phi_synthesis<T, NT, PT, SP, KP, float2>;
+        hipError_t e = sc_set_lds_attr((const void *)kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const float2 *)p->G, (T *)p->maps, p->lmax,
+                           p->rows, p->gst, p->cols, p->ncp, p->W, nk, p->pphi, p->twphi);
+    } else {
+        auto kern = k_phi_synthesis<T, NT, PT, SP, KP, double2>;
+        hipError_t e = sc_set_lds_attr((const void *)kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const double2 *)p->G, (T *)p->maps, p->lmax,
+                           p->rows, p->gst, p->cols, p->ncp, p->W, nk, p->pphi, p->twphi);
+    }
     return hipGetLastError();
 }
 

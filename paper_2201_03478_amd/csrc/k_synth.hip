@@ -135,9 +135,9 @@ __device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, cons
 }
 
 // Up to 3 rings per lane the kernel fits 168 registers: three waves per SIMD.
-template <int RPT>
+template <int RPT, typename FT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RPT <= 3 ? 3 : 2)))
-k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
+k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
             const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
             int ngroups, int alm_lmax) {
@@ -243,12 +243,12 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
         }
         if (j < nh) {
             if (tp == 0) {  // F_k(theta_j, m); F_k(pi - theta_j, -m) (for m = 0: -m = m, skip the equator)
-                F[((size_t)k * nm + (m + lmax)) * nring + j] = fp[r];
-                if (m > 0 || js != j) F[((size_t)k * nm + (lmax - m)) * nring + js] = fm[r];
+                st2(&F[((size_t)k * nm + (m + lmax)) * nring + j], fp[r]);
+                if (m > 0 || js != j) st2(&F[((size_t)k * nm + (lmax - m)) * nring + js], fm[r]);
             } else if (m > 0 && js != j) {  // F_k(theta_j, -m) = (-1)^k sum wm v; F_k(pi - theta_j, m) = (-1)^k sum wp v
                 const double sk = (k & 1) ? -1.0 : 1.0;
-                F[((size_t)k * nm + (lmax - m)) * nring + j] = cscale(fm[r], sk);
-                F[((size_t)k * nm + (m + lmax)) * nring + js] = cscale(fp[r], sk);
+                st2(&F[((size_t)k * nm + (lmax - m)) * nring + j], cscale(fm[r], sk));
+                st2(&F[((size_t)k * nm + (m + lmax)) * nring + js], cscale(fp[r], sk));
             }
         }
     }
@@ -256,22 +256,25 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, do
 
 }  // namespace
 
-#define SC_RING_CASE(R)                                                                                      \
-    case R:                                                                                                  \
-        hipLaunchKernelGGL(k_ring_sums<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,         \
-                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, \
-                           p->ngroups, p->alm_lmax);                                                         \
-        break;
+template <typename FT>
+static void launch_ring_sums(sc_plan *p, const double *alm, const double *blm, FT *F) {
+    const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups;
+    auto kern = k_ring_sums<4, FT>;
+    switch (p->rpt) {
+        case 1: kern = k_ring_sums<1, FT>; break;
+        case 2: kern = k_ring_sums<2, FT>; break;
+        case 3: kern = k_ring_sums<3, FT>; break;
+        default: break;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm, (const double2 *)blm, F,
+                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, p->ngroups, p->alm_lmax);
+}
 
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm) {
-    const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups;
-    switch (p->rpt) {
-        SC_RING_CASE(1)
-        SC_RING_CASE(2)
-        SC_RING_CASE(3)
-        default:
-        SC_RING_CASE(4)
-    }
+    if (p->mid32)
+        launch_ring_sums(p, alm, blm, (float2 *)p->F);
+    else
+        launch_ring_sums(p, alm, blm, p->F);
     return hipGetLastError();
 }
 

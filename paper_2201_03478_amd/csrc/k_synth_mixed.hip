@@ -77,9 +77,9 @@ __device__ __forceinline__ void mx_steps(int t0, int t1, const double *cA, const
     for (int t = te; t < t1; ++t) mx_step<RPT, MASK>(mx_load(t, cA, cB, cW), x, u, up, e, acc);
 }
 
-template <int RPT>
+template <int RPT, typename FT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RPT <= 3 ? 3 : 2)))
-k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ blm, double2 *__restrict__ F,
+k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT *__restrict__ F,
                   const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
                   const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
                   int ngroups, int alm_lmax) {
@@ -198,12 +198,12 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
         const double2 fp = make_double2(f[0], f[1]), fm = make_double2(f[2], f[3]);
         if (j < nh) {
             if (tp == 0) {
-                F[((size_t)k * nm + (m + lmax)) * nring + j] = fp;
-                if (m > 0 || js != j) F[((size_t)k * nm + (lmax - m)) * nring + js] = fm;
+                st2(&F[((size_t)k * nm + (m + lmax)) * nring + j], fp);
+                if (m > 0 || js != j) st2(&F[((size_t)k * nm + (lmax - m)) * nring + js], fm);
             } else if (m > 0 && js != j) {  // exchanged, times (-1)^k (see k_synth.hip)
                 const double sk = (k & 1) ? -1.0 : 1.0;
-                F[((size_t)k * nm + (lmax - m)) * nring + j] = cscale(fm, sk);
-                F[((size_t)k * nm + (m + lmax)) * nring + js] = cscale(fp, sk);
+                st2(&F[((size_t)k * nm + (lmax - m)) * nring + j], cscale(fm, sk));
+                st2(&F[((size_t)k * nm + (m + lmax)) * nring + js], cscale(fp, sk));
             }
         }
     }
@@ -211,22 +211,26 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
 
 }  // namespace
 
-#define SC_MIXED_CASE(R)                                                                                     \
-    case R:                                                                                                  \
-        hipLaunchKernelGGL(k_ring_sums_mixed<R>, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm,   \
-                           (const double2 *)blm, p->F, p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax,      \
-                           p->kmax, p->nring, p->ngroups_mx, p->alm_lmax);                                   \
-        break;
+template <typename FT>
+static void launch_mixed(sc_plan *p, const double *alm, const double *blm, FT *F) {
+    const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups_mx;
+    auto kern = k_ring_sums_mixed<4, FT>;
+    switch (p->rpt_mx) {
+        case 1: kern = k_ring_sums_mixed<1, FT>; break;
+        case 2: kern = k_ring_sums_mixed<2, FT>; break;
+        case 3: kern = k_ring_sums_mixed<3, FT>; break;
+        default: break;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm, (const double2 *)blm, F,
+                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, p->ngroups_mx,
+                       p->alm_lmax);
+}
 
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm) {
-    const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups_mx;
-    switch (p->rpt_mx) {
-        SC_MIXED_CASE(1)
-        SC_MIXED_CASE(2)
-        SC_MIXED_CASE(3)
-        default:
-        SC_MIXED_CASE(4)
-    }
+    if (p->mid32)
+        launch_mixed(p, alm, blm, (float2 *)p->F);
+    else
+        launch_mixed(p, alm, blm, p->F);
     return hipGetLastError();
 }
 

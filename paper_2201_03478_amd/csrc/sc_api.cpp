@@ -414,6 +414,8 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     }
     p->big = p->sp2 > 1 || p->spos > 1 || p->spphi > 1;
     p->spad = (2 * lmax + 1 + 63) & ~63;
+    p->mid32 = precision != SC_FP64 && !p->big;
+    p->gst = p->mid32 ? 2 * lmax + 2 : 2 * lmax + 1;
 
     const size_t nm = 2 * (size_t)lmax + 1;
     size_t tot = 0;
@@ -498,7 +500,7 @@ int sc_plan_set_stream(sc_plan *p, void *stream) {
 int sc_plan_info(const sc_plan *p, int64_t *out, int nout) {
     if (!p || (nout > 0 && !out)) return fail(SC_EINVAL, "NULL plan or output");
     const int64_t v[] = {p->lmax, p->kmax, p->prec, p->W, p->nring, p->n2, p->n2os, p->nphi,
-                         p->rows, p->cols, p->ncomp, p->ncp, (int64_t)p->ws_bytes};
+                         p->rows, p->cols, p->ncomp, p->ncp, (int64_t)p->ws_bytes, p->mid32 ? 8 : 16};
     const int nv = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < nout && i < nv; ++i) out[i] = v[i];
     return nv;
@@ -967,8 +969,17 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
     const void *src = nullptr;
     size_t bytes = 0;
     if (which == 0) {
+        // complex128 in either storage
         src = p->F;
-        bytes = sizeof(double2) * (p->kmax + 1) * (2 * (size_t)p->lmax + 1) * p->nring;
+        const size_t n = (p->kmax + 1) * (2 * (size_t)p->lmax + 1) * p->nring;
+        bytes = sizeof(double2) * n;
+        if (p->mid32) {
+            if ((int64_t)bytes > capacity)
+                return fail(SC_EINVAL, "destination holds %lld bytes, need %zu", (long long)capacity, bytes);
+            hipError_t e = sc_launch_widen((const float2 *)p->F, (double2 *)dst, n, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "stage copy");
+            return (int64_t)bytes;
+        }
     } else if (which == 1) {
         src = p->maps;
         bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;

@@ -111,9 +111,17 @@ struct sc_plan {
     double2 *S;        // big plans: theta spectra, [kmax+1][2 lmax+1][spad]
     int spad;          // padded row length of S (>= 2 lmax + 1)
 
+    // Storage of the two spectral intermediates of the forward synthesis.  The FP32-map
+    // forms (without split transforms) hold them as complex64: every value is still
+    // computed in FP64 and rounded once on store, an error (2^-24 relative) of the
+    // size the FP32 maps already carry, for half the bytes of the two largest
+    // round trips through HBM.  The adjoint always uses them as complex128.
+    int mid32;         // F and G hold float2 (forward path)
+    int gst;           // row stride of G in elements: 2 lmax + 1, or 2 lmax + 2 with mid32
+
     // device buffers
-    double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums
-    double2 *G;        // [kmax+1][rows][2 lmax+1] theta-upsampled, deconvolved
+    double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums (float2 with mid32)
+    double2 *G;        // [kmax+1][rows][gst] theta-upsampled, deconvolved (float2 with mid32)
     void *maps;        // [rows][cols][ncp] float or double
     double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
     double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
@@ -178,6 +186,7 @@ hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double
 void sc_choose_ring_layout_mixed(int nring, int *rpt, int *ngroups);
 hipError_t sc_launch_theta_upsample(sc_plan *p);
 hipError_t sc_launch_theta_upsample_big(sc_plan *p);
+hipError_t sc_launch_widen(const float2 *src, double2 *dst, size_t n, hipStream_t s);  // complex64 -> complex128
 hipError_t sc_launch_phi_synthesis_big(sc_plan *p);
 hipError_t sc_launch_phi_adjoint_big(sc_plan *p, const void *gmaps);
 hipError_t sc_launch_theta_adjoint_big(sc_plan *p);
@@ -247,3 +256,12 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// Loads and stores of complex values held as complex128 or complex64 (computed in FP64).
+__device__ __forceinline__ double2 ld2(const double2 *p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2 *p) {
+    const float2 v = *p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double2 *p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2 *p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }

@@ -69,9 +69,19 @@ def test_ring_sums_near_poles_lmax512(torch_dev, api, oracle_lib):
     torch, dev = torch_dev
     L, K = 512, 100
     a, b = _inputs(L, K, 2)
-    plan = api.Plan(L, K, "f64maps_f32gather")
+    plan = api.Plan(L, K, "fp64")
     plan.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
     F = plan.debug_stage(0)
+    # the FP32-map form runs the same FP64 kernel and stores F as complex64: each value
+    # is the FP64 one rounded once (FP32 subnormals aside)
+    plan32 = api.Plan(L, K, "f64maps_f32gather")
+    plan32.set_sky_beam(_to(torch, dev, a), _to(torch, dev, b))
+    F32 = plan32.debug_stage(0)
+    torch.cuda.synchronize()
+    dev_err = (F32 - F).abs() - (2.0 ** -24 * F.abs() + 1e-37)
+    assert float(dev_err.max()) <= 0.0
+    assert float((F32 - F).abs().max()) > 0.0  # it is rounded
+    del plan32, F32, dev_err
     nr = plan.info()["n_rings"]
     js = np.array([0, 1, nr // 3, nr - 1])
     th = (js + 0.5) * math.pi / nr
