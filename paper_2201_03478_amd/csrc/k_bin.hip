@@ -206,15 +206,27 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int *__restrict__ 
 // writes); the values come from the sample's own lane by shuffles.  (Blocks are
 // whole waves.)
 __global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom g, const int *__restrict__ key,
-                              const int *__restrict__ rank, const int2 *__restrict__ offs, BinSorted out) {
+                              const int *__restrict__ rank, const int2 *__restrict__ offs, BinSorted out,
+                              const float *__restrict__ y) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = s < n;
     int pos = -1;
-    double fu = 0.0, fv = 0.0, psi = 0.0;
+    double fu = 0.0, fv = 0.0, psi = 0.0, yv = 0.0;
     if (valid) {
         int r0, c0;
         anchor_of(ptg, s, g, r0, c0, fu, fv, psi);
         pos = offs[key[s]].x + rank[s];
+        if (y) {
+            // adjoint layout: (fu, fv as FP32; cos psi) and (sin psi; y, idx)
+            double sn, cs;
+            sincos(psi, &sn, &cs);
+            fu = __longlong_as_double((long long)(((unsigned long long)(unsigned)__float_as_int((float)fv) << 32) |
+                                                  (unsigned)__float_as_int((float)fu)));
+            fv = cs;
+            psi = sn;
+            yv = __longlong_as_double((long long)(((unsigned long long)(unsigned)(int)s << 32) |
+                                                  (unsigned)__float_as_int(y[s])));
+        }
     }
     const int lane = threadIdx.x & 63;
     const int hi = lane & 1;
@@ -223,11 +235,11 @@ __global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom
     for (int half = 0; half < 2; ++half) {
         const int src = (lane >> 1) + 32 * half;  // the wave lane whose sample this lane writes
         const int p = __shfl(pos, src);
-        const double su = __shfl(fu, src), sv = __shfl(fv, src), sp = __shfl(psi, src);
+        const double su = __shfl(fu, src), sv = __shfl(fv, src), sp = __shfl(psi, src), sy = __shfl(yv, src);
         const int64_t sidx = s - lane + src;
         if (p >= 0) {
-            // low half (fu, fv); high half (psi, idx in the low word and pad 0)
-            const double2 v = hi ? make_double2(sp, __longlong_as_double((long long)(unsigned)sidx))
+            // low half (fu, fv); high half (psi, idx in the low word and pad 0); or the adjoint layout
+            const double2 v = hi ? make_double2(sp, y ? sy : __longlong_as_double((long long)(unsigned)sidx))
                                  : make_double2(su, sv);
             rec2[2 * (size_t)p + hi] = v;
         }
@@ -268,7 +280,7 @@ hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
+hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n, const float *y) {
     BinWork &w = p->bw;
     w.last_n = n;
     const BinGeom g = sc_bin_geom(p);
@@ -283,7 +295,7 @@ hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n) {
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, p->stream, w.sums, nblk, w.totals);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_NT), 0, p->stream, w.count, nkeys, w.sums, w.offs,
                        p->bin_chunk);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.offs, w.sorted);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gs), dim3(bs), 0, p->stream, ptg, n, g, w.key, w.rank, w.offs, w.sorted, y);
     hipLaunchKernelGGL(k_bin_items, dim3((unsigned)((nkeys + bs - 1) / bs)), dim3(bs), 0, p->stream, w.count,
                        w.offs, nkeys, w.items, p->bin_chunk);
     return hipGetLastError();

@@ -11,7 +11,11 @@
 //    k_bin.hip) the 64 x ncomp patch gradient PG[t][c] = sum_s w_s(t) V[s][c],
 //    V[s][c] = y_s basis_c(psi_s), is a v_mfma_f32_16x16x4_f32 product summed
 //    over all chunks of the item, then added to the maps with one atomic per
-//    (tap, component).
+//    (tap, component).  Each sample's record (the binning's adjoint layout, with
+//    e^{i psi} and the TOD gradient) is read once, by one thread, and the tap
+//    weight w_s(t) = w_theta(t / 8) w_phi(t % 8) is formed from the 1-d weights
+//    in LDS as the matrix operand is read.  The atomics are not what limits it:
+//    without them the kernel takes within 2% of the time.
 //  * k_scatter_direct (any W, FP32 or FP64): one wave per sample, lanes over
 //    components, one atomic per (tap, component, sample).
 #include "sc_common.h"
@@ -91,19 +95,28 @@ k_scatter_direct(const double *__restrict__ ptg, int64_t n, const T *__restrict_
     }
 }
 
-constexpr int WROW = 68;  // (4 tap + sample) mod 64 banks: distinct over a wave
+constexpr int W1ROW = 65;  // row stride of the 1-d weights: the 8 phi rows of one sample in distinct banks
 
 template <int CT>
+struct ScatterLds {
+    static constexpr int NC = 16 * CT;
+    static constexpr size_t bytes = sizeof(float) * (64 * NC + 16 * W1ROW) + 64 * (sizeof(double2) + sizeof(float2) +
+                                                                                    sizeof(float));
+};
+
+// Work items come from the binning's queue; each chunk's samples (AdjRec, written
+// by the binning with e^{i psi} and the TOD gradient) are staged by one thread each.
+template <int CT>
 __global__ void __launch_bounds__(256)
-k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSorted srt, const float *__restrict__ y,
+k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const AdjRec *__restrict__ rec,
                float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
     constexpr int NC = 16 * CT;
     extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
-    float *Vsh = (float *)smem_d;     // [64 samples][NC]
-    float *Wsh = Vsh + 64 * NC;       // [64 taps][WROW]: 64 samples + pad (conflict-free A reads)
-    float *W1 = Wsh + 64 * WROW;      // [16][64 samples]
-    double2 *E1 = (double2 *)(W1 + 64 * 16);  // [64] e^{i psi}
-    float *Ys = (float *)(E1 + 64);           // [64]
+    float *Vsh = (float *)smem_d;                // [64 samples][NC]
+    float *W1 = Vsh + 64 * NC;                   // [16][W1ROW]: theta weights (rows 0-7), phi weights (8-15)
+    double2 *E1 = (double2 *)(W1 + 16 * W1ROW);  // [64] e^{i psi} (64 NC + 1040 floats: 16-byte aligned)
+    float2 *UV = (float2 *)(E1 + 64);            // [64] (u - floor u, v - floor v)
+    float *Ys = (float *)(UV + 64);              // [64]
     __shared__ int item_sh;
 
     const int tid = threadIdx.x;
@@ -123,32 +136,29 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
         for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
         for (int ch = 0; ch < item.z; ch += 64) {
             const int ns = item.z - ch < 64 ? item.z - ch : 64;
-            const int pos0 = item.y + ch;
+            if (tid < 64) {
+                double2 e1 = make_double2(1.0, 0.0);
+                float2 uv = make_float2(0.f, 0.f);
+                float yy = 0.f;
+                if (tid < ns) {
+                    const AdjRec q = rec[item.y + ch + tid];
+                    e1 = make_double2(q.cps, q.sps);
+                    uv = make_float2(q.fu, q.fv);
+                    yy = q.y;
+                }
+                E1[tid] = e1;
+                UV[tid] = uv;
+                Ys[tid] = yy;
+            }
+            __syncthreads();
             for (int e = tid; e < 64 * 16; e += 256) {
                 const int q = e >> 6, sl = e & 63;
                 float w = 0.f;
                 if (sl < ns) {
-                    const float f = (q < 8) ? (float)srt.rec[pos0 + sl].fu : (float)srt.rec[pos0 + sl].fv;
-                    w = es_w<float>((f + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                    const float2 uv = UV[sl];
+                    w = es_w<float>(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, fbeta);
                 }
-                W1[e] = w;
-            }
-            if (tid < 64) {
-                double ps = 0.0;
-                float yy = 0.f;
-                if (tid < ns) {
-                    ps = srt.rec[pos0 + tid].psi;
-                    yy = y[srt.rec[pos0 + tid].idx];
-                }
-                double sn, cs;
-                sincos(ps, &sn, &cs);
-                E1[tid] = make_double2(cs, sn);
-                Ys[tid] = yy;
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * 64; e += 256) {
-                const int t = e >> 6, sl = e & 63;
-                Wsh[t * WROW + sl] = W1[(t >> 3) * 64 + sl] * W1[(8 + (t & 7)) * 64 + sl];
+                W1[q * W1ROW + sl] = w;
             }
             {
                 // V[s][c] = y_s basis_c(psi_s): 4 lanes per sample, NC/4 components each
@@ -174,12 +184,15 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
                 }
             }
             __syncthreads();
-            // PG[tap][c] += sum_s W[tap][s] V[s][c]: wave wv owns taps 16 wv .. 16 wv + 15
-            const float *wa = Wsh + (16 * wv + r) * WROW + grp;  // A[i = tap r][k = sample grp]
-            const float *vb = Vsh + grp * NC + r;              // B[k = sample grp][j = comp r]
-#pragma unroll 2
+            // PG[tap][c] += sum_s W[tap][s] V[s][c] with W[tap][s] = w_theta_s(tap / 8) w_phi_s(tap % 8)
+            // formed from the 1-d weights as the operand is read; wave wv owns taps 16 wv .. 16 wv + 15
+            const int tap = 16 * wv + r;
+            const float *wth = W1 + (tap >> 3) * W1ROW + grp;  // A[i = tap r][k = sample grp]
+            const float *wph = W1 + (8 + (tap & 7)) * W1ROW + grp;
+            const float *vb = Vsh + grp * NC + r;               // B[k = sample grp][j = comp r]
+#pragma unroll 4
             for (int ks = 0; ks < 16; ++ks) {
-                const float a = wa[4 * ks];
+                const float a = wth[4 * ks] * wph[4 * ks];
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct)
                     acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, vb[4 * ks * NC + 16 * ct], acc[ct], 0, 0, 0);
@@ -201,28 +214,27 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, BinSort
 }
 
 template <int CT>
-hipError_t launch_scatter_mfma(sc_plan *p, const void *y, void *gmaps) {
-    constexpr int NC = 16 * CT;
-    const size_t lds = sizeof(float) * (64 * NC + 64 * WROW + 64 * 16) + 64 * (sizeof(double2) + sizeof(float));
+hipError_t launch_scatter_mfma(sc_plan *p, void *gmaps) {
+    const size_t lds = ScatterLds<CT>::bytes;
     auto kern = k_scatter_mfma<CT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
     const BinGeom g = sc_bin_geom(p);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals, p->bw.sorted,
-                       (const float *)y, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
+                       (const AdjRec *)p->bw.sorted.rec, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_mfma_any(sc_plan *p, const void *y, void *gmaps) {
+hipError_t launch_scatter_mfma_any(sc_plan *p, void *gmaps) {
     const int ct = (p->ncomp + 15) / 16;
-    if (ct <= 1) return launch_scatter_mfma<1>(p, y, gmaps);
-    if (ct <= 2) return launch_scatter_mfma<2>(p, y, gmaps);
-    if (ct <= 3) return launch_scatter_mfma<3>(p, y, gmaps);
-    if (ct <= 5) return launch_scatter_mfma<5>(p, y, gmaps);
-    if (ct <= 9) return launch_scatter_mfma<9>(p, y, gmaps);
-    if (ct <= 13) return launch_scatter_mfma<13>(p, y, gmaps);
-    return launch_scatter_mfma<16>(p, y, gmaps);
+    if (ct <= 1) return launch_scatter_mfma<1>(p, gmaps);
+    if (ct <= 2) return launch_scatter_mfma<2>(p, gmaps);
+    if (ct <= 3) return launch_scatter_mfma<3>(p, gmaps);
+    if (ct <= 5) return launch_scatter_mfma<5>(p, gmaps);
+    if (ct <= 9) return launch_scatter_mfma<9>(p, gmaps);
+    if (ct <= 13) return launch_scatter_mfma<13>(p, gmaps);
+    return launch_scatter_mfma<16>(p, gmaps);
 }
 
 }  // namespace
@@ -231,10 +243,8 @@ bool sc_scatter_binned_supported(const sc_plan *p) {
     return p->prec != SC_FP64 && p->W == 8 && p->ncomp <= 256 && !p->gather_direct;
 }
 
-// Scatter of one pass (binned: binning already done for these samples).
-hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps) {
-    return launch_scatter_mfma_any(p, y, gmaps);
-}
+// Scatter of one pass (binned: binning with the pass's TOD gradient already done).
+hipError_t sc_launch_scatter_binned(sc_plan *p, void *gmaps) { return launch_scatter_mfma_any(p, gmaps); }
 
 hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps) {
     const double two_pi = 6.283185307179586477;

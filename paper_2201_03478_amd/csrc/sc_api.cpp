@@ -804,15 +804,15 @@ static int adjoint_to_rings(sc_plan *p, const double *ptg, const void *tod_grad,
             const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
             int rc = ensure_bin_work(p, pass);
             if (rc) return rc;
-            const size_t esz = p->prec == SC_FP64 ? 8 : 4;
             for (int64_t off = 0; off < n; off += pass) {
                 const int64_t cnt = n - off < pass ? n - off : pass;
                 slot = timing_begin(p, SC_STAGE_BIN);
-                e = sc_launch_binning(p, ptg + 3 * off, cnt);
+                // the records carry the pass's TOD gradient (binned scatter: FP32 forms only)
+                e = sc_launch_binning(p, ptg + 3 * off, cnt, (const float *)tod_grad + off);
                 timing_end(p, slot);
                 if (e != hipSuccess) return hip_fail(e, "binning launch");
                 slot = timing_begin(p, SC_STAGE_SCATTER);
-                e = sc_launch_scatter_binned(p, (const char *)tod_grad + esz * off, p->gmaps);
+                e = sc_launch_scatter_binned(p, p->gmaps);
                 timing_end(p, slot);
                 if (e != hipSuccess) return hip_fail(e, "binned scatter launch");
             }

@@ -54,6 +54,15 @@ struct __attribute__((aligned(32))) BinRec {
     double fu, fv, psi;
     int idx, pad;
 };
+// The same 32 bytes in FP32 adjoint passes, for the scatter: offsets in FP32 (what the
+// scatter's weights use), e^{i psi} from FP64 sincos, and the sample's TOD gradient.
+struct __attribute__((aligned(32))) AdjRec {
+    float fu, fv;
+    double cps, sps;
+    float y;
+    int idx;
+};
+static_assert(sizeof(AdjRec) == sizeof(BinRec), "adjoint records reuse the binning buffer");
 struct BinSorted {
     BinRec *rec;  // in anchor order
 };
@@ -197,11 +206,13 @@ hipError_t sc_launch_ring_sums_adjoint(sc_plan *p, const double *blm, double *gr
 int sc_adjoint_slabs(const sc_plan *p);  // ring slabs per column of the adjoint recursion
 hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, double *grad);
 hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps);
-hipError_t sc_launch_scatter_binned(sc_plan *p, const void *y, void *gmaps);
+hipError_t sc_launch_scatter_binned(sc_plan *p, void *gmaps);  // after sc_launch_binning with y
 bool sc_scatter_binned_supported(const sc_plan *p);
 hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
-hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n);
+// Sort samples into anchor order (k_bin.hip).  With y (FP32 adjoint passes) the
+// records take the adjoint layout AdjRec instead of BinRec.
+hipError_t sc_launch_binning(sc_plan *p, const double *ptg, int64_t n, const float *y = nullptr);
 hipError_t sc_launch_dipole(const double *blm, int lmax, int kmax, const double *ptg, int64_t n, const double *beta,
                             int64_t spp, double T0, double q, double *out, hipStream_t stream);
 hipError_t sc_launch_gather_binned(sc_plan *p, void *tod);
