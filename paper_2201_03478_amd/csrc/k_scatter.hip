@@ -213,6 +213,174 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
     }
 }
 
+// Split products (the default): the same patch gradients from
+// v_mfma_f32_16x16x32_f16, to FP32 accuracy.  Operands are written as two FP16
+// parts, x = hi + lo with hi = fp16(x), lo = fp16(x - hi) (|x - hi - lo| <= 2^-22 |x|),
+// and PG ~ Wh Vh + Wh Vl + Wl Vh (the omitted Wl Vl is below 2^-22 of the product):
+// three FP16 products per 16 x 16 x 32 block, 3/16 of the matrix time of the FP32
+// form.  Ranges: tap weights (in [0, 1]) are scaled by 2^14, the chunk's V by
+// 2^(14 - e) with 2^e above its largest |y|; each chunk's product goes to a
+// temporary accumulator that is added, unscaled, into the item's sums.  The
+// operand layout of the 16x16x32 instruction: A[i][k] in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D as in the FP32 form.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+template <int CT>
+struct SplitScatterLds {
+    static constexpr size_t bytes = 2 * (2 * (size_t)CT * 64 * sizeof(half8)) + sizeof(float) * 16 * W1ROW +
+                                    64 * (sizeof(double2) + sizeof(float2) + sizeof(float));
+};
+
+template <int CT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT <= 5 ? 5 : 3)))
+k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const AdjRec *__restrict__ rec,
+                float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
+    constexpr int NC = 16 * CT;
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
+    half8 *Bhi = (half8 *)smem_d;                // [2 sample halves][CT][64 lanes]
+    half8 *Blo = Bhi + 2 * CT * 64;
+    float *W1 = (float *)(Blo + 2 * CT * 64);    // [16][W1ROW]: theta weights (rows 0-7), phi weights (8-15)
+    double2 *E1 = (double2 *)(W1 + 16 * W1ROW);  // [64] e^{i psi} (1040 floats after 16-byte blocks: aligned)
+    float2 *UV = (float2 *)(E1 + 64);            // [64] (u - floor u, v - floor v)
+    float *Ys = (float *)(UV + 64);              // [64] y 2^(14 - e)
+    __shared__ int item_sh;
+    __shared__ float osc_sh;  // 2^(e - 28): undoes both scalings
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, grp = lane >> 4;
+    const int nitems = totals[1];
+    const float fbeta = (float)beta;
+    for (;;) {
+        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
+        __syncthreads();
+        const int it = item_sh;
+        if (it >= nitems) break;
+        const int4 item = items[it];
+        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
+        floatx4 acc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ch = 0; ch < item.z; ch += 64) {
+            const int ns = item.z - ch < 64 ? item.z - ch : 64;
+            if (tid < 64) {  // one wave: one sample per lane
+                double2 e1 = make_double2(1.0, 0.0);
+                float2 uv = make_float2(0.f, 0.f);
+                float yy = 0.f;
+                if (tid < ns) {
+                    const AdjRec q = rec[item.y + ch + tid];
+                    e1 = make_double2(q.cps, q.sps);
+                    uv = make_float2(q.fu, q.fv);
+                    yy = q.y;
+                }
+                float m = fabsf(yy);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+                int e = 0;
+                if (m > 0.f) (void)frexpf(m, &e);  // m < 2^e
+                E1[tid] = e1;
+                UV[tid] = uv;
+                Ys[tid] = ldexpf(yy, 14 - e);  // exact
+                if (tid == 0) osc_sh = ldexpf(1.f, e - 28);
+            }
+            __syncthreads();
+            for (int e = tid; e < 64 * 16; e += 256) {
+                const int q = e >> 6, sl = e & 63;
+                float w = 0.f;
+                if (sl < ns) {
+                    const float2 uv = UV[sl];
+                    w = es_w<float>(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                }
+                W1[q * W1ROW + sl] = w;
+            }
+            {
+                // V[s][c] = y_s basis_c(psi_s) (scaled), split and written in the B layout:
+                // sample s -> half s / 32, lane group (s % 32) / 8, element s % 8; component c ->
+                // tile c / 16, lane c % 16.  4 lanes per sample; lane qq takes the orders
+                // k = qq + 4 j (components 2k, 2k + 1: tile j / 2, lanes 2 qq + 8 (j % 2) and
+                // the next), so its offsets are compile-time after the base, and steps the
+                // phase by e^{4 i psi}.
+                const int sl = tid >> 2, qq = tid & 3;
+                const double2 e1 = E1[sl];
+                const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
+                double2 z = qq == 0 ? make_double2(1.0, 0.0) : qq == 1 ? e1 : qq == 2 ? e2 : cmul(e2, e1);
+                const float yy = Ys[sl];
+                const int base = ((sl >> 5) * CT * 64 + 16 * ((sl & 31) >> 3)) * 8 + (sl & 7) + 16 * qq;
+                _Float16 *bh = (_Float16 *)Bhi + base, *bl = (_Float16 *)Blo + base;
+#pragma unroll
+                for (int j = 0; j < 2 * CT; ++j) {
+                    const int k = qq + 4 * j;
+                    const float vc = 2 * k < ncomp ? yy * (float)z.x : 0.f;
+                    const float vs = 2 * k + 1 < ncomp ? yy * (float)z.y : 0.f;
+                    const int o = (j >> 1) * 512 + 64 * (j & 1);
+                    const _Float16 hc = (_Float16)vc, hs = (_Float16)vs;
+                    bh[o] = hc;
+                    bl[o] = (_Float16)(vc - (float)hc);
+                    bh[o + 8] = hs;
+                    bl[o + 8] = (_Float16)(vs - (float)hs);
+                    z = cmul(z, e4);
+                }
+            }
+            __syncthreads();
+            {
+                // A: wave wv's taps 16 wv + r, samples 32 kh + 8 grp + q
+                const int tap = 16 * wv + r;
+                const float *wth = W1 + (tap >> 3) * W1ROW + 8 * grp;
+                const float *wph = W1 + (8 + (tap & 7)) * W1ROW + 8 * grp;
+                half8 ah[2], al[2];
+#pragma unroll
+                for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const float w = wth[32 * kh + q] * wph[32 * kh + q] * 16384.f;
+                        const _Float16 h = (_Float16)w;
+                        ah[kh][q] = h;
+                        al[kh][q] = (_Float16)(w - (float)h);
+                    }
+                const float osc = osc_sh;
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    floatx4 t = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh) {
+                        const half8 bh = Bhi[(kh * CT + ct) * 64 + lane], bl = Blo[(kh * CT + ct) * 64 + lane];
+                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kh], bh, t, 0, 0, 0);
+                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bl, t, 0, 0, 0);
+                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bh, t, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[ct][v] = fmaf(t[v], osc, acc[ct][v]);
+                }
+            }
+            __syncthreads();
+        }
+        // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int t = 16 * wv + 4 * grp + v;
+            float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int c = 16 * ct + r;
+                if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+            }
+        }
+    }
+}
+
+template <int CT>
+hipError_t launch_scatter_split(sc_plan *p, void *gmaps) {
+    const size_t lds = SplitScatterLds<CT>::bytes;
+    auto kern = k_scatter_split<CT>;
+    hipError_t e = sc_set_lds_attr((const void *)kern, lds);
+    if (e != hipSuccess) return e;
+    const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
+    const BinGeom g = sc_bin_geom(p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
+                       (const AdjRec *)p->bw.sorted.rec, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
+    return hipGetLastError();
+}
+
 template <int CT>
 hipError_t launch_scatter_mfma(sc_plan *p, void *gmaps) {
     const size_t lds = ScatterLds<CT>::bytes;
@@ -228,6 +396,15 @@ hipError_t launch_scatter_mfma(sc_plan *p, void *gmaps) {
 
 hipError_t launch_scatter_mfma_any(sc_plan *p, void *gmaps) {
     const int ct = (p->ncomp + 15) / 16;
+    if (p->gather_mma == 1) {  // split FP16 products (the plan's product form, as for the gather)
+        if (ct <= 1) return launch_scatter_split<1>(p, gmaps);
+        if (ct <= 2) return launch_scatter_split<2>(p, gmaps);
+        if (ct <= 3) return launch_scatter_split<3>(p, gmaps);
+        if (ct <= 5) return launch_scatter_split<5>(p, gmaps);
+        if (ct <= 9) return launch_scatter_split<9>(p, gmaps);
+        if (ct <= 13) return launch_scatter_split<13>(p, gmaps);
+        return launch_scatter_split<16>(p, gmaps);
+    }
     if (ct <= 1) return launch_scatter_mfma<1>(p, gmaps);
     if (ct <= 2) return launch_scatter_mfma<2>(p, gmaps);
     if (ct <= 3) return launch_scatter_mfma<3>(p, gmaps);
