@@ -316,8 +316,17 @@ int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage
  *   SC_PARAM_GATHER_WAVES       waves per workgroup of the SC_MMA_FP32 gather, 4 or 8 (default 4);
  *                               the same 128-sample chunk split over more waves (the split
  *                               form always runs 4)
- *   SC_PARAM_GATHER_MMA         product form of the FP32 matrix-core gather (sc_gather_mma):
- *                               SC_MMA_SPLIT16 (default) or SC_MMA_FP32
+ *   SC_PARAM_GATHER_MMA         product form of the FP32 matrix-core gather and adjoint
+ *                               scatter (sc_gather_mma): SC_MMA_SPLIT16 (default) or SC_MMA_FP32
+ *   SC_PARAM_VALIDATE           0 (default) or 1.  With 1, sc_set_sky_beam, sc_interpolate,
+ *                               sc_interpolate_psi, sc_plan_convolve and the adjoints first count
+ *                               the NaN and infinite values of their floating-point inputs on the
+ *                               plan's stream and wait for the count (a host synchronisation);
+ *                               any such value returns SC_EINVAL naming the input, before
+ *                               anything is launched.  With 0 nothing is inspected: theta is
+ *                               clamped to [0, pi], phi and psi are reduced modulo 2 pi, and a
+ *                               NaN angle is read as 0.  sc_interpolate_noalloc does not
+ *                               validate (the check needs a device counter).
  */
 enum sc_param {
     SC_PARAM_BIN_CHUNK = 1,
@@ -325,7 +334,8 @@ enum sc_param {
     SC_PARAM_RING_RPT = 3,
     SC_PARAM_SKY_LMAX = 4,
     SC_PARAM_GATHER_WAVES = 5,
-    SC_PARAM_GATHER_MMA = 6
+    SC_PARAM_GATHER_MMA = 6,
+    SC_PARAM_VALIDATE = 7
 };
 
 /*

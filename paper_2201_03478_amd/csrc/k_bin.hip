@@ -259,6 +259,15 @@ __global__ void k_bin_items(const int *__restrict__ count, const int2 *__restric
     }
 }
 
+template <typename T>
+__global__ void k_count_nonfinite(const T *__restrict__ x, int64_t n, int *count) {
+    int c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += isfinite(x[i]) ? 0 : 1;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 __global__ void k_zero_words(uint4 *a, int64_t nw) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x)
         a[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -277,6 +286,18 @@ hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream) {
     if (nw > 0) hipLaunchKernelGGL(k_zero_words, dim3(2048), dim3(256), 0, stream, (uint4 *)dst, nw);
     const int64_t tail = (int64_t)(bytes - 16 * (size_t)nw);
     if (tail > 0) hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, stream, (unsigned char *)dst + 16 * nw, tail);
+    return hipGetLastError();
+}
+
+hipError_t sc_launch_count_nonfinite(const void *x, int64_t n, int f32, int *count, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (f32)
+        hipLaunchKernelGGL(k_count_nonfinite<float>, dim3((unsigned)nb), dim3(256), 0, stream, (const float *)x, n, count);
+    else
+        hipLaunchKernelGGL(k_count_nonfinite<double>, dim3((unsigned)nb), dim3(256), 0, stream, (const double *)x, n,
+                           count);
     return hipGetLastError();
 }
 

@@ -213,6 +213,7 @@ void free_plan_buffers(sc_plan *p) {
         p->cube = nullptr;
     }
     if (p->gmaps) (void)hipFree(p->gmaps);
+    if (p->vcount) (void)hipFree(p->vcount);
     if (p->GA) (void)hipFree(p->GA);
     if (p->GB) (void)hipFree(p->GB);
     p->GB = nullptr;
@@ -331,6 +332,33 @@ int sc_persistent_grid(const void *kern, int block, size_t lds, int wgs_per_cu) 
     if (ncu < 1) ncu = 256;
     c.grid[key] = per_cu * ncu;
     return per_cu * ncu;
+}
+
+// Validation mode (SC_PARAM_VALIDATE): count the NaN / infinite values of an input
+// on the plan's stream and wait for the count; SC_EINVAL names the input.  Off by
+// default: then nothing is inspected and a NaN angle is read as 0.
+static int validate_input(sc_plan *p, const char *what, const void *x, int64_t n, int f32) {
+    if (!p->validate || n <= 0) return SC_OK;
+    if (!p->vcount) {
+        size_t tot = 0;
+        const int rc = alloc((void **)&p->vcount, sizeof(int), &tot);
+        if (rc) return rc;
+    }
+    int count = 0;
+    hipError_t e = sc_launch_zero(p->vcount, sizeof(int), p->stream);
+    if (e == hipSuccess) e = sc_launch_count_nonfinite(x, n, f32, p->vcount, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, p->vcount, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "input validation");
+    if (count) return fail(SC_EINVAL, "%s holds %d NaN or infinite values (validation mode)", what, count);
+    return SC_OK;
+}
+
+static int64_t n_blm_values(const sc_plan *p) {  // doubles in the beam layout
+    return 2 * ((int64_t)(p->kmax + 1) * (p->lmax + 1) - (int64_t)p->kmax * (p->kmax + 1) / 2);
+}
+static int64_t n_alm_values(const sc_plan *p) {  // doubles in the sky layout
+    return (int64_t)(p->alm_lmax + 1) * (p->alm_lmax + 2);
 }
 
 int sc_psi_slack_bytes();  // k_psi.hip: zeroed bytes after the cube
@@ -512,6 +540,9 @@ int sc_set_sky_beam(sc_plan *p, const double *alm, const double *blm) {
     if (!is_device_ptr(alm)) return fail(SC_EINVAL, "alm is not device memory");
     if (!is_device_ptr(blm)) return fail(SC_EINVAL, "blm is not device memory");
     if (((uintptr_t)alm & 15) || ((uintptr_t)blm & 15)) return fail(SC_EINVAL, "alm/blm not 16-byte aligned");
+    int rc = validate_input(p, "alm", alm, n_alm_values(p), 0);
+    if (!rc) rc = validate_input(p, "blm", blm, n_blm_values(p), 0);
+    if (rc) return rc;
     int slot = timing_begin(p, SC_STAGE_RING);
     hipError_t e = p->prec == SC_MIXED ? sc_launch_ring_sums_mixed(p, alm, blm) : sc_launch_ring_sums(p, alm, blm);
     timing_end(p, slot);
@@ -593,6 +624,7 @@ int sc_interpolate(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     if (n == 0) return SC_OK;
     if (!p->have_maps) return fail(SC_ESTATE, "sc_interpolate before sc_set_sky_beam");
     int rc = check_interp_args(p, ptg, tod);
+    if (!rc) rc = validate_input(p, "ptg", ptg, 3 * n, 0);
     if (rc) return rc;
     if (!uses_binning(p)) {
         int slot = timing_begin(p, SC_STAGE_GATHER);
@@ -664,6 +696,7 @@ int sc_interpolate_psi(sc_plan *p, const double *ptg, int64_t n, void *tod) {
     if (n == 0) return SC_OK;
     if (!p->have_cube) return fail(SC_ESTATE, "sc_interpolate_psi without a cube of the current maps");
     int rc = check_interp_args(p, ptg, tod);
+    if (!rc) rc = validate_input(p, "ptg", ptg, 3 * n, 0);
     if (rc) return rc;
     if (p->prec == SC_FP64 || !uses_binning(p)) {
         const hipError_t e = sc_launch_gather_psi(p, ptg, n, tod);
@@ -692,6 +725,12 @@ int sc_plan_convolve(sc_plan *p, const double *alm, const double *blm, const dou
         return rc ? rc : sc_interpolate(p, ptg, n, tod);
     }
     int rc = check_interp_args(p, ptg, tod);
+    if (!rc && p->validate) {
+        if (!is_device_ptr(alm) || !is_device_ptr(blm)) return fail(SC_EINVAL, "alm/blm is not device memory");
+        rc = validate_input(p, "alm", alm, n_alm_values(p), 0);
+        if (!rc) rc = validate_input(p, "blm", blm, n_blm_values(p), 0);
+        if (!rc) rc = validate_input(p, "ptg", ptg, 3 * n, 0);
+    }
     if (rc) return rc;
     rc = ensure_bin_work(p, n < p->bin_pass_max ? n : p->bin_pass_max);
     if (rc) return rc;
@@ -849,6 +888,9 @@ int sc_convolve_adjoint(sc_plan *p, const double *blm, const double *ptg, const 
                         double *alm_grad) {
     g_msg[0] = 0;
     int rc = check_adjoint_args(p, blm, ptg, tod_grad, n, alm_grad);
+    if (!rc) rc = validate_input(p, "blm", blm, n_blm_values(p), 0);
+    if (!rc) rc = validate_input(p, "ptg", ptg, 3 * n, 0);
+    if (!rc) rc = validate_input(p, "tod_grad", tod_grad, n, p->prec != SC_FP64);
     if (rc) return rc;
     rc = adjoint_to_rings(p, ptg, tod_grad, n);
     if (rc) return rc;
@@ -863,6 +905,9 @@ int sc_convolve_adjoint_beam(sc_plan *p, const double *alm, const double *ptg, c
                              double *blm_grad) {
     g_msg[0] = 0;
     int rc = check_adjoint_args(p, alm, ptg, tod_grad, n, blm_grad);
+    if (!rc) rc = validate_input(p, "alm", alm, n_alm_values(p), 0);
+    if (!rc) rc = validate_input(p, "ptg", ptg, 3 * n, 0);
+    if (!rc) rc = validate_input(p, "tod_grad", tod_grad, n, p->prec != SC_FP64);
     if (rc) return rc;
     if (!p->GB) {
         const size_t nblm = (size_t)(p->kmax + 1) * (2 * p->lmax + 2 - p->kmax) / 2;
@@ -915,6 +960,10 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
             if (v < p->lmax || v > 65535) return fail(SC_EINVAL, "sky lmax %lld below the plan's lmax %d", (long long)v, p->lmax);
             p->alm_lmax = (int)v;
             return SC_OK;
+        case SC_PARAM_VALIDATE:
+            if (v != 0 && v != 1) return fail(SC_EINVAL, "validate %lld is not 0 or 1", (long long)v);
+            p->validate = (int)v;
+            return SC_OK;
         default:
             return fail(SC_EINVAL, "unknown parameter %d", param);
     }
@@ -929,6 +978,7 @@ int sc_plan_get_param(const sc_plan *p, int param, int64_t *v) {
         case SC_PARAM_GATHER_MMA: *v = p->gather_mma; return SC_OK;
         case SC_PARAM_RING_RPT: *v = p->prec == SC_MIXED ? p->rpt_mx : p->rpt; return SC_OK;
         case SC_PARAM_SKY_LMAX: *v = p->alm_lmax; return SC_OK;
+        case SC_PARAM_VALIDATE: *v = p->validate; return SC_OK;
         default: return fail(SC_EINVAL, "unknown parameter %d", param);
     }
 }

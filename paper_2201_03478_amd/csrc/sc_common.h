@@ -168,6 +168,8 @@ struct sc_plan {
     void *cube;        // twpsi, gpsi and cube: stream-ordered allocations like bw
     int have_cube;
     int timing;
+    int validate;  // SC_PARAM_VALIDATE: count non-finite inputs before launching (synchronous)
+    int *vcount;   // its device counter (allocated on first use)
     struct TimedLaunch *tl;  // pool of event pairs
     int tl_n, tl_cap;
 };
@@ -209,6 +211,8 @@ hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const voi
 hipError_t sc_launch_scatter_binned(sc_plan *p, void *gmaps);  // after sc_launch_binning with y
 bool sc_scatter_binned_supported(const sc_plan *p);
 hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
+// Adds to *count the number of NaN or infinite values among x[0 .. n) (double, or float with f32).
+hipError_t sc_launch_count_nonfinite(const void *x, int64_t n, int f32, int *count, hipStream_t stream);
 hipError_t sc_launch_gather(sc_plan *p, const double *ptg, int64_t n, void *tod);
 // Sort samples into anchor order (k_bin.hip).  With y (FP32 adjoint passes) the
 // records take the adjoint layout AdjRec instead of BinRec.

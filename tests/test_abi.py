@@ -59,3 +59,16 @@ def test_null_plan_calls(lib):
     assert lib.sc_plan_build_psi_cube(None, 0) == N.SC_EINVAL
     assert lib.sc_interpolate_psi(None, None, 0, None) == N.SC_EINVAL
     assert lib.sc_plan_info(None, None, 0) == N.SC_EINVAL
+
+
+def test_header_constants_match_binding():
+    """Every enum constant of include/sidelobe.h that the Python binding names has the
+    header's value (status codes, precisions, parameters, product forms)."""
+    from paper_2201_03478_amd import _native as N
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sidelobe.h")).read(), flags=re.S)
+    consts = dict((k, int(v)) for k, v in re.findall(r"\b(SC_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    assert len(consts) >= 15
+    named = [k for k in consts if hasattr(N, k)]
+    assert "SC_PARAM_VALIDATE" in named and "SC_EINVAL" in named
+    for k in named:
+        assert getattr(N, k) == consts[k], k

@@ -341,7 +341,7 @@ def test_adjoint_dot_product_and_finite_difference(oracle_lib):
             assert abs(fd - ref) < 1e-9 * max(1.0, abs(ref)), (idx, part)
 
 
-def test_P9_beam_gradient_dot_identity_and_difference(oracle_lib):
+def test_P12_beam_gradient_dot_identity_and_difference(oracle_lib):
     """The beam-gradient oracle is the transpose of the forward sum in b: sum_t y_t c_t(a, b) =
     Re sum conj(h_lk) b_lk (c is linear in b), and a finite difference in one b_lk agrees."""
     L, K, n = 10, 3, 30
@@ -363,3 +363,45 @@ def test_P9_beam_gradient_dot_identity_and_difference(oracle_lib):
             dlin = float(y @ (oracle_lib.convolve(a, b + e, L, K, p) - c))  # exact: c is linear in b
             ref = h[i].real if comp == 0 else h[i].imag
             assert abs(dlin - ref) < 1e-12 * max(1.0, abs(ref)), (l, k, comp)
+
+
+def test_P13_terms_below_2e600_are_negligible(oracle_lib):
+    """Reading of the extended-exponent recursion: a column's contributions are counted once
+    its values reach 2^-600, so the terms dropped are each below 2^-600 |a_lm b_lk|.  At
+    lmax 1300 on a ring at 22.6 degrees (where the columns m ~ 430-460 start far below that)
+    dropping every term with |d^l_mk| < 2^-600 from the direct sum of Eq. 2 changes c by
+    less than 1e-14 relative; the sum itself is checked against the oracle's convolution."""
+    L, K = 1300, 2
+    theta, phi, psi = math.radians(22.6), 0.7, 1.9
+    a = W.sky_alm(L, 6800)
+    b = W.beam_alm(L, K, 6801)
+    d = oracle_lib.wigner_d(L, K, theta)  # [k + K, m + L, l]
+    A = np.zeros((2 * L + 1, L + 1), complex)  # a_lm for -l <= m <= l (Eq. 6 for m < 0)
+    for m in range(L + 1):
+        i0 = m * (2 * L + 1 - m) // 2
+        v = a[i0 + np.arange(m, L + 1)]  # a_lm, l = m .. L (m-major layout: index m(2L+1-m)/2 + l)
+        col = np.zeros(L + 1, complex)
+        col[m:] = v.real if m == 0 else v
+        A[L + m] = col
+        if m:
+            A[L - m] = (-1) ** m * np.conj(col)
+    B = np.zeros((2 * K + 1, L + 1), complex)
+    for k in range(K + 1):
+        i0 = k * (2 * L + 1 - k) // 2
+        col = np.zeros(L + 1, complex)
+        col[k:] = b[i0 + np.arange(k, L + 1)]
+        if k == 0:
+            col = col.real.astype(complex)
+        B[K + k] = col
+        if k:
+            B[K - k] = (-1) ** k * np.conj(col)
+    ph = np.exp(1j * (np.arange(-L, L + 1)[None, :] * phi + np.arange(-K, K + 1)[:, None] * psi))
+    terms = A[None, :, :] * np.conj(B)[:, None, :] * d  # [k, m, l]
+    full = np.sum(ph * terms.sum(axis=2)).real
+    ref = oracle_lib.convolve(a, b, L, K, np.array([[theta, phi, psi]]))[0]
+    assert abs(full - ref) <= 1e-12 * abs(ref)
+    small = (np.abs(d) < 2.0 ** -600) & (np.abs(A)[None, :, :] > 0)
+    assert np.count_nonzero(small & (d != 0)) > 1000  # many such terms are present
+    dropped = np.sum(ph * np.where(small, 0.0, terms).sum(axis=2)).real
+    print("c %.15e, change from dropping |d| < 2^-600: %.3e relative" % (full, abs(dropped - full) / abs(full)))
+    assert abs(dropped - full) <= 1e-14 * abs(full)
