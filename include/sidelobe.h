@@ -327,6 +327,16 @@ int sc_plan_stage_times(sc_plan *plan, double *ms, int64_t *launches, int nstage
  *                               clamped to [0, pi], phi and psi are reduced modulo 2 pi, and a
  *                               NaN angle is read as 0.  sc_interpolate_noalloc does not
  *                               validate (the check needs a device counter).
+ *   SC_PARAM_DETERMINISTIC      0 (default) or 1 (FP32-map plans with W = 8 only; SC_EINVAL
+ *                               otherwise).  With 1 the adjoints' scatter uses no atomics: each
+ *                               work item writes its 8 x 8 patch gradient to plan workspace
+ *                               (64 x 16 ceil(ncomp/16) floats per item, allocated on first
+ *                               use and kept), and every map pixel sums the patches that
+ *                               cover it in a fixed order, so the gradients are bit-identical
+ *                               from run to run.  It reads back the work-item count of each
+ *                               binning pass (a host synchronisation).  With 0 the patches are
+ *                               added with FP32 atomics (run-to-run differences at the FP32
+ *                               rounding level).
  */
 enum sc_param {
     SC_PARAM_BIN_CHUNK = 1,
@@ -335,7 +345,8 @@ enum sc_param {
     SC_PARAM_SKY_LMAX = 4,
     SC_PARAM_GATHER_WAVES = 5,
     SC_PARAM_GATHER_MMA = 6,
-    SC_PARAM_VALIDATE = 7
+    SC_PARAM_VALIDATE = 7,
+    SC_PARAM_DETERMINISTIC = 8
 };
 
 /*

@@ -19,6 +19,7 @@ SC_FP64, SC_F64MAPS_F32GATHER, SC_MIXED = 0, 1, 2
 SC_PARAM_BIN_CHUNK, SC_PARAM_GATHER_WGS_PER_CU, SC_PARAM_RING_RPT, SC_PARAM_SKY_LMAX, SC_PARAM_GATHER_WAVES = 1, 2, 3, 4, 5
 SC_PARAM_GATHER_MMA = 6
 SC_PARAM_VALIDATE = 7
+SC_PARAM_DETERMINISTIC = 8
 SC_MMA_FP32, SC_MMA_SPLIT16 = 0, 1
 
 EXPORTS = (

@@ -106,10 +106,11 @@ struct ScatterLds {
 
 // Work items come from the binning's queue; each chunk's samples (AdjRec, written
 // by the binning with e^{i psi} and the TOD gradient) are staged by one thread each.
-template <int CT>
+template <int CT, bool DET>
 __global__ void __launch_bounds__(256)
 k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const AdjRec *__restrict__ rec,
-               float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
+               const int *__restrict__ perm, float *__restrict__ gmaps, float *__restrict__ pg, int cols, int ncp,
+               int ncomp, int nkc, double beta) {
     constexpr int NC = 16 * CT;
     extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     float *Vsh = (float *)smem_d;                // [64 samples][NC]
@@ -141,7 +142,8 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
                 float2 uv = make_float2(0.f, 0.f);
                 float yy = 0.f;
                 if (tid < ns) {
-                    const AdjRec q = rec[item.y + ch + tid];
+                    const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
+                    const AdjRec q = rec[pos];
                     e1 = make_double2(q.cps, q.sps);
                     uv = make_float2(q.fu, q.fv);
                     yy = q.y;
@@ -203,11 +205,18 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int t = 16 * wv + 4 * grp + v;
-            float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+            if constexpr (DET) {
+                // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
+                float *dst = pg + ((size_t)it * 64 + t) * NC;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const int c = 16 * ct + r;
-                if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
+            } else {
+                float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const int c = 16 * ct + r;
+                    if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                }
             }
         }
     }
@@ -231,10 +240,11 @@ struct SplitScatterLds {
                                     64 * (sizeof(double2) + sizeof(float2) + sizeof(float));
 };
 
-template <int CT>
+template <int CT, bool DET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT <= 5 ? 5 : 3)))
 k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const AdjRec *__restrict__ rec,
-                float *__restrict__ gmaps, int cols, int ncp, int ncomp, int nkc, double beta) {
+                const int *__restrict__ perm, float *__restrict__ gmaps, float *__restrict__ pg, int cols, int ncp,
+                int ncomp, int nkc, double beta) {
     constexpr int NC = 16 * CT;
     extern __shared__ __attribute__((aligned(16))) double smem_d[];
     half8 *Bhi = (half8 *)smem_d;                // [2 sample halves][CT][64 lanes]
@@ -268,7 +278,8 @@ k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const 
                 float2 uv = make_float2(0.f, 0.f);
                 float yy = 0.f;
                 if (tid < ns) {
-                    const AdjRec q = rec[item.y + ch + tid];
+                    const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
+                    const AdjRec q = rec[pos];
                     e1 = make_double2(q.cps, q.sps);
                     uv = make_float2(q.fu, q.fv);
                     yy = q.y;
@@ -358,39 +369,158 @@ k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int t = 16 * wv + 4 * grp + v;
-            float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+            if constexpr (DET) {
+                // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
+                float *dst = pg + ((size_t)it * 64 + t) * NC;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const int c = 16 * ct + r;
-                if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
+            } else {
+                float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const int c = 16 * ct + r;
+                    if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                }
             }
         }
+    }
+}
+
+// Deterministic mode, sample order.  The binning ranks the samples of an anchor in
+// the order its atomics happen to run, so the same samples can land in different
+// 64-sample chunks from run to run.  In this mode every anchor is one work item and
+// this kernel sorts the item's samples by their index (a bitonic sort of (index,
+// position) pairs in LDS, one workgroup per item of at most DET_MAXN samples), writing
+// perm[first + i] = the sorted position of the i-th sample in index order; the scatter
+// reads its records through perm.  It also records the largest item (totals[3]).
+constexpr int DET_MAXN = 8192;
+
+__global__ void __launch_bounds__(256)
+k_det_order(const int4 *__restrict__ items, const int *__restrict__ totals, const AdjRec *__restrict__ rec,
+            int *__restrict__ perm, int *__restrict__ maxn) {
+    __shared__ unsigned key[DET_MAXN], val[DET_MAXN];
+    const int it = blockIdx.x;
+    if (it >= totals[1]) return;
+    const int4 item = items[it];
+    const int n = item.z, tid = threadIdx.x;
+    if (tid == 0) atomicMax(maxn, n);
+    if (n > DET_MAXN) return;  // the host splits the pass and bins again
+    int np = 64;
+    while (np < n) np <<= 1;
+    for (int i = tid; i < np; i += 256) {
+        key[i] = i < n ? (unsigned)rec[item.y + i].idx : 0xffffffffu;
+        val[i] = (unsigned)(item.y + i);
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < np; i += 256) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const unsigned a = key[i], b = key[l];
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[l] = a;
+                        const unsigned t = val[i];
+                        val[i] = val[l];
+                        val[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < n; i += 256) perm[item.y + i] = (int)val[i];
+}
+
+// Deterministic mode: gmaps[R][C] += sum over the anchors (R - i, C - j), i, j < 8, in that
+// order, and over each anchor's items in order, of the items' patch gradients at tap
+// (i, j).  One workgroup per 8 x 8 pixel tile; the item ranges of the tile's 15 x 15
+// anchors go to LDS first (an anchor's items are consecutive: ceil(count / chunk) of
+// them from offs[key].y).  Thread (pixel, part) sums CT float4s of its pixel (the map
+// record holds ncp <= 16 CT floats; the patch gradients 16 CT).
+template <int CT>
+__global__ void __launch_bounds__(256)
+k_scatter_reduce(const float4 *__restrict__ pg, const int *__restrict__ count, const int2 *__restrict__ offs,
+                 float *__restrict__ gmaps, int rows, int cols, int ncp, int nkr, int nkc, int chunk) {
+    constexpr int NC4 = 4 * CT;  // float4s per tap
+    __shared__ int2 rng[15 * 15];
+    const int tiles_c = (cols + 7) / 8;
+    const int R0 = 8 * (blockIdx.x / tiles_c), C0 = 8 * (blockIdx.x - (blockIdx.x / tiles_c) * tiles_c);
+    const int tid = threadIdx.x;
+    if (tid < 225) {
+        const int ar = R0 - 7 + tid / 15, ac = C0 - 7 + tid % 15;
+        int2 v = make_int2(0, 0);
+        if (ar >= 0 && ar < nkr && ac >= 0 && ac < nkc) {
+            const int64_t k = (int64_t)ar * nkc + ac;
+            const int c = count[k];
+            if (c > 0) v = make_int2(offs[k].y, (c + chunk - 1) / chunk);
+        }
+        rng[tid] = v;
+    }
+    __syncthreads();
+    const int pix = tid >> 2, part = tid & 3;
+    const int pr = pix >> 3, pc = pix & 7;
+    const int R = R0 + pr, C = C0 + pc;
+    if (R >= rows || C >= cols) return;
+    float4 acc[CT];
+#pragma unroll
+    for (int q = 0; q < CT; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) {
+            const int2 g = rng[(pr + 7 - i) * 15 + (pc + 7 - j)];
+            for (int it = g.x; it < g.x + g.y; ++it) {
+                const float4 *src = pg + ((size_t)it * 64 + 8 * i + j) * NC4 + part * CT;
+#pragma unroll
+                for (int q = 0; q < CT; ++q) {
+                    const float4 v = src[q];
+                    acc[q].x += v.x;
+                    acc[q].y += v.y;
+                    acc[q].z += v.z;
+                    acc[q].w += v.w;
+                }
+            }
+        }
+    float4 *dst = (float4 *)(gmaps + ((size_t)R * cols + C) * ncp) + part * CT;
+#pragma unroll
+    for (int q = 0; q < CT; ++q) {
+        if (4 * (part * CT + q) >= ncp) break;  // CT may round the map's tile count up
+        float4 o = dst[q];
+        o.x += acc[q].x;
+        o.y += acc[q].y;
+        o.z += acc[q].z;
+        o.w += acc[q].w;
+        dst[q] = o;
     }
 }
 
 template <int CT>
 hipError_t launch_scatter_split(sc_plan *p, void *gmaps) {
     const size_t lds = SplitScatterLds<CT>::bytes;
-    auto kern = k_scatter_split<CT>;
+    auto kern = p->det_adjoint ? k_scatter_split<CT, true> : k_scatter_split<CT, false>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
     const BinGeom g = sc_bin_geom(p);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
-                       (const AdjRec *)p->bw.sorted.rec, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
+                       (const AdjRec *)p->bw.sorted.rec, p->bw.key, (float *)gmaps, p->pg, p->cols, p->ncp, p->ncomp,
+                       g.nkc,
+                       p->beta);
     return hipGetLastError();
 }
 
 template <int CT>
 hipError_t launch_scatter_mfma(sc_plan *p, void *gmaps) {
     const size_t lds = ScatterLds<CT>::bytes;
-    auto kern = k_scatter_mfma<CT>;
+    auto kern = p->det_adjoint ? k_scatter_mfma<CT, true> : k_scatter_mfma<CT, false>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int grid = sc_persistent_grid((const void *)kern, 256, lds, p->gather_wgs_per_cu);
     const BinGeom g = sc_bin_geom(p);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, p->stream, p->bw.items, p->bw.totals,
-                       (const AdjRec *)p->bw.sorted.rec, (float *)gmaps, p->cols, p->ncp, p->ncomp, g.nkc, p->beta);
+                       (const AdjRec *)p->bw.sorted.rec, p->bw.key, (float *)gmaps, p->pg, p->cols, p->ncp, p->ncomp,
+                       g.nkc,
+                       p->beta);
     return hipGetLastError();
 }
 
@@ -414,10 +544,43 @@ hipError_t launch_scatter_mfma_any(sc_plan *p, void *gmaps) {
     return launch_scatter_mfma<16>(p, gmaps);
 }
 
+template <int CT>
+hipError_t launch_reduce(sc_plan *p, void *gmaps) {
+    const BinGeom g = sc_bin_geom(p);
+    const int tiles = ((p->rows + 7) / 8) * ((p->cols + 7) / 8);
+    hipLaunchKernelGGL(k_scatter_reduce<CT>, dim3(tiles), dim3(256), 0, p->stream, (const float4 *)p->pg,
+                       p->bw.count, p->bw.offs, (float *)gmaps, p->rows, p->cols, p->ncp, g.nkr, g.nkc, p->bin_chunk);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool sc_scatter_binned_supported(const sc_plan *p) {
     return p->prec != SC_FP64 && p->W == 8 && p->ncomp <= 256 && !p->gather_direct;
+}
+
+// Deterministic mode, after the binning (one item per anchor): the sample order of
+// every item into the binning's key buffer (free after the binning), and the largest
+// item into totals[3] (to be read back: above DET_MAXN the pass must be split).
+hipError_t sc_launch_det_order(sc_plan *p, int nitems) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_order, dim3((unsigned)nitems), dim3(256), 0, p->stream, p->bw.items, p->bw.totals,
+                       (const AdjRec *)p->bw.sorted.rec, p->bw.key, p->bw.totals + 3);
+    return hipGetLastError();
+}
+int sc_det_max_items() { return DET_MAXN; }
+
+// Deterministic mode, after the scatter of a pass has written its patch gradients (the
+// reduction's tile count must match the scatter's: the same (ncomp + 15) / 16 rounding).
+hipError_t sc_launch_scatter_reduce(sc_plan *p, void *gmaps) {
+    const int ct = (p->ncomp + 15) / 16;
+    if (ct <= 1) return launch_reduce<1>(p, gmaps);
+    if (ct <= 2) return launch_reduce<2>(p, gmaps);
+    if (ct <= 3) return launch_reduce<3>(p, gmaps);
+    if (ct <= 5) return launch_reduce<5>(p, gmaps);
+    if (ct <= 9) return launch_reduce<9>(p, gmaps);
+    if (ct <= 13) return launch_reduce<13>(p, gmaps);
+    return launch_reduce<16>(p, gmaps);
 }
 
 // Scatter of one pass (binned: binning with the pass's TOD gradient already done).

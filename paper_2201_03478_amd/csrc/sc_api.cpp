@@ -214,6 +214,7 @@ void free_plan_buffers(sc_plan *p) {
     }
     if (p->gmaps) (void)hipFree(p->gmaps);
     if (p->vcount) (void)hipFree(p->vcount);
+    if (p->pg) (void)hipFreeAsync(p->pg, p->stream);
     if (p->GA) (void)hipFree(p->GA);
     if (p->GB) (void)hipFree(p->GB);
     p->GB = nullptr;
@@ -816,6 +817,14 @@ int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg,
     return e != hipSuccess ? hip_fail(e, "dipole launch") : SC_OK;
 }
 
+// Component tiles of the scatter kernels' instantiation (the tile count rounded up to
+// 1, 2, 3, 5, 9, 13 or 16): the patch gradients of the deterministic mode hold 16 of
+// them per tile.
+static int scatter_tiles(const sc_plan *p) {
+    const int ct = (p->ncomp + 15) / 16;
+    return ct <= 3 ? ct : ct <= 5 ? 5 : ct <= 9 ? 9 : ct <= 13 ? 13 : 16;
+}
+
 // The part of the adjoint that depends on neither coefficient set: scatter of the
 // TOD gradient onto gradient maps, then the adjoint phi and theta transforms
 // (ring-sum gradients in p->F).
@@ -843,17 +852,59 @@ static int adjoint_to_rings(sc_plan *p, const double *ptg, const void *tod_grad,
             const int64_t pass = n < p->bin_pass_max ? n : p->bin_pass_max;
             int rc = ensure_bin_work(p, pass);
             if (rc) return rc;
-            for (int64_t off = 0; off < n; off += pass) {
-                const int64_t cnt = n - off < pass ? n - off : pass;
+            // The deterministic mode bins every anchor into one work item (restored below)
+            // and orders its samples by index; a pass whose largest anchor exceeds what
+            // the ordering kernel holds is binned again in smaller passes.
+            struct ChunkGuard {
+                sc_plan *p;
+                int saved;
+                ~ChunkGuard() { p->bin_chunk = saved; }
+            } guard{p, p->bin_chunk};
+            if (p->det_adjoint) p->bin_chunk = 1 << 30;
+            int64_t cur = pass;
+            for (int64_t off = 0; off < n;) {
+                const int64_t cnt = n - off < cur ? n - off : cur;
                 slot = timing_begin(p, SC_STAGE_BIN);
                 // the records carry the pass's TOD gradient (binned scatter: FP32 forms only)
                 e = sc_launch_binning(p, ptg + 3 * off, cnt, (const float *)tod_grad + off);
                 timing_end(p, slot);
                 if (e != hipSuccess) return hip_fail(e, "binning launch");
+                if (p->det_adjoint) {
+                    // work-item count and largest item are read back (the mode waits for the binning)
+                    int nitems = 0, maxn = 0;
+                    e = hipMemcpyAsync(&nitems, p->bw.totals + 1, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+                    if (e == hipSuccess) e = sc_launch_zero(p->bw.totals + 3, sizeof(int), p->stream);
+                    if (e == hipSuccess) e = sc_launch_det_order(p, nitems);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(&maxn, p->bw.totals + 3, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+                    if (e != hipSuccess) return hip_fail(e, "deterministic ordering");
+                    if (maxn > sc_det_max_items()) {
+                        // a pass of at most that many samples always fits; shrink and bin again
+                        const int64_t next = cnt * sc_det_max_items() / (2 * (int64_t)maxn);
+                        cur = next > 0 ? next : 1;
+                        continue;
+                    }
+                    const size_t need = sizeof(float) * (size_t)nitems * 64 * 16 * (size_t)scatter_tiles(p);
+                    if (need > p->pg_bytes) {
+                        if (p->pg) (void)hipFreeAsync(p->pg, p->stream);
+                        p->pg = nullptr;
+                        p->ws_bytes -= p->pg_bytes;
+                        p->pg_bytes = 0;
+                        size_t tot = 0;
+                        const int rc2 = alloc_async((void **)&p->pg, need, &tot, p->stream);
+                        if (rc2) return rc2;
+                        p->ws_bytes += need;
+                        p->pg_bytes = need;
+                    }
+                }
                 slot = timing_begin(p, SC_STAGE_SCATTER);
                 e = sc_launch_scatter_binned(p, p->gmaps);
+                if (e == hipSuccess && p->det_adjoint) e = sc_launch_scatter_reduce(p, p->gmaps);
                 timing_end(p, slot);
                 if (e != hipSuccess) return hip_fail(e, "binned scatter launch");
+                off += cnt;
             }
         } else {
             slot = timing_begin(p, SC_STAGE_SCATTER);
@@ -964,6 +1015,12 @@ int sc_plan_set_param(sc_plan *p, int param, int64_t v) {
             if (v != 0 && v != 1) return fail(SC_EINVAL, "validate %lld is not 0 or 1", (long long)v);
             p->validate = (int)v;
             return SC_OK;
+        case SC_PARAM_DETERMINISTIC:
+            if (v != 0 && v != 1) return fail(SC_EINVAL, "deterministic %lld is not 0 or 1", (long long)v);
+            if (v && !sc_scatter_binned_supported(p))
+                return fail(SC_EINVAL, "the deterministic adjoint needs the binned FP32 scatter (W = 8, FP32 maps)");
+            p->det_adjoint = (int)v;
+            return SC_OK;
         default:
             return fail(SC_EINVAL, "unknown parameter %d", param);
     }
@@ -979,6 +1036,7 @@ int sc_plan_get_param(const sc_plan *p, int param, int64_t *v) {
         case SC_PARAM_RING_RPT: *v = p->prec == SC_MIXED ? p->rpt_mx : p->rpt; return SC_OK;
         case SC_PARAM_SKY_LMAX: *v = p->alm_lmax; return SC_OK;
         case SC_PARAM_VALIDATE: *v = p->validate; return SC_OK;
+        case SC_PARAM_DETERMINISTIC: *v = p->det_adjoint; return SC_OK;
         default: return fail(SC_EINVAL, "unknown parameter %d", param);
     }
 }

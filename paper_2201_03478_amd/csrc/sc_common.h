@@ -169,6 +169,9 @@ struct sc_plan {
     int have_cube;
     int timing;
     int validate;  // SC_PARAM_VALIDATE: count non-finite inputs before launching (synchronous)
+    int det_adjoint;   // SC_PARAM_DETERMINISTIC: atomic-free scatter (patch gradients, fixed-order sums)
+    float *pg;         // its patch gradients [items][64 taps][16 CT]
+    size_t pg_bytes;
     int *vcount;   // its device counter (allocated on first use)
     struct TimedLaunch *tl;  // pool of event pairs
     int tl_n, tl_cap;
@@ -209,6 +212,9 @@ int sc_adjoint_slabs(const sc_plan *p);  // ring slabs per column of the adjoint
 hipError_t sc_launch_ring_sums_adjoint_beam(sc_plan *p, const double *alm, double *grad);
 hipError_t sc_launch_scatter(sc_plan *p, const double *ptg, int64_t n, const void *y, void *gmaps);
 hipError_t sc_launch_scatter_binned(sc_plan *p, void *gmaps);  // after sc_launch_binning with y
+hipError_t sc_launch_scatter_reduce(sc_plan *p, void *gmaps);  // deterministic mode, after the scatter
+hipError_t sc_launch_det_order(sc_plan *p, int nitems);         // deterministic mode, after the binning
+int sc_det_max_items();                                         // largest anchor it orders
 bool sc_scatter_binned_supported(const sc_plan *p);
 hipError_t sc_launch_zero(void *dst, size_t bytes, hipStream_t stream);
 // Adds to *count the number of NaN or infinite values among x[0 .. n) (double, or float with f32).

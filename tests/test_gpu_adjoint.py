@@ -220,3 +220,63 @@ def test_scatter_product_forms_agree(env):
     mx = float(np.max(np.abs(out[1] - out[0])) / np.max(np.abs(out[0])))
     print("split vs FP32 scatter: rel-L2 %.3e, max %.3e" % (err, mx))
     assert err <= 2e-6 and mx <= 2e-5
+
+
+def _det_inputs(torch, dev, L, K):
+    p = np.concatenate([W.scan_pointings(50000, t0=80.0), W.uniform_pointings(10000, 4501)])
+    y = np.random.default_rng(4502).standard_normal(p.shape[0])
+    return _to(torch, dev, W.beam_alm(L, K, 4503)), _to(torch, dev, W.sky_alm(L, 4504)), _to(torch, dev, p), \
+        _to(torch, dev, y).float()
+
+
+@pytest.mark.parametrize("form", [1, 0])
+def test_deterministic_adjoint_is_repeatable(env, form):
+    """SC_PARAM_DETERMINISTIC: no atomics, fixed summation order.  Two runs, and a run with a
+    different number of scatter workgroups, give bit-identical gradients (sky and beam);
+    against the atomic mode they agree to FP32 rounding."""
+    torch, api, dev = env
+    L, K = 64, 20
+    b, a, pt, yt = _det_inputs(torch, dev, L, K)
+
+    def run(det, wgs=0):
+        plan = api.Plan(L, K, "f64maps_f32gather")
+        plan.set_param("gather_mma", form)
+        plan.set_param("deterministic", det)
+        plan.set_param("gather_wgs_per_cu", wgs)
+        g = plan.adjoint(b, pt, yt).cpu().numpy()
+        h = plan.adjoint_beam(a, pt, yt).cpu().numpy()
+        return g, h
+
+    g1, h1 = run(1)
+    g2, h2 = run(1)
+    g3, h3 = run(1, wgs=1)
+    assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
+    assert np.array_equal(h1, h2) and np.array_equal(h1, h3)
+    ga, ha = run(0)
+    print("deterministic vs atomic: %.3e (sky), %.3e (beam)" % (_rel(g1, ga), _rel(h1, ha)))
+    assert _rel(g1, ga) <= 1e-6 and _rel(h1, ha) <= 1e-6
+
+
+def test_deterministic_adjoint_in_several_passes(env, monkeypatch):
+    """Binning passes of 20000 samples (the plan reads SC_BIN_PASS_MAX when created): each
+    pass's patches are summed into the maps in pass order, still repeatable."""
+    torch, api, dev = env
+    L, K = 48, 9
+    b, a, pt, yt = _det_inputs(torch, dev, L, K)
+    monkeypatch.setenv("SC_BIN_PASS_MAX", "20000")
+    outs = []
+    for _ in range(2):
+        plan = api.Plan(L, K, "f64maps_f32gather")
+        plan.set_param("deterministic", 1)
+        outs.append(plan.adjoint(b, pt, yt).cpu().numpy())
+    monkeypatch.delenv("SC_BIN_PASS_MAX")
+    ref = api.Plan(L, K, "f64maps_f32gather").adjoint(b, pt, yt).cpu().numpy()
+    assert np.array_equal(outs[0], outs[1])
+    assert _rel(outs[0], ref) <= 1e-6
+
+
+def test_deterministic_mode_needs_the_binned_scatter(env):
+    torch, api, dev = env
+    plan = api.Plan(16, 2, "fp64")
+    with pytest.raises(api.N.ScError, match="deterministic adjoint"):
+        plan.set_param("deterministic", 1)
