@@ -78,7 +78,30 @@ def stage_model(info: dict, n: int, prec: int, mma: int = 1):
                    ("mfma", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["split"] if mma == 1 else PEAK["fp32"])),
         # pointings read twice (keys, scatter), key + rank written and read, sorted record written
         "binning": ("hbm", n * (2 * 24.0 + 2 * 8.0 + 28.0), "GB/s", PEAK["hbm"]),
+        # adjoint: the transpose of the gather (same products), of the transforms (map
+        # gradients read, complex128 G written and read, F written) and of the ring sums
+        "scatter": (("alu", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["fp64"]) if prec == 0 else
+                    ("mfma", 2.0 * nc * Wd * Wd * n, "TFLOP/s", PEAK["split"] if mma == 1 else PEAK["fp32"])),
+        "adjoint_transforms": ("hbm", esz * rows * cols * nc + 16.0 * (K + 1) * nm * (2 * rows + nr), "GB/s",
+                               PEAK["hbm"]),
+        "adjoint_ring_sums": ("alu", 12.0 * dv, "TFLOP/s", PEAK["fp64"]),
     }
+
+
+def rooflines(model: dict, per_launch: dict, overlapped=()) -> dict:
+    """Achieved vs peak per stage from its algorithmic work per launch and launch time (ms)."""
+    out = {}
+    for s_, t_ in per_launch.items():
+        if not t_ or s_ not in model:
+            continue
+        b_, u_, un_, pk_ = model[s_]
+        a_ = u_ / (t_ * 1e-3)
+        sc_ = 1e12 if un_ == "TFLOP/s" else 1e9
+        out[s_] = {"bound": b_, "achieved": a_ / sc_, "peak": pk_ / sc_, "unit": un_, "frac": a_ / pk_,
+                   "avg_launch_ms": t_}
+        if s_ in overlapped:
+            out[s_]["overlapped"] = "side stream, concurrent with the map synthesis (span includes waits)"
+    return out
 
 
 def kernel_source_hash(stage: str) -> str:
@@ -213,17 +236,7 @@ def main():
         "algorithmic_per_launch": units,
     }
 
-    stage_roofline = {}
-    for s_, t_ in per_launch.items():
-        if not t_ or s_ not in model:
-            continue
-        b_, u_, un_, pk_ = model[s_]
-        a_ = u_ / (t_ * 1e-3)
-        sc_ = 1e12 if un_ == "TFLOP/s" else 1e9
-        stage_roofline[s_] = {"bound": b_, "achieved": a_ / sc_, "peak": pk_ / sc_, "unit": un_, "frac": a_ / pk_,
-                              "avg_launch_ms": t_}
-        if s_ in OVERLAPPED:
-            stage_roofline[s_]["overlapped"] = "side stream, concurrent with the map synthesis (span includes waits)"
+    stage_roofline = rooflines(model, per_launch, OVERLAPPED)
 
     result = {
         "metric": METRIC,
@@ -380,6 +393,10 @@ def extra_precision(torch, api, W, dev, no_oracle):
         plan, tod, ms, stages = run_form(torch, api, dev, a, b, ptg, L, K, prec, 8, 3, 1)
         rec = {"ms_per_step": ms, "value": n / (ms * 1e-3),
                "stages_ms_per_step": {k: t / 3 for k, (t, c) in stages.items() if c}}
+        # the mixed form's ring sums are priced at the FP64 form's 12 flop per d value
+        inf = plan.info()
+        rec["stage_roofline"] = rooflines(stage_model(inf, n, inf["precision"], plan.get_param("gather_mma")),
+                                          {k: t / c for k, (t, c) in stages.items() if c}, ("binning",))
         if not no_oracle:
             rec["rel_err_vs_oracle"] = _oracle_err(W, torch, dev, a_np, b_np, L, K, ptg, tod, 8, W.config_seed(3, 6))
         out[prec] = rec
@@ -420,9 +437,13 @@ def extra_adjoint(torch, api, W, dev, no_oracle):
     b_real0 = b.clone()
     b_real0[:L + 1] = b_real0[:L + 1].real.to(b.dtype)
     rhs_b = float(torch.sum(torch.conj(bgrad) * b_real0).real)
+    inf = plan.info()
+    adj_roof = rooflines(stage_model(inf, n, inf["precision"], plan.get_param("gather_mma")),
+                         {k: t / c for k, (t, c) in st.items() if c})
     return {"workload": "adjoint-lmax512-kmax32-scan1e8", "n_samples": n,
             "forward_ms": fms, "adjoint_ms": ams, "adjoint_value": n / (ams * 1e-3),
             "adjoint_stages_ms": {k: t / 4 for k, (t, c) in st.items() if c},
+            "adjoint_stage_roofline": adj_roof,
             "dot_test_rel": abs(lhs - rhs) / abs(lhs),
             "beam_adjoint_ms": bms, "beam_dot_test_rel": abs(lhs - rhs_b) / abs(lhs)}
 
@@ -537,22 +558,45 @@ def extra_batched(torch, api, W, dev, no_oracle):
     chosen = autotune.tune_batch(bt, sky, reps=2)
     eager = _event_ms(torch, lambda: bt.run(sky, use_graph=False), 3)
     graph = _event_ms(torch, lambda: bt.run(sky, use_graph=True), 3)
-    # per-stage kernel time of one eager pass, summed over the detectors (the synthesis
-    # chains overlap, so the sum can exceed the pass's wall time)
+    # Per-stage kernel time of one eager pass with one synthesis chain (the launches run
+    # one after another, so each launch's time is its own), summed over the detectors,
+    # with the rooflines of those sums; and the same pass with the four chains.
     views = [bt.plan(d) for d in range(len(dets))]
-    for v in views:
-        v.enable_timing(True)
-    bt.run(sky, use_graph=False)
-    torch.cuda.synchronize()
-    stage_ms = {}
-    for v in views:
-        for name, (ms, cnt) in v.stage_times().items():
-            if cnt:
-                stage_ms[name] = stage_ms.get(name, 0.0) + ms
-        v.enable_timing(False)
+
+    def stage_sums():
+        for v in views:
+            v.enable_timing(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        bt.run(sky, use_graph=False)
+        t1.record()
+        torch.cuda.synchronize()
+        sums = {}
+        for v in views:
+            for name, (ms_, cnt) in v.stage_times().items():
+                if cnt:
+                    sums[name] = sums.get(name, 0.0) + ms_
+            v.enable_timing(False)
+        return sums, t0.elapsed_time(t1)
+
+    bt.set_param("batch_chains", 1)
+    serial, serial_ms = stage_sums()
+    bt.set_param("batch_chains", 4)
+    chained, chained_ms = stage_sums()
+    units = {}
+    for d, v in enumerate(views):
+        inf = v.info()
+        for name, (b_, u_, un_, pk_) in stage_model(inf, dets[d]["ptg"].shape[0], inf["precision"]).items():
+            units[name] = (b_, units.get(name, (b_, 0.0))[1] + u_, un_, pk_)
+    units["gather"] = units["gather"][:3] + (PEAK["split"],)
+    batch_roof = rooflines(units, serial)
     out = {"workload": "batched-12det-scan4e7", "n_samples": ntot, "ms_per_step_graph": graph,
            "value": ntot / (graph * 1e-3), "ms_per_step_eager": eager, "ms_per_step_eager_untuned": eager_default,
-           "synthesis_chains": 4, "stage_kernel_ms_sum": {k: round(v, 3) for k, v in stage_ms.items()},
+           "synthesis_chains": 4, "eager_pass_ms_one_chain": serial_ms, "eager_pass_ms_four_chains": chained_ms,
+           "stage_kernel_ms_one_chain": {k: round(v, 3) for k, v in serial.items()},
+           "stage_kernel_ms_four_chains": {k: round(v, 3) for k, v in chained.items()},
+           "stage_roofline_one_chain": batch_roof,
            "tuned": [dict(det=i, lmax=d["lmax"], kmax=d["kmax"], **c) for i, (d, c) in enumerate(zip(bt.dets, chosen))]}
     bt.close()
     return out

@@ -346,7 +346,8 @@ enum sc_param {
     SC_PARAM_GATHER_WAVES = 5,
     SC_PARAM_GATHER_MMA = 6,
     SC_PARAM_VALIDATE = 7,
-    SC_PARAM_DETERMINISTIC = 8
+    SC_PARAM_DETERMINISTIC = 8,
+    SC_PARAM_BATCH_CHAINS = 9
 };
 
 /*
@@ -400,7 +401,11 @@ int sc_batch_create(sc_batch **batch, const sc_det_desc *dets, int ndet, int lma
 int sc_batch_run(sc_batch *batch, const double *alm_sky, int use_graph);
 
 /* Tunables: det = -1 applies to every detector.  SC_PARAM_GATHER_WGS_PER_CU is
-   batch-wide (the single gather launch). */
+   batch-wide (the single gather launch), and so is SC_PARAM_BATCH_CHAINS: the
+   detectors' map synthesis and binning run as that many independent chains (1 .. 4,
+   default 4; chain 0 on the batch's stream, the others on side streams at default
+   priority forked from it and joined before the gather, also inside the captured
+   graph), detectors assigned by estimated work.  The outputs do not depend on it. */
 int sc_batch_set_param(sc_batch *batch, int det, int param, int64_t value);
 int sc_batch_get_param(const sc_batch *batch, int det, int param, int64_t *value);
 

@@ -20,6 +20,7 @@ SC_PARAM_BIN_CHUNK, SC_PARAM_GATHER_WGS_PER_CU, SC_PARAM_RING_RPT, SC_PARAM_SKY_
 SC_PARAM_GATHER_MMA = 6
 SC_PARAM_VALIDATE = 7
 SC_PARAM_DETERMINISTIC = 8
+SC_PARAM_BATCH_CHAINS = 9
 SC_MMA_FP32, SC_MMA_SPLIT16 = 0, 1
 
 EXPORTS = (

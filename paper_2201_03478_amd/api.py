@@ -62,7 +62,7 @@ def _dev(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
 PARAMS = {"bin_chunk": N.SC_PARAM_BIN_CHUNK, "gather_wgs_per_cu": N.SC_PARAM_GATHER_WGS_PER_CU,
           "ring_rpt": N.SC_PARAM_RING_RPT, "sky_lmax": N.SC_PARAM_SKY_LMAX, "gather_waves": N.SC_PARAM_GATHER_WAVES,
           "gather_mma": N.SC_PARAM_GATHER_MMA, "validate": N.SC_PARAM_VALIDATE,
-          "deterministic": N.SC_PARAM_DETERMINISTIC}
+          "deterministic": N.SC_PARAM_DETERMINISTIC, "batch_chains": N.SC_PARAM_BATCH_CHAINS}
 
 
 class Plan:

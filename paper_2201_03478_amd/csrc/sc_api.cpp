@@ -1141,6 +1141,7 @@ struct sc_batch {
     hipStream_t side[3];
     hipEvent_t ev_fork, ev_join[3];
     std::vector<int> chain;  // chain of each detector
+    int nchains;             // chains in use, 1 .. SC_BATCH_CHAINS (SC_PARAM_BATCH_CHAINS)
 };
 
 #define SC_BATCH_CHAINS 4
@@ -1203,6 +1204,27 @@ hipError_t batch_enqueue(sc_batch *b, const double *alm, hipStream_t s, bool tim
     }
     for (sc_plan *p : b->plans) p->stream = b->stream;
     return e;
+}
+
+double det_work(const sc_plan *p, int64_t n);
+
+// Longest-processing-time assignment of the detectors to the batch's chains.
+void batch_assign_chains(sc_batch *b) {
+    const int ndet = b->ndet;
+    std::vector<int> order(ndet);
+    for (int d = 0; d < ndet; ++d) order[d] = d;
+    std::vector<double> work(ndet);
+    for (int d = 0; d < ndet; ++d) work[d] = det_work(b->plans[d], b->dets[d].n);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    double load[SC_BATCH_CHAINS] = {};
+    b->chain.assign(ndet, 0);
+    for (int d : order) {
+        int best = 0;
+        for (int c = 1; c < b->nchains; ++c)
+            if (load[c] < load[best]) best = c;
+        b->chain[d] = best;
+        load[best] += work[d];
+    }
 }
 
 // Estimated work of a detector (for the chain assignment): Wigner-d values of the
@@ -1301,21 +1323,8 @@ int sc_batch_create(sc_batch **out, const sc_det_desc *dets, int ndet, int lmax_
             sc_batch_destroy(b);
             return hip_fail(es, "batch side streams");
         }
-        // longest-processing-time assignment of detectors to chains
-        std::vector<int> order(ndet);
-        for (int d = 0; d < ndet; ++d) order[d] = d;
-        std::vector<double> work(ndet);
-        for (int d = 0; d < ndet; ++d) work[d] = det_work(b->plans[d], dets[d].n);
-        std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-        double load[SC_BATCH_CHAINS] = {};
-        b->chain.assign(ndet, 0);
-        for (int d : order) {
-            int best = 0;
-            for (int c = 1; c < SC_BATCH_CHAINS; ++c)
-                if (load[c] < load[best]) best = c;
-            b->chain[d] = best;
-            load[best] += work[d];
-        }
+        b->nchains = SC_BATCH_CHAINS;
+        batch_assign_chains(b);
     }
     hipError_t e = hipMemcpyAsync(b->dets_dev, gd.data(), sizeof(GatherDet) * ndet, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1332,6 +1341,14 @@ int sc_batch_set_param(sc_batch *b, int det, int param, int64_t value) {
     if (param == SC_PARAM_GATHER_WGS_PER_CU) {
         if (value < 0 || value > 16) return fail(SC_EINVAL, "workgroups per CU outside [0, 16]");
         b->wgs_per_cu = (int)value;
+        batch_drop_graph(b);
+        return SC_OK;
+    }
+    if (param == SC_PARAM_BATCH_CHAINS) {
+        if (value < 1 || value > SC_BATCH_CHAINS)
+            return fail(SC_EINVAL, "synthesis chains %lld outside [1, %d]", (long long)value, SC_BATCH_CHAINS);
+        b->nchains = (int)value;
+        batch_assign_chains(b);
         batch_drop_graph(b);
         return SC_OK;
     }
@@ -1367,6 +1384,10 @@ int sc_batch_get_param(const sc_batch *b, int det, int param, int64_t *value) {
     }
     if (param == SC_PARAM_GATHER_WAVES) {
         *value = b->waves;
+        return SC_OK;
+    }
+    if (param == SC_PARAM_BATCH_CHAINS) {
+        *value = b->nchains;
         return SC_OK;
     }
     if (param == SC_PARAM_GATHER_MMA) {

@@ -156,3 +156,23 @@ def test_batch_stage_timing_leaves_results(env):
     torch.cuda.synchronize()
     for x, y in zip(ref, graph):
         assert torch.equal(x, y)
+
+
+def test_batch_chain_count_leaves_results(env):
+    """One to four synthesis chains (SC_PARAM_BATCH_CHAINS): the same kernels on the same data,
+    so eager passes and graph replays give the same bits whatever the chain count."""
+    torch, api, dev = env
+    dets, sky = _small_batch(torch, dev)
+    b = api.Batch(dets, 80)
+    assert b.get_param("batch_chains") == 4
+    ref = [t.clone() for t in b.run(sky, use_graph=False)]
+    for nch in (1, 2, 3, 4):
+        b.set_param("batch_chains", nch)
+        assert b.get_param("batch_chains") == nch
+        for g in (False, True, True):
+            out = [t.clone() for t in b.run(sky, use_graph=g)]
+            torch.cuda.synchronize()
+            for x, y in zip(ref, out):
+                assert torch.equal(x, y), (nch, g)
+    with pytest.raises(api.N.ScError):
+        b.set_param("batch_chains", 5)
