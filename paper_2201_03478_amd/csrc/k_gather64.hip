@@ -216,10 +216,14 @@ hipError_t sc_launch_gather_mfma64(sc_plan *p, void *tod) {
     switch (p->W) {
         case 4: return launch64<4, 4, 4>(p, tod);
         case 6: return launch64<6, 4, 4>(p, tod);
-        case 8: return launch64<8, 4, 4>(p, tod);
-        case 10: return launch64<10, 4, 4>(p, tod);
-        case 12: return launch64<12, 4, 4>(p, tod);
-        case 14: return launch64<14, 3, 4>(p, tod);
+        // Two component tiles per staged chunk from W = 8 up: at lmax 512 / kmax 100 / 1e7 scan
+        // samples W = 8 took 7.6 ms against 8.2 (2, 2), 8.6 (4, 2), 11.3 (8, 2), 11.5 (4, 4) and
+        // 13.7 (8, 4); W = 14 took 20.9 ms against 21.7 (3, 4), 21.9 (2, 2), 22.8 (1, 4) and
+        // 25.1 (3, 2) (more LDS per chunk means fewer workgroups per CU, more tiles more registers).
+        case 8: return launch64<8, 2, 4>(p, tod);
+        case 10: return launch64<10, 2, 4>(p, tod);
+        case 12: return launch64<12, 2, 4>(p, tod);
+        case 14: return launch64<14, 2, 4>(p, tod);
         case 16: return launch64<16, 2, 4>(p, tod);
         default: return hipErrorInvalidValue;
     }
