@@ -135,12 +135,12 @@ __device__ __forceinline__ void rec_steps(int t0, int t1, const double *cA, cons
 }
 
 // Up to 3 rings per lane the kernel fits 168 registers: three waves per SIMD.
-template <int RPT, typename FT>
+template <int RPT, typename FT, bool TAB>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RPT <= 3 ? 3 : 2)))
 k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT *__restrict__ F,
             const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
-            const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
-            int ngroups, int alm_lmax) {
+            const double *__restrict__ rtab, const double2 *__restrict__ rroot, const double4 *__restrict__ ctab,
+            const long long *__restrict__ ctab_off, int lmax, int kmax, int nring, int ngroups, int alm_lmax) {
     __shared__ double cA[64], cB[2 * 64];
     __shared__ double2 cWp[64], cWm[64];
 
@@ -190,8 +190,12 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT
     const size_t aoff = (size_t)m * (2 * alm_lmax + 1 - m) / 2;  // sky layout may have a larger lmax
     const size_t boff = (size_t)k * (2 * lmax + 1 - k) / 2;
     double s_prev = 1.0, s_cur = 1.0;  // S_{lc-1}, S_{lc} (S_{l0-1} := 1 only seeds the scan)
+    // with the table, each chunk's entry is loaded during the previous chunk's steps
+    const double4 *ccol = TAB ? ctab + ctab_off[m * (kmax + 1) + k] : nullptr;
+    ChunkCoef cnext{0.0, 0.0, 0.0, 0.0};
+    if (TAB) cnext = chunk_coefs_tab(ccol, l0, lane, l0, lmax);
     for (int lc = l0; lc <= lmax; lc += 64) {
-        const ChunkCoef cc = chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
+        const ChunkCoef cc = TAB ? cnext : chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
         __syncthreads();  // previous chunk's coefficients are consumed
         cA[lane] = cc.a;
         cB[lane] = cc.b;
@@ -201,6 +205,7 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT
             if (which == 1) cWm[lane] = v;  // the R- weights are these, exchanged and signed
         });
         __syncthreads();
+        if (TAB) cnext = chunk_coefs_tab(ccol, lc + 64, lane, l0, lmax);  // in flight during the steps
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
         const double *cBt = cB + 64 * tp;
         if (fast) {
@@ -256,25 +261,61 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT
 
 }  // namespace
 
-template <typename FT>
+template <typename FT, bool TAB>
 static void launch_ring_sums(sc_plan *p, const double *alm, const double *blm, FT *F) {
     const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups;
-    auto kern = k_ring_sums<4, FT>;
+    auto kern = k_ring_sums<4, FT, TAB>;
     switch (p->rpt) {
-        case 1: kern = k_ring_sums<1, FT>; break;
-        case 2: kern = k_ring_sums<2, FT>; break;
-        case 3: kern = k_ring_sums<3, FT>; break;
+        case 1: kern = k_ring_sums<1, FT, TAB>; break;
+        case 2: kern = k_ring_sums<2, FT, TAB>; break;
+        case 3: kern = k_ring_sums<3, FT, TAB>; break;
         default: break;
     }
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm, (const double2 *)blm, F,
-                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, p->ngroups, p->alm_lmax);
+                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->ctab, p->ctab_off, p->lmax, p->kmax, p->nring,
+                       p->ngroups, p->alm_lmax);
 }
 
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm) {
-    if (p->mid32)
-        launch_ring_sums(p, alm, blm, (float2 *)p->F);
-    else
-        launch_ring_sums(p, alm, blm, p->F);
+    if (p->mid32) {
+        if (p->ctab)
+            launch_ring_sums<float2, true>(p, alm, blm, (float2 *)p->F);
+        else
+            launch_ring_sums<float2, false>(p, alm, blm, (float2 *)p->F);
+    } else {
+        if (p->ctab)
+            launch_ring_sums<double2, true>(p, alm, blm, p->F);
+        else
+            launch_ring_sums<double2, false>(p, alm, blm, p->F);
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
+// One wave per (m, k) column: the chunk coefficients of every step, in the ring
+// kernels' chunking (l0, l0 + 64, ...), so the table holds exactly the values they
+// would compute.
+__global__ void __launch_bounds__(64) k_rec_table(const double2 *__restrict__ rroot, double4 *__restrict__ ctab,
+                                                  const long long *__restrict__ ctab_off, int lmax, int kmax) {
+    const int col = blockIdx.x;
+    const int m = col / (kmax + 1), k = col - m * (kmax + 1);
+    const int l0 = m > k ? m : k;
+    const int lane = threadIdx.x;
+    double4 *out = ctab + ctab_off[col];
+    double s_prev = 1.0, s_cur = 1.0;
+    for (int lc = l0; lc <= lmax; lc += 64) {
+        const ChunkCoef cc = chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
+        if (lc + lane <= lmax) out[lc - l0 + lane] = make_double4(cc.a, cc.b, cc.bn, cc.sl);
+    }
+}
+
+}  // namespace
+
+hipError_t sc_launch_rec_table(sc_plan *p) {
+    if (!p->ctab) return hipSuccess;
+    hipLaunchKernelGGL(k_rec_table, dim3((p->lmax + 1) * (p->kmax + 1)), dim3(64), 0, p->stream, p->rroot, p->ctab,
+                       p->ctab_off, p->lmax, p->kmax);
     return hipGetLastError();
 }
 

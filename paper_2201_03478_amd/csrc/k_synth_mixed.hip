@@ -77,12 +77,13 @@ __device__ __forceinline__ void mx_steps(int t0, int t1, const double *cA, const
     for (int t = te; t < t1; ++t) mx_step<RPT, MASK>(mx_load(t, cA, cB, cW), x, u, up, e, acc);
 }
 
-template <int RPT, typename FT>
+template <int RPT, typename FT, bool TAB>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RPT <= 3 ? 3 : 2)))
 k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT *__restrict__ F,
                   const double *__restrict__ sbin_m, const int *__restrict__ sbin_e,
-                  const double *__restrict__ rtab, const double2 *__restrict__ rroot, int lmax, int kmax, int nring,
-                  int ngroups, int alm_lmax) {
+                  const double *__restrict__ rtab, const double2 *__restrict__ rroot,
+                  const double4 *__restrict__ ctab, const long long *__restrict__ ctab_off, int lmax, int kmax,
+                  int nring, int ngroups, int alm_lmax) {
     __shared__ double cA[64], cB[2 * 64];
     __shared__ float cW[64 * 4];
     __shared__ double Fs[RPT][64][4];
@@ -135,8 +136,12 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
     double s_prev = 1.0, s_cur = 1.0;
     const double *cBt = cB + 64 * tp;
     const float *cWt = cW + (lane & 3);
+    // with the table, each chunk's entry is loaded during the previous chunk's steps
+    const double4 *ccol = TAB ? ctab + ctab_off[m * (kmax + 1) + k] : nullptr;
+    ChunkCoef cnext{0.0, 0.0, 0.0, 0.0};
+    if (TAB) cnext = chunk_coefs_tab(ccol, l0, lane, l0, lmax);
     for (int lc = l0; lc <= lmax; lc += 64) {
-        const ChunkCoef cc = chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
+        const ChunkCoef cc = TAB ? cnext : chunk_coefs(lc, lane, l0, lmax, m, k, rroot, s_prev, s_cur);
         __syncthreads();  // previous chunk's coefficients are consumed
         cA[lane] = cc.a;
         cB[lane] = cc.b;
@@ -150,6 +155,7 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
             }
         });
         __syncthreads();
+        if (TAB) cnext = chunk_coefs_tab(ccol, lc + 64, lane, l0, lmax);  // in flight during the steps
         const int nl = (lmax - lc + 1) < 64 ? (lmax - lc + 1) : 64;
         if (fast) {
             mx_steps<RPT, false>(0, nl, cA, cBt, cWt, x, u, up, e, acc);
@@ -211,26 +217,33 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
 
 }  // namespace
 
-template <typename FT>
+template <typename FT, bool TAB>
 static void launch_mixed(sc_plan *p, const double *alm, const double *blm, FT *F) {
     const int nblk = (p->lmax + 1) * (p->kmax + 1) * p->ngroups_mx;
-    auto kern = k_ring_sums_mixed<4, FT>;
+    auto kern = k_ring_sums_mixed<4, FT, TAB>;
     switch (p->rpt_mx) {
-        case 1: kern = k_ring_sums_mixed<1, FT>; break;
-        case 2: kern = k_ring_sums_mixed<2, FT>; break;
-        case 3: kern = k_ring_sums_mixed<3, FT>; break;
+        case 1: kern = k_ring_sums_mixed<1, FT, TAB>; break;
+        case 2: kern = k_ring_sums_mixed<2, FT, TAB>; break;
+        case 3: kern = k_ring_sums_mixed<3, FT, TAB>; break;
         default: break;
     }
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, p->stream, (const double2 *)alm, (const double2 *)blm, F,
-                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->lmax, p->kmax, p->nring, p->ngroups_mx,
-                       p->alm_lmax);
+                       p->sbin_m, p->sbin_e, p->rtab, p->rroot, p->ctab, p->ctab_off, p->lmax, p->kmax, p->nring,
+                       p->ngroups_mx, p->alm_lmax);
 }
 
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm) {
-    if (p->mid32)
-        launch_mixed(p, alm, blm, (float2 *)p->F);
-    else
-        launch_mixed(p, alm, blm, p->F);
+    if (p->mid32) {
+        if (p->ctab)
+            launch_mixed<float2, true>(p, alm, blm, (float2 *)p->F);
+        else
+            launch_mixed<float2, false>(p, alm, blm, (float2 *)p->F);
+    } else {
+        if (p->ctab)
+            launch_mixed<double2, true>(p, alm, blm, p->F);
+        else
+            launch_mixed<double2, false>(p, alm, blm, p->F);
+    }
     return hipGetLastError();
 }
 

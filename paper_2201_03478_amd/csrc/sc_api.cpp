@@ -228,7 +228,7 @@ void free_plan_buffers(sc_plan *p) {
     p->tl = nullptr;
     p->tl_cap = p->tl_n = 0;
     void *bufs[] = {p->F, p->G, p->maps, p->rroot, p->sbin_m, p->sbin_e, p->rtab, p->tw2, p->tw2os, p->twphi,
-                    p->phase, p->dphi, p->glx, p->glw, p->S};
+                    p->phase, p->dphi, p->glx, p->glw, p->S, p->ctab, p->ctab_off};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -464,6 +464,20 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     rc = rc ? rc : alloc((void **)&p->dphi, sizeof(double) * (lmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->glx, sizeof(double) * p->nq, &tot);
     rc = rc ? rc : alloc((void **)&p->glw, sizeof(double) * p->nq, &tot);
+    // Recursion coefficients of every (m, k, l) column for the ring-sum kernels (32 B per
+    // entry: 0.66 GB at lmax 512 / kmax 100, 3.2 GB at lmax 8192 / kmax 2); above 8 GiB the
+    // kernels compute them per chunk instead.
+    std::vector<long long> coff((size_t)(lmax + 1) * (kmax + 1));
+    long long ctot = 0;
+    for (int m = 0; m <= lmax; ++m)
+        for (int k = 0; k <= kmax; ++k) {
+            coff[(size_t)m * (kmax + 1) + k] = ctot;
+            ctot += lmax - (m > k ? m : k) + 1;
+        }
+    if ((double)ctot * 32.0 <= 8.0 * (1 << 30)) {
+        rc = rc ? rc : alloc((void **)&p->ctab, 32 * (size_t)ctot, &tot);
+        rc = rc ? rc : alloc((void **)&p->ctab_off, sizeof(long long) * coff.size(), &tot);
+    }
     if (rc) {
         free_plan_buffers(p);
         delete p;
@@ -473,6 +487,10 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     // padding components stay zero for the plan's lifetime
     hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, p->stream);
     if (e == hipSuccess) e = sc_launch_tables(p);
+    if (e == hipSuccess && p->ctab)
+        e = hipMemcpyAsync(p->ctab_off, coff.data(), sizeof(long long) * coff.size(), hipMemcpyHostToDevice,
+                           p->stream);  // coff outlives the synchronisation below
+    if (e == hipSuccess) e = sc_launch_rec_table(p);
     if (e == hipSuccess) {
         // ring table in extended host precision: theta_j = (j + 1/2) pi / nring;
         // 1 - cos(theta_j) as 2 sin^2(theta_j / 2), which keeps its full relative

@@ -133,6 +133,8 @@ struct sc_plan {
     double2 *G;        // [kmax+1][rows][gst] theta-upsampled, deconvolved (float2 with mid32)
     void *maps;        // [rows][cols][ncp] float or double
     double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
+    double4 *ctab;     // recursion coefficients (a, b, bn, S_l) of every (m, k, l), l >= max(m, k) (or null)
+    long long *ctab_off;  // [lmax+1][kmax+1] first entry of each column
     double *sbin_m;    // [lmax+1][kmax+1] mantissa of sqrt(C(2 l, l + n))
     int *sbin_e;       // [lmax+1][kmax+1] binary exponent
     double *rtab;      // [nring][5] 1 - cos(theta_j); log2 cos(theta_j / 2), log2 sin(theta_j / 2) as (hi, lo) pairs
@@ -194,6 +196,7 @@ hipError_t sc_launch_psi_cube(sc_plan *p);
 hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod);
 int sc_psi_max_len();
 hipError_t sc_launch_ring_sums(sc_plan *p, const double *alm, const double *blm);
+hipError_t sc_launch_rec_table(sc_plan *p);  // fills ctab (after sc_launch_tables)
 void sc_choose_ring_layout(int nring, int *rpt, int *ngroups);
 int sc_ring_groups(int nring, int rpt);  // ring groups of the FP64 ring-sum kernel
 hipError_t sc_launch_ring_sums_mixed(sc_plan *p, const double *alm, const double *blm);

@@ -142,6 +142,19 @@ __device__ __forceinline__ ChunkCoef chunk_coefs(int lc, int lane, int l0, int l
     return ChunkCoef{A * ratio, B * ratio, Bn * ratio, Sl};
 }
 
+// The chunk coefficients depend on (m, k, l) only, so a plan can hold them for every
+// column (k_rec_table, entry l - l0 of column (m, k) = (a, b, bn, S_l) as chunk_coefs
+// returns them, with the same chunking from l0): one coalesced load per lane instead
+// of the root-table loads, two divisions and the product scan, in every wave of every
+// synthesis.  Zero past lmax (no step reads those; the weights there are zero).
+__device__ __forceinline__ ChunkCoef chunk_coefs_tab(const double4 *__restrict__ col, int lc, int lane, int l0,
+                                                     int lmax) {
+    const int l = lc + lane;
+    if (l > lmax) return ChunkCoef{0.0, 0.0, 0.0, 0.0};
+    const double4 q = col[l - l0];
+    return ChunkCoef{q.x, q.y, q.z, q.w};
+}
+
 // Contraction weights of step l (zero past lmax), each times S_l:
 //   R+: wp = a_lm conj(b_lk)                    -> F_k(theta_j, m)
 //       wm = (-1)^{l+k+m} conj(a_lm) conj(b_lk) -> F_k(pi - theta_j, -m)
