@@ -343,9 +343,10 @@ __device__ __forceinline__ void fft_passes_c(double2 *buf, const double2 *__rest
 // only the base row w^k = e^{-2 pi i k / (R NS)}, k < NS (NS values), is stored,
 // and w^{r k} is formed by repeated multiplication (r < 16 products: a relative
 // error of a few 1e-16), so a transform needs no global loads once the bases of all
-// its passes are in LDS.
-template <int R, int DIR, int NT, int N, int NS>
-__device__ __forceinline__ void stockham_stage_l(double2 *buf, const double2 *twl, int tid) {
+// its passes are in LDS.  The buffer holds complex128 or complex64 values (BT); the
+// arithmetic is FP64 either way, so complex64 only rounds each pass's outputs.
+template <int R, int DIR, int NT, int N, int NS, typename BT>
+__device__ __forceinline__ void stockham_stage_l(BT *buf, const double2 *twl, int tid) {
     constexpr int nb = N / R;
     constexpr int B = (nb + NT - 1) / NT;
     double2 v[B][R];
@@ -364,7 +365,7 @@ __device__ __forceinline__ void stockham_stage_l(double2 *buf, const double2 *tw
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double2 x = buf[j + r * nb];
+                double2 x = ld2(buf + j + r * nb);
                 if (NS > 1 && r > 0) {
                     x = cmul(x, w);
                     if (r + 1 < R) w = cmul(w, w1);
@@ -380,14 +381,14 @@ __device__ __forceinline__ void stockham_stage_l(double2 *buf, const double2 *tw
         const int j = tid + b * NT;
         if ((b + 1) * NT <= nb || j < nb) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[widx[b] + r * NS] = v[b][r];
+            for (int r = 0; r < R; ++r) st2(buf + widx[b] + r * NS, v[b][r]);
         }
     }
     __syncthreads();
 }
 
-template <int DIR, int NT, int N, int NS, int R, int... Rest>
-__device__ __forceinline__ void fft_passes_l(double2 *buf, const double2 *twl, int tid) {
+template <int DIR, int NT, int N, int NS, int R, int... Rest, typename BT>
+__device__ __forceinline__ void fft_passes_l(BT *buf, const double2 *twl, int tid) {
     stockham_stage_l<R, DIR, NT, N, NS>(buf, twl, tid);
     if constexpr (sizeof...(Rest) > 0) fft_passes_l<DIR, NT, N, NS * R, Rest...>(buf, twl + (NS > 1 ? NS : 0), tid);
 }
@@ -441,8 +442,9 @@ struct FftRun<DIR, NT, PT, FftSpec<N, Rs...>> {
     __device__ __forceinline__ static void load_tw(double2 *twl, const double2 *__restrict__ tw, int tid) {
         tw_base_load<NT, 1, Rs...>(twl, tw, tid);
     }
-    // twl: the bases written by load_tw (visible to all threads)
-    __device__ __forceinline__ static void run_l(double2 *buf, const double2 *twl, int tid) {
+    // twl: the bases written by load_tw (visible to all threads); buf complex128 or complex64
+    template <typename BT>
+    __device__ __forceinline__ static void run_l(BT *buf, const double2 *twl, int tid) {
         fft_passes_l<DIR, NT, N, 1, Rs...>(buf, twl, tid);
     }
 };

@@ -204,11 +204,13 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int *__restrict__ 
 // Sample records in anchor order.  Lane pairs write the two 16-byte halves of one
 // record in the same instruction (one 32-byte run per sample, not four partial
 // writes); the values come from the sample's own lane by shuffles.  (Blocks are
-// whole waves.)
+// whole waves.)  Samples of one key within a span of consecutive samples have
+// consecutive ranks, so their records are neighbours: the blocks of a span run on
+// one XCD, whose L2 merges those partial-line writes.
 __global__ void k_bin_scatter(const double *__restrict__ ptg, int64_t n, BinGeom g, const int *__restrict__ key,
                               const int *__restrict__ rank, const int2 *__restrict__ offs, BinSorted out,
                               const float *__restrict__ y) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool valid = s < n;
     int pos = -1;
     double fu = 0.0, fv = 0.0, psi = 0.0, yv = 0.0;

@@ -66,7 +66,7 @@ __device__ inline void store_quad<double>(double *o, double a, double b, double 
 // variant that walks consecutive pairs and prefetches the next pair's columns
 // measured slower at lmax 512 than one pair per workgroup.)
 template <int NT, int PT, typename S2, typename SOS, typename FT, typename GT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(GT) == sizeof(float2) ? (NT > 256 ? 5 : 6) : 4)))
 k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nring, int rows, int gst,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
                  const double2 *__restrict__ twos, const double2 *__restrict__ phase,
@@ -74,6 +74,9 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
     using Fwd = FftRun<-1, NT, PT, S2>;
     using Inv = FftRun<1, NT, PT, SOS>;
     constexpr bool TWL = FftLen<S2>::value > 0 && FftLen<SOS>::value > 0;
+    // complex64 spectra with compile-time transforms: the transform buffer holds
+    // complex64 too (half the LDS per workgroup); the arithmetic stays FP64
+    using BT = typename std::conditional<TWL && sizeof(GT) == sizeof(float2), float2, double2>::type;
     extern __shared__ double2 sbuf[];
     const int nm = 2 * lmax + 1;
     const int npair = lmax + 1;  // ceil(nm / 2)
@@ -84,8 +87,8 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
     const int m = mi - lmax;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n2 = P2.n, nos = Pos.n;
-    double2 *B = sbuf;         // length nos; the forward transform runs in B[0 .. n2)
-    double2 *T2 = sbuf + nos;  // LDS twiddle bases (TWL): forward, then inverse
+    BT *B = (BT *)sbuf;                         // length nos; the forward transform runs in B[0 .. n2)
+    double2 *T2 = (double2 *)(B + nos);  // LDS twiddle bases (TWL): forward, then inverse (nos is even)
     double2 *Tos = T2;
     if constexpr (TWL) {
         Tos = T2 + Fwd::ntw;
@@ -98,14 +101,14 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
     for (int j = tid; j < nring; j += nth) {
         const double2 a = ld2(col + j);
         const double2 b = two ? ld2(col + nring + j) : make_double2(0.0, 0.0);
-        B[j] = make_double2(a.x - b.y, a.y + b.x);                         // a + i b
-        B[n2 - 1 - j] = make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x));  // s1 (a - i b)
+        st2(B + j, make_double2(a.x - b.y, a.y + b.x));                         // a + i b
+        st2(B + n2 - 1 - j, make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x)));  // s1 (a - i b)
     }
     __syncthreads();
     if constexpr (TWL)
         Fwd::run_l(B, T2, tid);
     else
-        Fwd::run(B, P2, tw2, tid, nth);
+        Fwd::run((double2 *)B, P2, tw2, tid, nth);
 
     // Coefficients n in [-lmax, lmax]: n >= 0 stay at n, n < 0 move from
     // n + n2 to n + nos (sources and targets are disjoint since nos >= n2 + lmax),
@@ -122,7 +125,7 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
         if (t < nm) {
             const int n = t - lmax;
             const double2 p = phase[t];
-            const double2 hp = B[n < 0 ? n + n2 : n], hm = B[n > 0 ? n2 - n : -n];
+            const double2 hp = ld2(B + (n < 0 ? n + n2 : n)), hm = ld2(B + (n > 0 ? n2 - n : -n));
             const double2 u = cmul(p, hp), v = cmul(cconj(p), hm);
             xs[i] = make_double2(ca * u.x + cb * v.x, ca * u.y + cb * v.y);
         }
@@ -133,15 +136,15 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
         const int t = tid + i * nth;
         if (t < nm) {
             const int n = t - lmax;
-            B[n < 0 ? n + nos : n] = xs[i];
+            st2(B + (n < 0 ? n + nos : n), xs[i]);
         }
     }
-    for (int t = lmax + 1 + tid; t < nos - lmax; t += nth) B[t] = make_double2(0.0, 0.0);
+    for (int t = lmax + 1 + tid; t < nos - lmax; t += nth) st2(B + t, make_double2(0.0, 0.0));
     __syncthreads();
     if constexpr (TWL)
         Inv::run_l(B, Tos, tid);
     else
-        Inv::run(B, Pos, twos, tid, nth);
+        Inv::run((double2 *)B, Pos, twos, tid, nth);
 
     const int r0 = -W / 2 + 1;
     GT *gk = G + (size_t)k * rows * gst + mi;
@@ -153,7 +156,7 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
             int r = row + r0;
             r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
             const int rm = r == 0 ? 0 : nos - r;
-            const double2 o = B[r], om = B[rm];
+            const double2 o = ld2(B + r), om = ld2(B + rm);
             const double2 g1 = make_double2(o.x + s1 * om.x, o.y + s1 * om.y);
             const double2 g2 = two ? make_double2(o.y - s1 * om.y, s1 * om.x - o.x) : make_double2(0.0, 0.0);
             *(float4 *)(gk + (size_t)row * gst) = make_float4((float)g1.x, (float)g1.y, (float)g2.x, (float)g2.y);
@@ -166,7 +169,7 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
             int r = row + r0;
             r = r < 0 ? r + nos : (r >= nos ? r - nos : r);
             const int rm = r == 0 ? 0 : nos - r;
-            const double2 o = B[r], om = B[rm];
+            const double2 o = ld2(B + r), om = ld2(B + rm);
             const double2 g = c == 0 ? make_double2(o.x + s1 * om.x, o.y + s1 * om.y)
                                      : make_double2(o.y - s1 * om.y, s1 * om.x - o.x);  // -i (o - s1 om)
             gk[(size_t)row * gst + c] = g;
@@ -182,27 +185,27 @@ __device__ __forceinline__ double2 phi_pair(double2 v, int k) {
 // G row (nm spectral values) into registers; lanes past nm read a valid duplicate,
 // which phi_scatter replaces by zero.
 template <int NT, int MAXC, typename GT>
-__device__ __forceinline__ void phi_load(double2 (&spec)[MAXC], const GT *__restrict__ src, int tid, int nm) {
+__device__ __forceinline__ void phi_load(GT (&spec)[MAXC], const GT *__restrict__ src, int tid, int nm) {
 #pragma unroll
     for (int i = 0; i < MAXC; ++i) {
         const int t = tid + i * NT;
-        spec[i] = ld2(src + (t < nm ? t : nm - 1));
+        spec[i] = src[t < nm ? t : nm - 1];
     }
 }
 
 // Zero-padded spectrum in A: m >= 0 at m, m < 0 at m + np, zeros in between (lanes
 // past nm write a zero into that band too).
-template <int NT, int MAXC>
-__device__ __forceinline__ void phi_scatter(double2 *A, const double2 (&spec)[MAXC], int tid, int lmax, int np) {
+template <int NT, int MAXC, typename BT, typename GT>
+__device__ __forceinline__ void phi_scatter(BT *A, const GT (&spec)[MAXC], int tid, int lmax, int np) {
     const int nm = 2 * lmax + 1;
-    for (int t = lmax + 1 + tid; t < np - lmax; t += NT) A[t] = make_double2(0.0, 0.0);
+    for (int t = lmax + 1 + tid; t < np - lmax; t += NT) st2(A + t, make_double2(0.0, 0.0));
 #pragma unroll
     for (int i = 0; i < MAXC; ++i) {
         const int t = tid + i * NT;
         const int m = t - lmax;
         const bool in = t < nm;
-        const double2 v = spec[i];
-        A[in ? (m < 0 ? m + np : m) : lmax + 1] = make_double2(in ? v.x : 0.0, in ? v.y : 0.0);
+        const double2 v = make_double2((double)spec[i].x, (double)spec[i].y);
+        st2(A + (in ? (m < 0 ? m + np : m) : lmax + 1), make_double2(in ? v.x : 0.0, in ? v.y : 0.0));
     }
 }
 
@@ -212,7 +215,7 @@ __device__ __forceinline__ void phi_scatter(double2 *A, const double2 (&spec)[MA
 // wait in registers, so each lane writes both k's component pairs of a column as
 // one 16-byte store (a column's map record is contiguous in k).
 template <typename T, int NT, int PT, typename SP, int KP, typename GT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(GT) == sizeof(float2) ? 5 : 4)))
 k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int gst, int cols, int ncp,
                 int W, int nk, FftPlan Pp, const double2 *__restrict__ twp) {
     static_assert(KP == 1 || KP == 2, "one or two k per workgroup");
@@ -225,17 +228,20 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
     const bool two = KP == 2 && k0 + 1 < nk;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int np = Pp.n;
-    double2 *A = sbuf;
     constexpr int NP = FftLen<SP>::value;  // 0: runtime-planned transform
+    // complex64 spectra with a compile-time transform: complex64 transform buffer
+    // (half the LDS per workgroup), FP64 arithmetic
+    using BT = typename std::conditional<(NP > 0 && sizeof(GT) == sizeof(float2)), float2, double2>::type;
+    BT *A = (BT *)sbuf;
     using Run = FftRun<1, NT, PT, SP>;
-    double2 *Tw = sbuf + np;  // compile-time transforms: LDS twiddle bases
+    double2 *Tw = (double2 *)(A + np);  // compile-time transforms: LDS twiddle bases (np is even)
     if constexpr (NP > 0) Run::load_tw(Tw, twp, tid);  // visible after the first barrier
     constexpr int MAXC = (PT + 1) / 2;                            // nm <= NT MAXC
     constexpr int MAXS = NP > 0 ? (NP + 15 + NT - 1) / NT : PT + 1;  // cols <= np + 15 <= NT MAXS
     const int q0 = -W / 2 + 1;
     const GT *src = G + ((size_t)k0 * rows + row) * gst;
     T *dst = maps + (size_t)row * cols * ncp + 2 * k0;
-    double2 spec[MAXC];
+    GT spec[MAXC];  // complex64 spectra stay complex64 in registers until they are scattered
     phi_load<NT, MAXC>(spec, src, tid, nm);
     phi_scatter<NT, MAXC>(A, spec, tid, lmax, np);
     __syncthreads();
@@ -245,14 +251,14 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
         if constexpr (NP > 0)
             Run::run_l(A, Tw, tid);
         else
-            Run::run(A, Pp, twp, tid, nth);
+            Run::run((double2 *)A, Pp, twp, tid, nth);
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) {
             int col = tid + i * NT;
             col = col < cols ? col : cols - 1;
             int q = col + q0;
             q = q < 0 ? q + np : (q >= np ? q - np : q);
-            const double2 v = phi_pair(A[q], k0);
+            const double2 v = phi_pair(ld2(A + q), k0);
             stage[KP == 2 ? i : 0][0] = (T)v.x;
             stage[KP == 2 ? i : 0][1] = (T)v.y;
         }
@@ -263,7 +269,7 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
     if constexpr (NP > 0)
         Run::run_l(A, Tw, tid);
     else
-        Run::run(A, Pp, twp, tid, nth);
+        Run::run((double2 *)A, Pp, twp, tid, nth);
     const int k = two ? k0 + 1 : k0;
 #pragma unroll
     for (int i = 0; i < MAXS; ++i) {
@@ -271,7 +277,7 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
         if (col < cols) {
             int q = col + q0;
             q = q < 0 ? q + np : (q >= np ? q - np : q);
-            const double2 v = phi_pair(A[q], k);
+            const double2 v = phi_pair(ld2(A + q), k);
             T *o = dst + (size_t)col * ncp;
             if (two)
                 store_quad<T>(o, stage[KP == 2 ? i : 0][0], stage[KP == 2 ? i : 0][1], (T)v.x, (T)v.y);
@@ -448,8 +454,10 @@ static inline int fft_class(int n) {
 template <int NT, int PT, typename S2, typename SOS, typename CT>
 static hipError_t theta_up_t(sc_plan *p) {
     const int nblk = (p->kmax + 1) * (p->lmax + 1);  // column pairs
-    const int ntw = FftRun<-1, NT, PT, S2>::ntw + FftRun<1, NT, PT, SOS>::ntw;  // zero unless both are compile-time
-    const size_t lds = sizeof(double2) * ((size_t)p->n2os + ntw);
+    constexpr int ntw = FftRun<-1, NT, PT, S2>::ntw + FftRun<1, NT, PT, SOS>::ntw;  // zero unless both are compile-time
+    // complex64 transform buffer (the kernel's choice: complex64 spectra, compile-time transforms)
+    constexpr bool c64 = FftLen<S2>::value > 0 && FftLen<SOS>::value > 0 && sizeof(CT) == sizeof(float2);
+    const size_t lds = (c64 ? sizeof(float2) : sizeof(double2)) * (size_t)p->n2os + sizeof(double2) * ntw;
     auto kern = k_theta_upsample<NT, PT, S2, SOS, CT, CT>;
     hipError_t e = sc_set_lds_attr((const void *)kern, lds);
     if (e != hipSuccess) return e;
@@ -470,14 +478,17 @@ static hipError_t phi_syn(sc_plan *p) {
     constexpr int KP = sizeof(T) == 4 && FftLen<SP>::value > 0 ? 2 : 1;
     const int nk = p->kmax + 1;
     const int nblk = (nk + KP - 1) / KP * p->rows;
-    const size_t lds = sizeof(double2) * ((size_t)p->nphi + FftRun<1, NT, PT, SP>::ntw);
+    constexpr int ntw = FftRun<1, NT, PT, SP>::ntw;
     if (p->mid32) {
+        const size_t lds = (FftLen<SP>::value > 0 ? sizeof(float2) : sizeof(double2)) * (size_t)p->nphi +
+                           sizeof(double2) * ntw;
         auto kern = k_phi_synthesis<T, NT, PT, SP, KP, float2>;
         hipError_t e = sc_set_lds_attr((const void *)kern, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, p->stream, (const float2 *)p->G, (T *)p->maps, p->lmax,
                            p->rows, p->gst, p->cols, p->ncp, p->W, nk, p->pphi, p->twphi);
     } else {
+        const size_t lds = sizeof(double2) * ((size_t)p->nphi + ntw);
         auto kern = k_phi_synthesis<T, NT, PT, SP, KP, double2>;
         hipError_t e = sc_set_lds_attr((const void *)kern, lds);
         if (e != hipSuccess) return e;
