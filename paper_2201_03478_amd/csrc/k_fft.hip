@@ -66,7 +66,8 @@ __device__ inline void store_quad<double>(double *o, double a, double b, double 
 // variant that walks consecutive pairs and prefetches the next pair's columns
 // measured slower at lmax 512 than one pair per workgroup.)
 template <int NT, int PT, typename S2, typename SOS, typename FT, typename GT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(GT) == sizeof(float2) ? (NT > 256 ? 5 : 6) : 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    FftLen<S2>::value > 0 && FftLen<SOS>::value > 0 && sizeof(GT) == sizeof(float2) ? (NT > 256 ? 5 : 6) : 4)))
 k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nring, int rows, int gst,
                  int W, FftPlan P2, FftPlan Pos, const double2 *__restrict__ tw2,
                  const double2 *__restrict__ twos, const double2 *__restrict__ phase,
@@ -215,7 +216,8 @@ __device__ __forceinline__ void phi_scatter(BT *A, const GT (&spec)[MAXC], int t
 // wait in registers, so each lane writes both k's component pairs of a column as
 // one 16-byte store (a column's map record is contiguous in k).
 template <typename T, int NT, int PT, typename SP, int KP, typename GT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(GT) == sizeof(float2) ? 5 : 4)))
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(FftLen<SP>::value > 0 && sizeof(GT) == sizeof(float2) && NT <= 256 ? 5 : 4)))
 k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int rows, int gst, int cols, int ncp,
                 int W, int nk, FftPlan Pp, const double2 *__restrict__ twp) {
     static_assert(KP == 1 || KP == 2, "one or two k per workgroup");

@@ -144,9 +144,8 @@ k_ring_sums(const double2 *__restrict__ alm, const double2 *__restrict__ blm, FT
     __shared__ double cA[64], cB[2 * 64];
     __shared__ double2 cWp[64], cWm[64];
 
-    int b = blockIdx.x;
-    const int g = b % ngroups;
-    b /= ngroups;
+    int b, g;  // b = column m (kmax + 1) + k
+    xcd_column_group(blockIdx.x, (lmax + 1) * (kmax + 1), ngroups, b, g);
     const int k = b % (kmax + 1);
     const int m = b / (kmax + 1);
     const int lane = threadIdx.x;

@@ -88,9 +88,8 @@ k_ring_sums_mixed(const double2 *__restrict__ alm, const double2 *__restrict__ b
     __shared__ float cW[64 * 4];
     __shared__ double Fs[RPT][64][4];
 
-    int b = blockIdx.x;
-    const int g = b % ngroups;
-    b /= ngroups;
+    int b, g;  // b = column m (kmax + 1) + k
+    xcd_column_group(blockIdx.x, (lmax + 1) * (kmax + 1), ngroups, b, g);
     const int k = b % (kmax + 1);
     const int m = b / (kmax + 1);
     const int lane = threadIdx.x;

@@ -273,6 +273,24 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// Blocks (column, ring group) of a launch with ng groups per column: the ng
+// blocks of one column run on one XCD at about the same time, so the column's
+// coefficients and weights are fetched from HBM once and the other groups find
+// them in that XCD's L2; consecutive columns go round-robin over the XCDs.
+__device__ __forceinline__ void xcd_column_group(int b, int ncol, int ng, int &col, int &g) {
+    const int span = 8 * ng;
+    const int full = (ncol >> 3) * span;  // blocks of whole 8-column chunks
+    if (b < full) {
+        const int c8 = b / span, r = b - c8 * span;
+        g = r >> 3;
+        col = 8 * c8 + (r & 7);  // XCD b % 8 = col % 8 for every group
+    } else {
+        const int r = b - full;
+        col = (ncol & ~7) + r / ng;
+        g = r - (r / ng) * ng;
+    }
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
