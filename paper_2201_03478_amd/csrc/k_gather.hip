@@ -384,11 +384,12 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
         const int ns = item.z - ch < GCH ? item.z - ch : GCH;
         {
             const float fu = (float)pf_u, fv = (float)pf_v;
+            const float nbl = -D.beta * 1.44269504088896341f;  // -beta log2(e)
 #pragma unroll
             for (int i = 0; i < 16 * GCH / NT; ++i) {
                 const int q = (tid >> 7) + (NT / GCH) * i;  // NT threads cover NT / GCH weight rows per step
                 float w = 0.f;
-                if (sw < ns) w = es_weight<float>(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, D.beta);
+                if (sw < ns) w = es_weight_f32(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, nbl);
                 W1[q * GW1 + sw] = w;
             }
         }
@@ -613,11 +614,12 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
         const int ns = item.z - ch < GCH ? item.z - ch : GCH;
         {
             const float fu = (float)pf_u, fv = (float)pf_v;
+            const float nbl = -D.beta * 1.44269504088896341f;  // -beta log2(e)
 #pragma unroll
             for (int i = 0; i < 16 * GCH / NT; ++i) {
                 const int q = (tid >> 7) + (NT / GCH) * i;
                 float w = 0.f;
-                if (sw < ns) w = es_weight<float>(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, D.beta);
+                if (sw < ns) w = es_weight_f32(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, nbl);
                 W1[q * GW1 + sw] = w;
             }
         }

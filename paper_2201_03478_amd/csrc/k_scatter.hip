@@ -124,7 +124,7 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
     const int nitems = totals[1];
-    const float fbeta = (float)beta;
+    const float nbl = -(float)beta * 1.44269504088896341f;  // -beta log2(e)
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
         __syncthreads();
@@ -158,7 +158,7 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
                 float w = 0.f;
                 if (sl < ns) {
                     const float2 uv = UV[sl];
-                    w = es_w<float>(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                    w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
                 }
                 W1[q * W1ROW + sl] = w;
             }
@@ -260,7 +260,7 @@ k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const 
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
     const int nitems = totals[1];
-    const float fbeta = (float)beta;
+    const float nbl = -(float)beta * 1.44269504088896341f;  // -beta log2(e)
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
         __syncthreads();
@@ -300,7 +300,7 @@ k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const 
                 float w = 0.f;
                 if (sl < ns) {
                     const float2 uv = UV[sl];
-                    w = es_w<float>(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, fbeta);
+                    w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
                 }
                 W1[q * W1ROW + sl] = w;
             }

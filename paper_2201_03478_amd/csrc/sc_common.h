@@ -291,6 +291,20 @@ __device__ __forceinline__ void xcd_column_group(int b, int ncol, int ng, int &c
     }
 }
 
+// Exponential-of-semicircle tap weight in FP32, exp(beta (sqrt(1 - z^2) - 1)) for |z| < 1
+// and 0 outside, evaluated as 2^(-beta log2(e) z^2 / (1 + sqrt(1 - z^2))): the same function
+// without the cancellation of sqrt(1 - z^2) - 1 next to z = 0, where the weights are largest.
+// nbl = -beta log2(e).  Hardware square root, reciprocal and exp2 (about 1 ulp each): the
+// exponent carries a relative error of a few ulp, so the weight's relative error is below
+// 1e-7 plus 2.4e-7 times its |log2|, i.e. an absolute error under 1e-7 at every z.
+__device__ __forceinline__ float es_weight_f32(float z, float nbl) {
+    const float z2 = z * z;
+    const float q = __builtin_fmaf(-z, z, 1.f);
+    if (!(q > 0.f)) return 0.f;
+    const float s = __builtin_amdgcn_sqrtf(q);
+    return __builtin_amdgcn_exp2f(nbl * z2 * __builtin_amdgcn_rcpf(1.f + s));
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
