@@ -20,10 +20,12 @@ namespace {
 
 int ct_class(int ncomp);
 
+// exp(beta (sqrt(1 - z^2) - 1)) as exp(-beta z^2 / (1 + sqrt(1 - z^2))): no cancellation next to
+// z = 0, where the weights are largest
 template <typename T>
 __device__ __forceinline__ T es_weight(T z, T beta) {
-    const T q = (T)1 - z * z;
-    return q > (T)0 ? exp(beta * (sqrt(q) - (T)1)) : (T)0;
+    const T z2 = z * z, q = (T)1 - z2;
+    return q > (T)0 ? exp(-beta * z2 / ((T)1 + sqrt(q))) : (T)0;
 }
 
 template <typename T>

@@ -33,9 +33,10 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+// exp(beta (sqrt(1 - z^2) - 1)) without the cancellation next to z = 0
 __device__ __forceinline__ double es_weight64(double z, double beta) {
-    const double q = 1.0 - z * z;
-    return q > 0.0 ? exp(beta * (sqrt(q) - 1.0)) : 0.0;
+    const double z2 = z * z, q = 1.0 - z2;
+    return q > 0.0 ? exp(-beta * z2 / (1.0 + sqrt(q))) : 0.0;
 }
 
 template <int W, int CTC, int STW>

@@ -128,10 +128,11 @@ k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int n
     }
 }
 
+// exp(beta (sqrt(1 - z^2) - 1)) without the cancellation next to z = 0
 template <typename T>
 __device__ __forceinline__ T es_w(T z, T beta) {
-    const T q = (T)1 - z * z;
-    return q > (T)0 ? exp(beta * (sqrt(q) - (T)1)) : (T)0;
+    const T z2 = z * z, q = (T)1 - z2;
+    return q > (T)0 ? exp(-beta * z2 / ((T)1 + sqrt(q))) : (T)0;
 }
 
 // Grid coordinate in [0, n) of an angle on a periodic grid of n points.
