@@ -201,6 +201,7 @@ def main():
 
     import workloads as W
     from paper_2201_03478_amd import api
+    from paper_2201_03478_amd import _native as N
 
     dev = torch.device("cuda", 0)
     cfg = W.CONFIGS["sidelobe-lmax512-kmax100"]
@@ -255,7 +256,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if prec == 1 else "f64",
+        # FP64 synthesis; the FP32-map gather's products are split FP16/FP8 (FP32-accurate, FP32 accumulation)
+        "dtype": ("f64+f16/f8split" if plan.get_param("gather_mma") == N.SC_MMA_SPLIT16 else "f64+f32")
+        if prec == 1 else "f64",
         "data": "synthetic",
         "config": {
             "workload": workload_name,
