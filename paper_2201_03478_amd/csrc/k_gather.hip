@@ -15,6 +15,12 @@
 #include "sc_common.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+#ifndef GATHER_RUN_DIV
+#define GATHER_RUN_DIV 64
+#endif
+#ifndef GATHER_SLIDE
+#define GATHER_SLIDE true
+#endif
 
 namespace {
 
@@ -526,8 +532,24 @@ __device__ __forceinline__ long pack_fp8x8(const float (&f)[8]) {
     return (long)(((unsigned long)(unsigned)w1 << 32) | (unsigned)w0);
 }
 
-template <int CT, int NWV>
-__device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax) {
+// Block reuse between consecutive items of one workgroup (LDS).  Work items come
+// in anchor order, and the next anchor is usually the next column of the same map
+// row, so its 8 x 8 block shares seven columns with the staged one.  The staged
+// block keeps its columns in slots: map column c sits in element c mod 8 of every
+// operand vector (the phi weight rows of W1 are permuted to match), so moving one
+// column on replaces one slot.  Each item's block is split with the scale of its
+// own maximum, as a freshly staged block is (the per-slot maxima are kept), so the
+// products and the result do not depend on which items a workgroup took before.
+struct SlideLds {
+    int key;              // anchor of the staged block (-2: none)
+    int e;                // its scale exponent (block maximum < 2^e)
+    unsigned smax8[8];    // maximum |value| of each slot's column (float bits)
+    unsigned wmax[8][8];  // per-wave slot maxima while a block is staged
+};
+
+template <int CT, int NWV, bool SLIDE = false>
+__device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax,
+                                                  SlideLds *sl = nullptr, bool reuse = false) {
     constexpr int NT = 64 * NWV;
     constexpr int TPW = 8 / NWV;
     constexpr int NC = 16 * CT;
@@ -560,7 +582,75 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
         }
     }
     float oscale;
-    {
+    int e = 0;
+    bool restage = true;
+    // slot of map column col0 + j (j < 8): element j, or (col0 + j) mod 8 with block reuse
+    const bool track = SLIDE && reuse;  // slot order and block reuse (uniform)
+    const int c7 = track ? (col0 & 7) : 0;
+    if (track) {
+        const int skey = sl->key;
+        if (item.x == skey) {
+            restage = false;  // the same anchor (a large one split into several items)
+            e = sl->e;
+        } else if (item.x == skey + 1 && col0 != 0) {
+            // one column on: stage column col0 + 7 into slot (col0 + 7) mod 8, unless the
+            // block's scale changes
+            const int snew = (col0 + 7) & 7;
+            constexpr int NU1 = 8 * NC4;  // (map row, 4 components) units of one column
+            constexpr int UP1 = (NU1 + NT - 1) / NT;
+            floatx4 nv[UP1];
+            float m = 0.f;
+#pragma unroll
+            for (int k = 0; k < UP1; ++k) {
+                const int u = tid + k * NT;
+                nv[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+                if (u < NU1) {
+                    const int i = u / NC4, c4 = u - i * NC4;
+                    nv[k] = ((const floatx4 *)(D.maps + ((size_t)(row0 + i) * D.cols + col0 + 7) * NC))[c4];
+                }
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(nv[k][0]), fabsf(nv[k][1])), fmaxf(fabsf(nv[k][2]), fabsf(nv[k][3]))));
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+            if (lane == 0) atomicMax(smax, __float_as_uint(m));
+            __syncthreads();
+            const unsigned mnew = *smax;
+            unsigned mb = mnew;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j != snew) mb = max(mb, sl->smax8[j]);
+            int eb;
+            (void)frexpf(__uint_as_float(mb), &eb);
+            if (eb == sl->e) {
+                restage = false;
+                e = eb;
+                const float ms = ldexpf(1.f, 15 - e);
+#pragma unroll
+                for (int k = 0; k < UP1; ++k) {
+                    const int u = tid + k * NT;
+                    if (u < NU1) {
+                        const int i = u / NC4, c4 = u - i * NC4;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int c = 4 * c4 + q;
+                            const float x = as_is(nv[k][q] * ms);  // the same split as a staged block's
+                            const _Float16 h1 = (_Float16)x;
+                            const float r1 = as_is(x - (float)h1);
+                            const _Float16 h2 = (_Float16)r1;
+                            const float rm = (r1 - (float)h2) * SPLIT_RSCALE;
+                            const int o = ((i >> 2) * CT + (c >> 4)) * 64 + (i & 3) * 16 + (c & 15);
+                            ((_Float16 *)(Ahi + o))[snew] = h1;
+                            ((_Float16 *)(Alo + o))[snew] = h2;
+                            ((unsigned char *)(Arm + o))[snew] =
+                                (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(rm, 0.f, 0, false) & 0xff);
+                        }
+                    }
+                }
+                if (tid == 0) sl->smax8[snew] = mnew;  // no thread reads this slot's entry again before a barrier
+            }
+        }
+    }
+    if (restage) {
         floatx4 v[UPT][8];
         float m = 0.f;
 #pragma unroll
@@ -571,19 +661,50 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
             if (u < NU) {
                 const int i = u / NC4, c4 = u - i * NC4;
                 const floatx4 *s4 = (const floatx4 *)(D.maps + ((size_t)(row0 + i) * D.cols + col0) * NC) + c4;
+                // slot j holds map column col0 + ((j - col0) mod 8)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[k][j] = s4[j * NC4];
+                for (int j = 0; j < 8; ++j) v[k][j] = s4[((j - c7) & 7) * NC4];
             }
+            if (!track) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                m = fmaxf(m, fmaxf(fmaxf(fabsf(v[k][j][0]), fabsf(v[k][j][1])), fmaxf(fabsf(v[k][j][2]), fabsf(v[k][j][3]))));
+                for (int j = 0; j < 8; ++j)
+                    m = fmaxf(m, fmaxf(fmaxf(fabsf(v[k][j][0]), fabsf(v[k][j][1])),
+                                       fmaxf(fabsf(v[k][j][2]), fabsf(v[k][j][3]))));
+            }
         }
+        if (track) {
+            // per-slot maxima (a wave reduction per slot), kept for the next items
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-        if (lane == 0) atomicMax(smax, __float_as_uint(m));  // non-negative floats order as their bits
-        __syncthreads();
-        int e;
-        (void)frexpf(__uint_as_float(*smax), &e);  // block maximum < 2^e
+            for (int j = 0; j < 8; ++j) {
+                float mj = 0.f;
+#pragma unroll
+                for (int k = 0; k < UPT; ++k)
+                    mj = fmaxf(mj, fmaxf(fmaxf(fabsf(v[k][j][0]), fabsf(v[k][j][1])),
+                                         fmaxf(fabsf(v[k][j][2]), fabsf(v[k][j][3]))));
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off));
+                if (lane == 0) sl->wmax[wv][j] = __float_as_uint(mj);
+            }
+            __syncthreads();
+            unsigned mb = 0u;
+#pragma unroll
+            for (int w = 0; w < NWV; ++w)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) mb = max(mb, sl->wmax[w][j]);
+            if (tid < 8) {
+                unsigned mj = 0u;
+#pragma unroll
+                for (int w = 0; w < NWV; ++w) mj = max(mj, sl->wmax[w][tid]);
+                sl->smax8[tid] = mj;
+            }
+            (void)frexpf(__uint_as_float(mb), &e);  // block maximum < 2^e
+        } else {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+            if (lane == 0) atomicMax(smax, __float_as_uint(m));  // non-negative floats order as their bits
+            __syncthreads();
+            (void)frexpf(__uint_as_float(*smax), &e);  // block maximum < 2^e
+        }
         const float ms = ldexpf(1.f, 15 - e);
         oscale = ldexpf(1.f, e - 15) * (1.f / SPLIT_WSCALE);
 #pragma unroll
@@ -612,17 +733,26 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
             }
         }
     }
+    if (track) {
+        if (!restage) oscale = ldexpf(1.f, e - 15) * (1.f / SPLIT_WSCALE);
+        if (tid == 0) {  // read by the next item after the barriers below
+            sl->key = item.x;
+            sl->e = e;
+        }
+    }
     for (int ch = 0; ch < item.z; ch += GCH) {
         const int ns = item.z - ch < GCH ? item.z - ch : GCH;
         {
             const float fu = (float)pf_u, fv = (float)pf_v;
             const float nbl = -D.beta * 1.44269504088896341f;  // -beta log2(e)
+            // col0 mod 8 (recomputed from the item, not held across the staging)
+            const int cslot = track ? ((item.x - (item.x / D.nkc) * D.nkc) & 7) : 0;
 #pragma unroll
             for (int i = 0; i < 16 * GCH / NT; ++i) {
                 const int q = (tid >> 7) + (NT / GCH) * i;
                 float w = 0.f;
                 if (sw < ns) w = es_weight_f32(((q < 8 ? fu : fv) + (float)(3 - (q & 7))) * 0.25f, nbl);
-                W1[q * GW1 + sw] = w;
+                W1[(track && q >= 8 ? 8 + ((q + cslot) & 7) : q) * GW1 + sw] = w;  // phi factor of column col0 + j: slot row
             }
         }
         if (tid < GCH) {
@@ -728,10 +858,11 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
     }
 }
 
-template <int CT, int NWV, int MM>
-__device__ __forceinline__ void gather_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax) {
+template <int CT, int NWV, int MM, bool SLIDE = false>
+__device__ __forceinline__ void gather_item(const GatherDet &D, const int4 item, double *smem_d, unsigned *smax,
+                                            SlideLds *sl = nullptr, bool reuse = false) {
     if constexpr (MM == SC_MMA_SPLIT16)
-        gather_split_item<CT, NWV>(D, item, smem_d, smax);
+        gather_split_item<CT, NWV, SLIDE>(D, item, smem_d, smax, sl, reuse);
     else
         gather_mfma_item<CT, NWV>(D, item, smem_d);
 }
@@ -745,24 +876,58 @@ __global__ void __launch_bounds__(64 * NWV, NWV / 2)
 k_gather_mfma(GatherDet D, int *__restrict__ cursor) {
     extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte operands
     __shared__ int item_sh;
-    __shared__ unsigned smax;  // block maximum of the split form, cleared before every item
+    __shared__ unsigned smax;  // block / new-column maximum of the split form, cleared before every item
     const int nitems = D.totals[1];
-    if (threadIdx.x == 0) {
-        item_sh = atomicAdd(cursor, 1);
-        smax = 0u;
-    }
-    __syncthreads();
-    int it = item_sh;
-    while (it < nitems) {
-        int nxt = 0;
-        if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
-        gather_item<CT, NWV, MM>(D, D.items[it], smem_d, &smax);  // ends with a barrier
+    // Up to 8 component tiles (where the registers fit beside the accumulators), the
+    // split form takes its items in runs of consecutive ones when there are many
+    // short items (over ~64 per workgroup): one queue atomic per run instead of per
+    // item (the single counter is contended otherwise), and since consecutive items
+    // are mostly neighbouring anchors the run reuses the staged block.
+    constexpr bool SL = GATHER_SLIDE && MM == SC_MMA_SPLIT16 && CT <= 8;
+    if constexpr (SL) {
+        __shared__ SlideLds sl;  // the staged block
+        int run = nitems / (GATHER_RUN_DIV * (int)gridDim.x);
+        run = run < 1 ? 1 : (run > 32 ? 32 : run);
+        const bool reuse = run > 1;
         if (threadIdx.x == 0) {
-            item_sh = nxt;
+            item_sh = atomicAdd(cursor, run);
+            smax = 0u;
+            sl.key = -2;
+            sl.e = 0;
+        }
+        __syncthreads();
+        int it = __builtin_amdgcn_readfirstlane(item_sh);
+        while (it < nitems) {
+            int nxt = 0;
+            if (threadIdx.x == 0) nxt = atomicAdd(cursor, run);  // the next run, taken while this one runs
+            const int iend = __builtin_amdgcn_readfirstlane(it + run < nitems ? it + run : nitems);
+            for (int j = it; j < iend; ++j) {
+                gather_item<CT, NWV, MM, true>(D, D.items[j], smem_d, &smax, &sl, reuse);  // ends with a barrier
+                if (threadIdx.x == 0) smax = 0u;
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) item_sh = nxt;
+            __syncthreads();
+            it = __builtin_amdgcn_readfirstlane(item_sh);
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            item_sh = atomicAdd(cursor, 1);
             smax = 0u;
         }
         __syncthreads();
-        it = item_sh;
+        int it = item_sh;
+        while (it < nitems) {
+            int nxt = 0;
+            if (threadIdx.x == 0) nxt = atomicAdd(cursor, 1);  // the next item, taken while this one runs
+            gather_item<CT, NWV, MM>(D, D.items[it], smem_d, &smax);  // ends with a barrier
+            if (threadIdx.x == 0) {
+                item_sh = nxt;
+                smax = 0u;
+            }
+            __syncthreads();
+            it = item_sh;
+        }
     }
 }
 
