@@ -126,97 +126,104 @@ k_scatter_mfma(const int4 *__restrict__ items, int *__restrict__ totals, const A
     const int r = lane & 15, grp = lane >> 4;
     const int nitems = totals[1];
     const float nbl = -(float)beta * 1.44269504088896341f;  // -beta log2(e)
+    // with many items (over ~64 per workgroup) they are taken in runs of consecutive
+    // ones, one queue atomic per run (the single counter is contended otherwise)
+    int run = nitems / (64 * (int)gridDim.x);
+    run = run < 1 ? 1 : (run > 32 ? 32 : run);
     for (;;) {
-        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
+        if (tid == 0) item_sh = atomicAdd(&totals[2], run);
         __syncthreads();
-        const int it = item_sh;
-        if (it >= nitems) break;
-        const int4 item = items[it];
-        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
-        floatx4 acc[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int ch = 0; ch < item.z; ch += 64) {
-            const int ns = item.z - ch < 64 ? item.z - ch : 64;
-            if (tid < 64) {
-                double2 e1 = make_double2(1.0, 0.0);
-                float2 uv = make_float2(0.f, 0.f);
-                float yy = 0.f;
-                if (tid < ns) {
-                    const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
-                    const AdjRec q = rec[pos];
-                    e1 = make_double2(q.cps, q.sps);
-                    uv = make_float2(q.fu, q.fv);
-                    yy = q.y;
-                }
-                E1[tid] = e1;
-                UV[tid] = uv;
-                Ys[tid] = yy;
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * 16; e += 256) {
-                const int q = e >> 6, sl = e & 63;
-                float w = 0.f;
-                if (sl < ns) {
-                    const float2 uv = UV[sl];
-                    w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
-                }
-                W1[q * W1ROW + sl] = w;
-            }
-            {
-                // V[s][c] = y_s basis_c(psi_s): 4 lanes per sample, NC/4 components each
-                const int sl = tid >> 2, qq = tid & 3;
-                constexpr int PER = NC / 4;
-                const int c0 = qq * PER;
-                const double2 e1 = E1[sl];
-                const float yy = Ys[sl];
-                int kc = c0 >> 1;  // PER is even: the range starts on a cos/sin pair
-                double2 z = cpow_int(e1, kc);
-                float *vrow = Vsh + sl * NC;
-                for (int j = 0; j < PER; ++j) {
-                    const int c = c0 + j;
-                    float vv = 0.f;
-                    if (c < ncomp) {
-                        if ((c >> 1) > kc) {
-                            z = cmul(z, e1);
-                            ++kc;
-                        }
-                        vv = yy * (float)((c & 1) ? z.y : z.x);
+        const int i0 = __builtin_amdgcn_readfirstlane(item_sh);  // read before the first barrier below
+        if (i0 >= nitems) break;
+        const int iend = i0 + run < nitems ? i0 + run : nitems;
+        for (int it = i0; it < iend; ++it) {
+            const int4 item = items[it];
+            const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
+            floatx4 acc[CT];
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int ch = 0; ch < item.z; ch += 64) {
+                const int ns = item.z - ch < 64 ? item.z - ch : 64;
+                if (tid < 64) {
+                    double2 e1 = make_double2(1.0, 0.0);
+                    float2 uv = make_float2(0.f, 0.f);
+                    float yy = 0.f;
+                    if (tid < ns) {
+                        const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
+                        const AdjRec q = rec[pos];
+                        e1 = make_double2(q.cps, q.sps);
+                        uv = make_float2(q.fu, q.fv);
+                        yy = q.y;
                     }
-                    vrow[c] = vv;
+                    E1[tid] = e1;
+                    UV[tid] = uv;
+                    Ys[tid] = yy;
                 }
+                __syncthreads();
+                for (int e = tid; e < 64 * 16; e += 256) {
+                    const int q = e >> 6, sl = e & 63;
+                    float w = 0.f;
+                    if (sl < ns) {
+                        const float2 uv = UV[sl];
+                        w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
+                    }
+                    W1[q * W1ROW + sl] = w;
+                }
+                {
+                    // V[s][c] = y_s basis_c(psi_s): 4 lanes per sample, NC/4 components each
+                    const int sl = tid >> 2, qq = tid & 3;
+                    constexpr int PER = NC / 4;
+                    const int c0 = qq * PER;
+                    const double2 e1 = E1[sl];
+                    const float yy = Ys[sl];
+                    int kc = c0 >> 1;  // PER is even: the range starts on a cos/sin pair
+                    double2 z = cpow_int(e1, kc);
+                    float *vrow = Vsh + sl * NC;
+                    for (int j = 0; j < PER; ++j) {
+                        const int c = c0 + j;
+                        float vv = 0.f;
+                        if (c < ncomp) {
+                            if ((c >> 1) > kc) {
+                                z = cmul(z, e1);
+                                ++kc;
+                            }
+                            vv = yy * (float)((c & 1) ? z.y : z.x);
+                        }
+                        vrow[c] = vv;
+                    }
+                }
+                __syncthreads();
+                // PG[tap][c] += sum_s W[tap][s] V[s][c] with W[tap][s] = w_theta_s(tap / 8) w_phi_s(tap % 8)
+                // formed from the 1-d weights as the operand is read; wave wv owns taps 16 wv .. 16 wv + 15
+                const int tap = 16 * wv + r;
+                const float *wth = W1 + (tap >> 3) * W1ROW + grp;  // A[i = tap r][k = sample grp]
+                const float *wph = W1 + (8 + (tap & 7)) * W1ROW + grp;
+                const float *vb = Vsh + grp * NC + r;               // B[k = sample grp][j = comp r]
+    #pragma unroll 4
+                for (int ks = 0; ks < 16; ++ks) {
+                    const float a = wth[4 * ks] * wph[4 * ks];
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct)
+                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, vb[4 * ks * NC + 16 * ct], acc[ct], 0, 0, 0);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            // PG[tap][c] += sum_s W[tap][s] V[s][c] with W[tap][s] = w_theta_s(tap / 8) w_phi_s(tap % 8)
-            // formed from the 1-d weights as the operand is read; wave wv owns taps 16 wv .. 16 wv + 15
-            const int tap = 16 * wv + r;
-            const float *wth = W1 + (tap >> 3) * W1ROW + grp;  // A[i = tap r][k = sample grp]
-            const float *wph = W1 + (8 + (tap & 7)) * W1ROW + grp;
-            const float *vb = Vsh + grp * NC + r;               // B[k = sample grp][j = comp r]
-#pragma unroll 4
-            for (int ks = 0; ks < 16; ++ks) {
-                const float a = wth[4 * ks] * wph[4 * ks];
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
-                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, vb[4 * ks * NC + 16 * ct], acc[ct], 0, 0, 0);
-            }
-            __syncthreads();
-        }
-        // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int t = 16 * wv + 4 * grp + v;
-            if constexpr (DET) {
-                // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
-                float *dst = pg + ((size_t)it * 64 + t) * NC;
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
-            } else {
-                float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                    const int c = 16 * ct + r;
-                    if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+            // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
+    #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = 16 * wv + 4 * grp + v;
+                if constexpr (DET) {
+                    // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
+                    float *dst = pg + ((size_t)it * 64 + t) * NC;
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
+                } else {
+                    float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        const int c = 16 * ct + r;
+                        if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                    }
                 }
             }
         }
@@ -262,125 +269,132 @@ k_scatter_split(const int4 *__restrict__ items, int *__restrict__ totals, const 
     const int r = lane & 15, grp = lane >> 4;
     const int nitems = totals[1];
     const float nbl = -(float)beta * 1.44269504088896341f;  // -beta log2(e)
+    // with many items (over ~64 per workgroup) they are taken in runs of consecutive
+    // ones, one queue atomic per run (the single counter is contended otherwise)
+    int run = nitems / (64 * (int)gridDim.x);
+    run = run < 1 ? 1 : (run > 32 ? 32 : run);
     for (;;) {
-        if (tid == 0) item_sh = atomicAdd(&totals[2], 1);
+        if (tid == 0) item_sh = atomicAdd(&totals[2], run);
         __syncthreads();
-        const int it = item_sh;
-        if (it >= nitems) break;
-        const int4 item = items[it];
-        const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
-        floatx4 acc[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int ch = 0; ch < item.z; ch += 64) {
-            const int ns = item.z - ch < 64 ? item.z - ch : 64;
-            if (tid < 64) {  // one wave: one sample per lane
-                double2 e1 = make_double2(1.0, 0.0);
-                float2 uv = make_float2(0.f, 0.f);
-                float yy = 0.f;
-                if (tid < ns) {
-                    const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
-                    const AdjRec q = rec[pos];
-                    e1 = make_double2(q.cps, q.sps);
-                    uv = make_float2(q.fu, q.fv);
-                    yy = q.y;
-                }
-                float m = fabsf(yy);
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-                int e = 0;
-                if (m > 0.f) (void)frexpf(m, &e);  // m < 2^e
-                E1[tid] = e1;
-                UV[tid] = uv;
-                Ys[tid] = ldexpf(yy, 14 - e);  // exact
-                if (tid == 0) osc_sh = ldexpf(1.f, e - 28);
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * 16; e += 256) {
-                const int q = e >> 6, sl = e & 63;
-                float w = 0.f;
-                if (sl < ns) {
-                    const float2 uv = UV[sl];
-                    w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
-                }
-                W1[q * W1ROW + sl] = w;
-            }
-            {
-                // V[s][c] = y_s basis_c(psi_s) (scaled), split and written in the B layout:
-                // sample s -> half s / 32, lane group (s % 32) / 8, element s % 8; component c ->
-                // tile c / 16, lane c % 16.  4 lanes per sample; lane qq takes the orders
-                // k = qq + 4 j (components 2k, 2k + 1: tile j / 2, lanes 2 qq + 8 (j % 2) and
-                // the next), so its offsets are compile-time after the base, and steps the
-                // phase by e^{4 i psi}.
-                const int sl = tid >> 2, qq = tid & 3;
-                const double2 e1 = E1[sl];
-                const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
-                double2 z = qq == 0 ? make_double2(1.0, 0.0) : qq == 1 ? e1 : qq == 2 ? e2 : cmul(e2, e1);
-                const float yy = Ys[sl];
-                const int base = ((sl >> 5) * CT * 64 + 16 * ((sl & 31) >> 3)) * 8 + (sl & 7) + 16 * qq;
-                _Float16 *bh = (_Float16 *)Bhi + base, *bl = (_Float16 *)Blo + base;
-#pragma unroll
-                for (int j = 0; j < 2 * CT; ++j) {
-                    const int k = qq + 4 * j;
-                    const float vc = 2 * k < ncomp ? yy * (float)z.x : 0.f;
-                    const float vs = 2 * k + 1 < ncomp ? yy * (float)z.y : 0.f;
-                    const int o = (j >> 1) * 512 + 64 * (j & 1);
-                    const _Float16 hc = (_Float16)vc, hs = (_Float16)vs;
-                    bh[o] = hc;
-                    bl[o] = (_Float16)(vc - (float)hc);
-                    bh[o + 8] = hs;
-                    bl[o + 8] = (_Float16)(vs - (float)hs);
-                    z = cmul(z, e4);
-                }
-            }
-            __syncthreads();
-            {
-                // A: wave wv's taps 16 wv + r, samples 32 kh + 8 grp + q
-                const int tap = 16 * wv + r;
-                const float *wth = W1 + (tap >> 3) * W1ROW + 8 * grp;
-                const float *wph = W1 + (8 + (tap & 7)) * W1ROW + 8 * grp;
-                half8 ah[2], al[2];
-#pragma unroll
-                for (int kh = 0; kh < 2; ++kh)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const float w = wth[32 * kh + q] * wph[32 * kh + q] * 16384.f;
-                        const _Float16 h = (_Float16)w;
-                        ah[kh][q] = h;
-                        al[kh][q] = (_Float16)(w - (float)h);
+        const int i0 = __builtin_amdgcn_readfirstlane(item_sh);  // read before the first barrier below
+        if (i0 >= nitems) break;
+        const int iend = i0 + run < nitems ? i0 + run : nitems;
+        for (int it = i0; it < iend; ++it) {
+            const int4 item = items[it];
+            const int row0 = item.x / nkc, col0 = item.x - (item.x / nkc) * nkc;
+            floatx4 acc[CT];
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int ch = 0; ch < item.z; ch += 64) {
+                const int ns = item.z - ch < 64 ? item.z - ch : 64;
+                if (tid < 64) {  // one wave: one sample per lane
+                    double2 e1 = make_double2(1.0, 0.0);
+                    float2 uv = make_float2(0.f, 0.f);
+                    float yy = 0.f;
+                    if (tid < ns) {
+                        const int pos = DET ? perm[item.y + ch + tid] : item.y + ch + tid;
+                        const AdjRec q = rec[pos];
+                        e1 = make_double2(q.cps, q.sps);
+                        uv = make_float2(q.fu, q.fv);
+                        yy = q.y;
                     }
-                const float osc = osc_sh;
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                    floatx4 t = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int kh = 0; kh < 2; ++kh) {
-                        const half8 bh = Bhi[(kh * CT + ct) * 64 + lane], bl = Blo[(kh * CT + ct) * 64 + lane];
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kh], bh, t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bl, t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bh, t, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[ct][v] = fmaf(t[v], osc, acc[ct][v]);
+                    float m = fabsf(yy);
+    #pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+                    int e = 0;
+                    if (m > 0.f) (void)frexpf(m, &e);  // m < 2^e
+                    E1[tid] = e1;
+                    UV[tid] = uv;
+                    Ys[tid] = ldexpf(yy, 14 - e);  // exact
+                    if (tid == 0) osc_sh = ldexpf(1.f, e - 28);
                 }
+                __syncthreads();
+                for (int e = tid; e < 64 * 16; e += 256) {
+                    const int q = e >> 6, sl = e & 63;
+                    float w = 0.f;
+                    if (sl < ns) {
+                        const float2 uv = UV[sl];
+                        w = es_weight_f32(((q < 8 ? uv.x : uv.y) + (float)(3 - (q & 7))) * 0.25f, nbl);
+                    }
+                    W1[q * W1ROW + sl] = w;
+                }
+                {
+                    // V[s][c] = y_s basis_c(psi_s) (scaled), split and written in the B layout:
+                    // sample s -> half s / 32, lane group (s % 32) / 8, element s % 8; component c ->
+                    // tile c / 16, lane c % 16.  4 lanes per sample; lane qq takes the orders
+                    // k = qq + 4 j (components 2k, 2k + 1: tile j / 2, lanes 2 qq + 8 (j % 2) and
+                    // the next), so its offsets are compile-time after the base, and steps the
+                    // phase by e^{4 i psi}.
+                    const int sl = tid >> 2, qq = tid & 3;
+                    const double2 e1 = E1[sl];
+                    const double2 e2 = cmul(e1, e1), e4 = cmul(e2, e2);
+                    double2 z = qq == 0 ? make_double2(1.0, 0.0) : qq == 1 ? e1 : qq == 2 ? e2 : cmul(e2, e1);
+                    const float yy = Ys[sl];
+                    const int base = ((sl >> 5) * CT * 64 + 16 * ((sl & 31) >> 3)) * 8 + (sl & 7) + 16 * qq;
+                    _Float16 *bh = (_Float16 *)Bhi + base, *bl = (_Float16 *)Blo + base;
+    #pragma unroll
+                    for (int j = 0; j < 2 * CT; ++j) {
+                        const int k = qq + 4 * j;
+                        const float vc = 2 * k < ncomp ? yy * (float)z.x : 0.f;
+                        const float vs = 2 * k + 1 < ncomp ? yy * (float)z.y : 0.f;
+                        const int o = (j >> 1) * 512 + 64 * (j & 1);
+                        const _Float16 hc = (_Float16)vc, hs = (_Float16)vs;
+                        bh[o] = hc;
+                        bl[o] = (_Float16)(vc - (float)hc);
+                        bh[o + 8] = hs;
+                        bl[o + 8] = (_Float16)(vs - (float)hs);
+                        z = cmul(z, e4);
+                    }
+                }
+                __syncthreads();
+                {
+                    // A: wave wv's taps 16 wv + r, samples 32 kh + 8 grp + q
+                    const int tap = 16 * wv + r;
+                    const float *wth = W1 + (tap >> 3) * W1ROW + 8 * grp;
+                    const float *wph = W1 + (8 + (tap & 7)) * W1ROW + 8 * grp;
+                    half8 ah[2], al[2];
+    #pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+    #pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const float w = wth[32 * kh + q] * wph[32 * kh + q] * 16384.f;
+                            const _Float16 h = (_Float16)w;
+                            ah[kh][q] = h;
+                            al[kh][q] = (_Float16)(w - (float)h);
+                        }
+                    const float osc = osc_sh;
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        floatx4 t = floatx4{0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+                        for (int kh = 0; kh < 2; ++kh) {
+                            const half8 bh = Bhi[(kh * CT + ct) * 64 + lane], bl = Blo[(kh * CT + ct) * 64 + lane];
+                            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kh], bh, t, 0, 0, 0);
+                            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bl, t, 0, 0, 0);
+                            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kh], bh, t, 0, 0, 0);
+                        }
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[ct][v] = fmaf(t[v], osc, acc[ct][v]);
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
-        }
-        // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int t = 16 * wv + 4 * grp + v;
-            if constexpr (DET) {
-                // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
-                float *dst = pg + ((size_t)it * 64 + t) * NC;
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
-            } else {
-                float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                    const int c = 16 * ct + r;
-                    if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+            // D[i][j] in lane j + 16 (i/4), register i%4: tap 16 wv + 4 grp + v, component 16 ct + r
+    #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = 16 * wv + 4 * grp + v;
+                if constexpr (DET) {
+                    // the item's patch gradient, summed per pixel in a fixed order by k_scatter_reduce
+                    float *dst = pg + ((size_t)it * 64 + t) * NC;
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) dst[16 * ct + r] = acc[ct][v];
+                } else {
+                    float *base = gmaps + ((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp;
+    #pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        const int c = 16 * ct + r;
+                        if (c < ncomp && c != 1) atomic_add(base + c, acc[ct][v]);  // basis_1 = sin 0 = 0
+                    }
                 }
             }
         }
