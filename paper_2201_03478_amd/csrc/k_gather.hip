@@ -15,12 +15,14 @@
 #include "sc_common.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-#ifndef GATHER_RUN_DIV
-#define GATHER_RUN_DIV 64
-#endif
-#ifndef GATHER_SLIDE
-#define GATHER_SLIDE true
-#endif
+
+namespace {
+// Work-queue runs: with more than GATHER_RUN_DIV items per workgroup the persistent
+// gather takes up to 32 consecutive items per queue atomic; GATHER_SLIDE enables the
+// reuse of the staged block between consecutive items of a run (split form).
+constexpr int GATHER_RUN_DIV = 64;
+constexpr bool GATHER_SLIDE = true;
+}  // namespace
 
 namespace {
 
