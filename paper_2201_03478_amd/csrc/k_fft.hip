@@ -90,6 +90,12 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
     const int n2 = P2.n, nos = Pos.n;
     BT *B = (BT *)sbuf;                         // length nos; the forward transform runs in B[0 .. n2)
     double2 *T2 = (double2 *)(B + nos);  // LDS twiddle bases (TWL): forward, then inverse (nos is even)
+    // With a complex64 buffer of nos >= 2 n2 points the forward transform still fits
+    // in complex128 (the same bytes): it runs without conversions, and only the
+    // deconvolved spectrum is stored in complex64 for the inverse transform.
+    using FT2 = typename std::conditional<(TWL && sizeof(BT) == sizeof(float2) &&
+                                           FftLen<SOS>::value >= 2 * FftLen<S2>::value), double2, BT>::type;
+    FT2 *Bf = (FT2 *)sbuf;
     double2 *Tos = T2;
     if constexpr (TWL) {
         Tos = T2 + Fwd::ntw;
@@ -102,12 +108,12 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
     for (int j = tid; j < nring; j += nth) {
         const double2 a = ld2(col + j);
         const double2 b = two ? ld2(col + nring + j) : make_double2(0.0, 0.0);
-        st2(B + j, make_double2(a.x - b.y, a.y + b.x));                         // a + i b
-        st2(B + n2 - 1 - j, make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x)));  // s1 (a - i b)
+        st2(Bf + j, make_double2(a.x - b.y, a.y + b.x));                         // a + i b
+        st2(Bf + n2 - 1 - j, make_double2(s1 * (a.x + b.y), s1 * (a.y - b.x)));  // s1 (a - i b)
     }
     __syncthreads();
     if constexpr (TWL)
-        Fwd::run_l(B, T2, tid);
+        Fwd::run_l(Bf, T2, tid);
     else
         Fwd::run((double2 *)B, P2, tw2, tid, nth);
 
@@ -126,7 +132,7 @@ k_theta_upsample(const FT *__restrict__ F, GT *__restrict__ G, int lmax, int nri
         if (t < nm) {
             const int n = t - lmax;
             const double2 p = phase[t];
-            const double2 hp = ld2(B + (n < 0 ? n + n2 : n)), hm = ld2(B + (n > 0 ? n2 - n : -n));
+            const double2 hp = ld2(Bf + (n < 0 ? n + n2 : n)), hm = ld2(Bf + (n > 0 ? n2 - n : -n));
             const double2 u = cmul(p, hp), v = cmul(cconj(p), hm);
             xs[i] = make_double2(ca * u.x + cb * v.x, ca * u.y + cb * v.y);
         }
