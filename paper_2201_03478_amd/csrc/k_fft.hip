@@ -220,7 +220,8 @@ __device__ __forceinline__ void phi_scatter(BT *A, const GT (&spec)[MAXC], int t
 // transforms run one after the other in one LDS buffer: the second k's spectrum is
 // loaded into registers while the first is transformed, and the first k's columns
 // wait in registers, so each lane writes both k's component pairs of a column as
-// one 16-byte store (a column's map record is contiguous in k).
+// one 16-byte store; with the column-tiled FP32 maps the workgroup's stores of
+// eight consecutive columns fill one 128-byte line.
 template <typename T, int NT, int PT, typename SP, int KP, typename GT>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(FftLen<SP>::value > 0 && sizeof(GT) == sizeof(float2) && NT <= 256 ? 5 : 4)))
@@ -248,7 +249,6 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
     constexpr int MAXS = NP > 0 ? (NP + 15 + NT - 1) / NT : PT + 1;  // cols <= np + 15 <= NT MAXS
     const int q0 = -W / 2 + 1;
     const GT *src = G + ((size_t)k0 * rows + row) * gst;
-    T *dst = maps + (size_t)row * cols * ncp + 2 * k0;
     GT spec[MAXC];  // complex64 spectra stay complex64 in registers until they are scattered
     phi_load<NT, MAXC>(spec, src, tid, nm);
     phi_scatter<NT, MAXC>(A, spec, tid, lmax, np);
@@ -286,7 +286,7 @@ k_phi_synthesis(const GT *__restrict__ G, T *__restrict__ maps, int lmax, int ro
             int q = col + q0;
             q = q < 0 ? q + np : (q >= np ? q - np : q);
             const double2 v = phi_pair(ld2(A + q), k);
-            T *o = dst + (size_t)col * ncp;
+            T *o = maps + sc_map_off<T>(row, col, 2 * k0, cols, ncp);
             if (two)
                 store_quad<T>(o, stage[KP == 2 ? i : 0][0], stage[KP == 2 ? i : 0][1], (T)v.x, (T)v.y);
             else
@@ -506,6 +506,19 @@ static hipError_t phi_syn(sc_plan *p) {
     return hipGetLastError();
 }
 
+namespace {
+// FP32 maps from their column-tiled storage into (row, column, component) order.
+__global__ void k_maps_rowmajor(const float *__restrict__ maps, float *__restrict__ dst, int rows, int cols, int ncp) {
+    const int64_t n4 = (int64_t)rows * cols * (ncp >> 2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        const int q4 = (int)(i % (ncp >> 2));
+        const int64_t rc = i / (ncp >> 2);
+        const int r = (int)(rc / cols), c = (int)(rc - (int64_t)r * cols);
+        ((float4 *)dst)[i] = *(const float4 *)(maps + sc_map_off<float>(r, c, 4 * q4, cols, ncp));
+    }
+}
+}  // namespace
+
 template <typename T, int NT, int PT>
 static hipError_t phi_adj(sc_plan *p, const void *gmaps) {
     const int nblk = (p->kmax + 1) * p->rows;
@@ -573,6 +586,13 @@ static hipError_t phi_adj_any(sc_plan *p, const void *gmaps) {
         case 1: return phi_adj<T, SC_FFT_NT_BIG, SC_FFT_PT>(p, gmaps);
         default: return phi_adj<T, SC_FFT_NT_HUGE, SC_FFT_PT_HUGE>(p, gmaps);
     }
+}
+
+hipError_t sc_launch_maps_rowmajor(sc_plan *p, float *dst) {
+    if (p->prec == SC_FP64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_maps_rowmajor, dim3(2048), dim3(256), 0, p->stream, (const float *)p->maps, dst, p->rows,
+                       p->cols, p->ncp);
+    return hipGetLastError();
 }
 
 hipError_t sc_launch_phi_adjoint(sc_plan *p, const void *gmaps) {

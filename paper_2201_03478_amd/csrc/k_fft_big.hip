@@ -149,7 +149,6 @@ k_phi_synthesis_big(const double2 *__restrict__ G, T *__restrict__ maps, int lma
         return zero;
     };
     const int q0 = -W / 2 + 1;
-    T *dst = maps + (size_t)row * cols * ncp + 2 * k;
     for (int s = 0; s < P; ++s) {
         split_pass<1>(sbuf, Q, tw, P, s, nphi, gin, tid);
         for (int qq = tid; qq < Q.n; qq += BNT) {
@@ -157,7 +156,7 @@ k_phi_synthesis_big(const double2 *__restrict__ G, T *__restrict__ maps, int lma
             const double2 v = comp_pair(sbuf[qq], k);
             // column q - q0 and the wrap copies q - q0 -+ nphi inside [0, cols)
             for (int c = q - q0 - nphi; c < cols; c += nphi)
-                if (c >= 0) put_pair<T>(dst + (size_t)c * ncp, v);
+                if (c >= 0) put_pair<T>(maps + sc_map_off<T>(row, c, 2 * k, cols, ncp), v);
         }
         __syncthreads();
     }

@@ -66,11 +66,10 @@ k_gather_v1(const double *__restrict__ ptg, int64_t n, const T *__restrict__ map
             const T wi = __shfl(w, i);
             for (int j = 0; j < W; ++j) {
                 const T wij = wi * __shfl(w, W + j);
-                const T *base = maps + ((size_t)(row0 + i) * cols + (col0 + j)) * ncp;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int c = lane + 64 * t;
-                    if (c < ncomp) acc[t] += wij * base[c];
+                    if (c < ncomp) acc[t] += wij * maps[sc_map_off<T>(row0 + i, col0 + j, c, cols, ncp)];
                 }
             }
         }
@@ -143,7 +142,7 @@ k_gather_binned(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
         for (int e = tid; e < 64 * NC; e += 256) {
             const int t = e / NC, c = e - t * NC;
             T v = (T)0;
-            if (c < ncp) v = maps[((size_t)(row0 + (t >> 3)) * cols + (col0 + (t & 7))) * ncp + c];
+            if (c < ncp) v = maps[sc_map_off<T>(row0 + (t >> 3), col0 + (t & 7), c, cols, ncp)];
             Psh[e] = v;
         }
         for (int ch = 0; ch < item.z; ch += 64) {
@@ -380,14 +379,12 @@ __device__ __forceinline__ void gather_mfma_item(const GatherDet &D, const int4 
         }
     }
     {
-        // tap t = 8 i + j is map row row0 + i, column col0 + j: NC contiguous floats
-        const float4 *src = (const float4 *)(D.maps + ((size_t)row0 * D.cols + col0) * NC);
-        const size_t rstride = (size_t)D.cols * NC / 4;
-        const int n4 = NC / 4;
+        // tap t = 8 i + j is map row row0 + i, column col0 + j: NC / 4 groups of four components
+        const int n4 = NC / 4, ntile = sc_map_ntile(D.cols);
         for (int t = wv; t < 64; t += NWV) {
-            const float4 *s4 = src + (t >> 3) * rstride + (t & 7) * n4;
             float4 *d4 = (float4 *)(Psh + t * NCS);
-            for (int q = lane; q < n4; q += 64) d4[q] = s4[q];
+            for (int q = lane; q < n4; q += 64)
+                d4[q] = *(const float4 *)(D.maps + sc_tile_off(row0 + (t >> 3), col0 + (t & 7), q, ntile, n4));
         }
     }
     for (int ch = 0; ch < item.z; ch += GCH) {
@@ -569,6 +566,12 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, grp = lane >> 4;
     const int row0 = item.x / D.nkc, col0 = item.x - (item.x / D.nkc) * D.nkc;
+    // column col0 + jj of a (row, four-component group): the group's run in col0's tile,
+    // then (col0 mod 8 + jj >= 8) the same group in the next tile, 32 (NC4 - 1) floats on
+    const int ntile = sc_map_ntile(D.cols), cm8 = col0 & 7;
+    auto col_at = [&](const float *b0, int jj) -> const floatx4 * {
+        return (const floatx4 *)(b0 + 4 * jj + (cm8 + jj >= 8 ? 32 * (NC4 - 1) : 0));
+    };
     const int sw = tid & (GCH - 1);
     double pf_u = 0.0, pf_v = 0.0, pf_psi = 0.0;
     int pf_idx = -1;
@@ -608,7 +611,7 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
                 nv[k] = floatx4{0.f, 0.f, 0.f, 0.f};
                 if (u < NU1) {
                     const int i = u / NC4, c4 = u - i * NC4;
-                    nv[k] = ((const floatx4 *)(D.maps + ((size_t)(row0 + i) * D.cols + col0 + 7) * NC))[c4];
+                    nv[k] = *col_at(D.maps + sc_tile_off(row0 + i, col0, c4, ntile, NC4), 7);
                 }
                 m = fmaxf(m, fmaxf(fmaxf(fabsf(nv[k][0]), fabsf(nv[k][1])), fmaxf(fabsf(nv[k][2]), fabsf(nv[k][3]))));
             }
@@ -662,10 +665,10 @@ __device__ __forceinline__ void gather_split_item(const GatherDet &D, const int4
             for (int j = 0; j < 8; ++j) v[k][j] = floatx4{0.f, 0.f, 0.f, 0.f};
             if (u < NU) {
                 const int i = u / NC4, c4 = u - i * NC4;
-                const floatx4 *s4 = (const floatx4 *)(D.maps + ((size_t)(row0 + i) * D.cols + col0) * NC) + c4;
+                const float *b0 = D.maps + sc_tile_off(row0 + i, col0, c4, ntile, NC4);
                 // slot j holds map column col0 + ((j - col0) mod 8)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[k][j] = s4[((j - c7) & 7) * NC4];
+                for (int j = 0; j < 8; ++j) v[k][j] = *col_at(b0, (j - c7) & 7);
             }
             if (!track) {
 #pragma unroll

@@ -36,19 +36,23 @@ constexpr int PSI_SLACK = 512;  // zeroed bytes after the cube (reached by the l
 // among the NTS lanes of its transform): (M_2k, M_2k+1) of pixel a, then of pixel b (zero past
 // kmax and for a missing b).  Two orders per lane suffice: kmax + 1 <= npsi / 4 <= 2 NTS.
 template <typename T, int NTS>
-__device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t pair, int64_t npix, int ncp, int kmax,
-                                           int tg, T (&r)[8]) {
+__device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t pair, int64_t npix, int cols, int ncp,
+                                           int kmax, int tg, T (&r)[8]) {
     const int64_t a = 2 * pair;
     const bool hb = a + 1 < npix;
-    const T *ma = maps + a * ncp, *mb = ma + (hb ? ncp : 0);
+    const int64_t b = hb ? a + 1 : a;  // pixels are (row, column) in row-major order
+    const int ra = (int)(a / cols), ca = (int)(a - (int64_t)ra * cols);
+    const int rb = (int)(b / cols), cb = (int)(b - (int64_t)rb * cols);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int k = tg + NTS * h;
         const bool ok = k <= kmax;
-        r[4 * h] = ok ? ma[2 * k] : (T)0;
-        r[4 * h + 1] = ok ? ma[2 * k + 1] : (T)0;
-        r[4 * h + 2] = ok && hb ? mb[2 * k] : (T)0;
-        r[4 * h + 3] = ok && hb ? mb[2 * k + 1] : (T)0;
+        const size_t oa = sc_map_off<T>(ra, ca, ok ? 2 * k : 0, cols, ncp);
+        const size_t ob = sc_map_off<T>(rb, cb, ok ? 2 * k : 0, cols, ncp);
+        r[4 * h] = ok ? maps[oa] : (T)0;
+        r[4 * h + 1] = ok ? maps[oa + 1] : (T)0;
+        r[4 * h + 2] = ok && hb ? maps[ob] : (T)0;
+        r[4 * h + 3] = ok && hb ? maps[ob + 1] : (T)0;
     }
 }
 
@@ -62,7 +66,7 @@ __device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t p
 // one without a pair in the last iteration transforms stale values and stores nothing.
 template <typename T, typename S, int G>
 __global__ void __launch_bounds__(2 * PSI_NT)
-k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int ncp, int kmax, int npsi, int npst,
+k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int cols, int ncp, int kmax, int npsi, int npst,
            int W, FftPlan P, const double2 *__restrict__ tw, const double *__restrict__ gpsi) {
     constexpr int NTS = PSI_NT / G;   // lanes per transform
     constexpr int PTS = PSI_PT * G;   // points per lane: NTS PTS = 512
@@ -89,14 +93,14 @@ k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int n
     T nxt[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) nxt[e] = (T)0;
-    if ((2 * it + wv) * G + g < npairs) fetch_pair<T, NTS>(maps, (2 * it + wv) * G + g, npix, ncp, kmax, tg, nxt);
+    if ((2 * it + wv) * G + g < npairs) fetch_pair<T, NTS>(maps, (2 * it + wv) * G + g, npix, cols, ncp, kmax, tg, nxt);
     for (; 2 * it * G < npairs; it += gridDim.x) {
         const int64_t pair = (2 * it + wv) * G + g;
         T cur[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
         const int64_t pn = (2 * (it + gridDim.x) + wv) * G + g;
-        if (pn < npairs) fetch_pair<T, NTS>(maps, pn, npix, ncp, kmax, tg, nxt);
+        if (pn < npairs) fetch_pair<T, NTS>(maps, pn, npix, cols, ncp, kmax, tg, nxt);
         for (int t = tg; t < npsi; t += NTS)
             if (t > kmax && t < npsi - kmax) buf[t] = make_double2(0.0, 0.0);
 #pragma unroll
@@ -289,7 +293,7 @@ void launch_psi_cube(sc_plan *p, int64_t npix) {
     const int64_t iters = ((npix + 1) / 2 + 2 * G - 1) / (2 * G);  // 2 G pixel pairs per workgroup iteration
     const unsigned nblk = (unsigned)(iters < 16384 ? iters : 16384);
     hipLaunchKernelGGL((k_psi_cube<T, S, G>), dim3(nblk), dim3(2 * PSI_NT), 0, p->stream, (const T *)p->maps,
-                       (T *)p->cube, npix, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi, p->gpsi);
+                       (T *)p->cube, npix, p->cols, p->ncp, p->kmax, p->npsi, p->npst, p->W, p->ppsi, p->twpsi, p->gpsi);
 }
 
 template <typename T>

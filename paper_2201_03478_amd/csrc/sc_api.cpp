@@ -451,7 +451,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     int rc = SC_OK;
     rc = rc ? rc : alloc((void **)&p->F, sizeof(double2) * (kmax + 1) * nm * p->nring, &tot);
     rc = rc ? rc : alloc((void **)&p->G, sizeof(double2) * (kmax + 1) * (size_t)p->rows * nm, &tot);
-    rc = rc ? rc : alloc(&p->maps, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, &tot);
+    rc = rc ? rc : alloc(&p->maps, sc_map_bytes(p), &tot);
     rc = rc ? rc : alloc((void **)&p->rroot, sizeof(double2) * (size_t)(lmax + 1) * (lmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_m, sizeof(double) * (lmax + 1) * (kmax + 1), &tot);
     rc = rc ? rc : alloc((void **)&p->sbin_e, sizeof(int) * (lmax + 1) * (kmax + 1), &tot);
@@ -485,7 +485,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     }
     p->ws_bytes = tot;
     // padding components stay zero for the plan's lifetime
-    hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp, p->stream);
+    hipError_t e = hipMemsetAsync(p->maps, 0, sc_map_bytes(p), p->stream);
     if (e == hipSuccess) e = sc_launch_tables(p);
     if (e == hipSuccess && p->ctab)
         e = hipMemcpyAsync(p->ctab_off, coff.data(), sizeof(long long) * coff.size(), hipMemcpyHostToDevice,
@@ -1109,6 +1109,13 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
     } else if (which == 1) {
         src = p->maps;
         bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
+        if (p->prec != SC_FP64) {  // column-tiled storage: reordered into (row, column, component)
+            if ((int64_t)bytes > capacity)
+                return fail(SC_EINVAL, "destination holds %lld bytes, need %zu", (long long)capacity, bytes);
+            hipError_t e = sc_launch_maps_rowmajor(p, (float *)dst);
+            if (e != hipSuccess) return hip_fail(e, "stage copy");
+            return (int64_t)bytes;
+        }
     } else if (which == 2) {
         // the index field of each 32-byte sample record
         if (!p->bw.sorted.rec) return fail(SC_ESTATE, "no binning pass has run on this plan");

@@ -131,7 +131,7 @@ struct sc_plan {
     // device buffers
     double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums (float2 with mid32)
     double2 *G;        // [kmax+1][rows][gst] theta-upsampled, deconvolved (float2 with mid32)
-    void *maps;        // [rows][cols][ncp] float or double
+    void *maps;        // FP64: [rows][cols][ncp]; FP32: column-tiled (sc_map_off)
     double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
     double4 *ctab;     // recursion coefficients (a, b, bn, S_l) of every (m, k, l), l >= max(m, k) (or null)
     long long *ctab_off;  // [lmax+1][kmax+1] first entry of each column
@@ -147,7 +147,7 @@ struct sc_plan {
     int have_maps;
     size_t ws_bytes;
     BinWork bw;        // stream-ordered allocations (hipMallocAsync / hipFreeAsync on the plan's stream)
-    void *gmaps;       // adjoint: gradient maps, same layout as maps (allocated on first use)
+    void *gmaps;       // adjoint: gradient maps, [rows][cols][ncp] in both precisions (allocated on first use)
     double2 *GA;       // adjoint: per-k gradient contributions [kmax+1][n_alm]
     double2 *GB;       // beam adjoint: per-m gradient contributions [lmax+1][n_blm] (allocated on first use)
     size_t adj_bytes;
@@ -189,8 +189,34 @@ struct TimedLaunch {
 
 static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_FP64 ? 8 : 4; }
 
+// Storage order of the component maps.  FP64 maps hold one record of ncp values
+// per (row, column).  FP32 maps are column-tiled: value (row r, column c,
+// component q) sits at ((r ntile + c / 8) (ncp / 4) + q / 4) 32 + (c mod 8) 4 +
+// q mod 4, ntile = ceil(cols / 8), so the four values of one k pair (components
+// 4g .. 4g + 3) at eight consecutive columns are 128 contiguous bytes: the phi
+// synthesis of a k pair writes whole lines, and the gather reads a pair's 8 x 8
+// block as eight 128-byte runs.  ncp is a multiple of 16 for FP32 maps.
+__host__ __device__ __forceinline__ int sc_map_ntile(int cols) { return (cols + 7) >> 3; }
+__device__ __forceinline__ size_t sc_tile_off(int r, int c, int q4, int ntile, int ng) {
+    return ((((size_t)r * ntile + (c >> 3)) * ng + q4) << 5) + ((c & 7) << 2);
+}
+template <typename T>
+__device__ __forceinline__ size_t sc_map_off(int r, int c, int q, int cols, int ncp) {
+    if constexpr (sizeof(T) == 4)
+        return sc_tile_off(r, c, q >> 2, sc_map_ntile(cols), ncp >> 2) + (q & 3);
+    else
+        return ((size_t)r * cols + c) * ncp + q;
+}
+// bytes of the plan's map buffer (FP32: whole tiles of eight columns)
+static inline size_t sc_map_bytes(const sc_plan *p) {
+    const size_t c = p->prec == SC_FP64 ? (size_t)p->cols : 8 * (size_t)sc_map_ntile(p->cols);
+    return sc_map_elem_bytes(p) * (size_t)p->rows * c * p->ncp;
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t sc_launch_tables(sc_plan *p);
+// FP32 maps in (row, column, component) order into dst (rows x cols x ncp floats)
+hipError_t sc_launch_maps_rowmajor(sc_plan *p, float *dst);
 hipError_t sc_launch_psi_tables(sc_plan *p);
 hipError_t sc_launch_psi_cube(sc_plan *p);
 hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod);
