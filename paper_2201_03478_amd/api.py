@@ -230,7 +230,7 @@ class Plan:
 
     def debug_stage(self, which: int, n: int = 0) -> torch.Tensor:
         """Copy of an internal stage: 0 = ring sums F (complex128 [kmax+1, 2 lmax+1, n_rings]),
-        1 = the stored component maps ([map_rows, map_cols, n_comp_padded]),
+        1 = the component maps in (row, column, component) order ([map_rows, map_cols, n_comp_padded]),
         2 = the anchor-grouped sample order of the last binning pass (int32 [n], n its samples)."""
         inf = self.info()
         dev = torch.device("cuda", torch.cuda.current_device())

@@ -40,9 +40,10 @@ __device__ __forceinline__ void fetch_pair(const T *__restrict__ maps, int64_t p
                                            int kmax, int tg, T (&r)[8]) {
     const int64_t a = 2 * pair;
     const bool hb = a + 1 < npix;
-    const int64_t b = hb ? a + 1 : a;  // pixels are (row, column) in row-major order
-    const int ra = (int)(a / cols), ca = (int)(a - (int64_t)ra * cols);
-    const int rb = (int)(b / cols), cb = (int)(b - (int64_t)rb * cols);
+    // pixels are (row, column) in row-major order; rows x cols < 2^31 up to lmax 8192
+    const unsigned ua = (unsigned)a, ub = hb ? ua + 1u : ua, uc = (unsigned)cols;
+    const int ra = (int)(ua / uc), ca = (int)(ua - (unsigned)ra * uc);
+    const int rb = (int)(ub / uc), cb = (int)(ub - (unsigned)rb * uc);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int k = tg + NTS * h;
@@ -89,7 +90,9 @@ k_psi_cube(const T *__restrict__ maps, T *__restrict__ cube, int64_t npix, int c
         const int k = tg + NTS * h;
         gk[h] = k > kmax ? 0.0 : (k == 0 ? gpsi[0] : 0.5 * gpsi[k]);
     }
-    int64_t it = blockIdx.x;
+    // consecutive pairs share the 128-byte lines of the column-tiled maps: the workgroups
+    // that take them start on one XCD (xcd_remap is a permutation of the block indices)
+    int64_t it = xcd_remap(blockIdx.x, gridDim.x);
     T nxt[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) nxt[e] = (T)0;
