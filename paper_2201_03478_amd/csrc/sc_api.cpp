@@ -417,8 +417,9 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     // component pairs: (2k, 2k + 1) hold the cos k psi and sin k psi maps; the
     // sin 0 psi slot (component 1) is zero, so each phi column stores one pair.
     p->ncomp = 2 * kmax + 2;
-    // FP32 maps: components padded to the 16-wide tiles of the matrix-core gather,
-    // so an 8 x 8 block of the map is 8 contiguous runs; FP64 maps: to 4.
+    // FP32 maps: components padded to the 16-wide tiles of the matrix-core gather
+    // (and a whole number of four-component groups of the column-tiled storage);
+    // FP64 maps: to 4.
     p->ncp = precision == SC_FP64 ? (p->ncomp + 3) & ~3 : (p->ncomp + 15) & ~15;
     p->nq = 128;
     p->alm_lmax = lmax;
