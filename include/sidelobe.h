@@ -283,7 +283,7 @@ int sc_dipole_response(const double *blm, int lmax, int kmax, const double *ptg,
  * [kmax+1][2 lmax+1][n_rings], F_k(theta_j, m) = sum_l a_lm conj(b_lk) d^l_mk(theta_j),
  * theta_j = (j + 1/2) pi / n_rings); which = 1: the component maps in (row,
  * column, component) order (map_rows x map_cols x n_comp_padded, FP64 or FP32 by
- * precision; FP32 maps are stored column-tiled and reordered by the copy, which is
+ * precision; the maps are stored column-tiled and reordered by the copy, which is
  * enqueued on the plan's stream);
  * which = 2: the sample order of the most recent binning pass (int32, one entry
  * per sample of that pass: the index, within the pass, of the sample at each

@@ -220,8 +220,9 @@ __device__ __forceinline__ void phi_scatter(BT *A, const GT (&spec)[MAXC], int t
 // transforms run one after the other in one LDS buffer: the second k's spectrum is
 // loaded into registers while the first is transformed, and the first k's columns
 // wait in registers, so each lane writes both k's component pairs of a column as
-// one 16-byte store; with the column-tiled FP32 maps the workgroup's stores of
-// eight consecutive columns fill one 128-byte line.
+// one 16-byte store.  In the column-tiled maps (FP32: four components, FP64: the
+// pair of one k per 16-byte group) the workgroup's stores of eight consecutive
+// columns fill one 128-byte line.
 template <typename T, int NT, int PT, typename SP, int KP, typename GT>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(FftLen<SP>::value > 0 && sizeof(GT) == sizeof(float2) && NT <= 256 ? 5 : 4)))
@@ -507,14 +508,18 @@ static hipError_t phi_syn(sc_plan *p) {
 }
 
 namespace {
-// FP32 maps from their column-tiled storage into (row, column, component) order.
-__global__ void k_maps_rowmajor(const float *__restrict__ maps, float *__restrict__ dst, int rows, int cols, int ncp) {
-    const int64_t n4 = (int64_t)rows * cols * (ncp >> 2);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
-        const int q4 = (int)(i % (ncp >> 2));
-        const int64_t rc = i / (ncp >> 2);
+// The maps from their column-tiled storage into (row, column, component) order,
+// one 16-byte group (G = 16 / sizeof(T) components) per thread and step.
+template <typename T>
+__global__ void k_maps_rowmajor(const T *__restrict__ maps, T *__restrict__ dst, int rows, int cols, int ncp) {
+    constexpr int G = 16 / (int)sizeof(T);
+    const int ng = ncp / G;
+    const int64_t n = (int64_t)rows * cols * ng;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(i % ng);
+        const int64_t rc = i / ng;
         const int r = (int)(rc / cols), c = (int)(rc - (int64_t)r * cols);
-        ((float4 *)dst)[i] = *(const float4 *)(maps + sc_map_off<float>(r, c, 4 * q4, cols, ncp));
+        ((uint4 *)dst)[i] = *(const uint4 *)(maps + sc_map_off<T>(r, c, G * g, cols, ncp));
     }
 }
 }  // namespace
@@ -588,10 +593,13 @@ static hipError_t phi_adj_any(sc_plan *p, const void *gmaps) {
     }
 }
 
-hipError_t sc_launch_maps_rowmajor(sc_plan *p, float *dst) {
-    if (p->prec == SC_FP64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_maps_rowmajor, dim3(2048), dim3(256), 0, p->stream, (const float *)p->maps, dst, p->rows,
-                       p->cols, p->ncp);
+hipError_t sc_launch_maps_rowmajor(sc_plan *p, void *dst) {
+    if (p->prec == SC_FP64)
+        hipLaunchKernelGGL(k_maps_rowmajor<double>, dim3(2048), dim3(256), 0, p->stream, (const double *)p->maps,
+                           (double *)dst, p->rows, p->cols, p->ncp);
+    else
+        hipLaunchKernelGGL(k_maps_rowmajor<float>, dim3(2048), dim3(256), 0, p->stream, (const float *)p->maps,
+                           (float *)dst, p->rows, p->cols, p->ncp);
     return hipGetLastError();
 }
 

@@ -112,13 +112,13 @@ k_gather_mfma64(const int4 *__restrict__ items, int *__restrict__ totals, BinSor
                 __syncthreads();  // the previous chunk's reads are done; weights and phases written
                 const int cbase = cc * NCC;
                 // stage the chunk: taps t of the W x W block, components cbase .. cbase + NCC - 1
-                // (zero past ncomp), as 16-byte runs (ncp and cbase are multiples of 4)
+                // (zero past ncomp), as 16-byte pairs (one group of the tiled maps; c is even)
 #pragma unroll 4
                 for (int e = tid; e < NT * (NCC / 2); e += 256) {
                     const int t = e / (NCC / 2), c2 = e - t * (NCC / 2);
                     const int c = cbase + 2 * c2;
                     const int i = t / W, j = t - (t / W) * W;
-                    const double *src = maps + ((size_t)(row0 + i) * cols + (col0 + j)) * ncp + c;
+                    const double *src = maps + sc_map_off<double>(row0 + i, col0 + j, c, cols, ncp);
                     double2 v = make_double2(0.0, 0.0);
                     if (c + 1 < ncomp)
                         v = *(const double2 *)src;

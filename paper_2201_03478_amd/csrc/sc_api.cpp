@@ -419,7 +419,7 @@ int sc_plan_create(sc_plan **out, int lmax, int kmax, int precision, int kernel_
     p->ncomp = 2 * kmax + 2;
     // FP32 maps: components padded to the 16-wide tiles of the matrix-core gather
     // (and a whole number of four-component groups of the column-tiled storage);
-    // FP64 maps: to 4.
+    // FP64 maps: to 4 (whole two-component groups).
     p->ncp = precision == SC_FP64 ? (p->ncomp + 3) & ~3 : (p->ncomp + 15) & ~15;
     p->nq = 128;
     p->alm_lmax = lmax;
@@ -1108,15 +1108,13 @@ int64_t sc_debug_copy_stage(sc_plan *p, int which, void *dst, int64_t capacity) 
             return (int64_t)bytes;
         }
     } else if (which == 1) {
-        src = p->maps;
         bytes = sc_map_elem_bytes(p) * (size_t)p->rows * p->cols * p->ncp;
-        if (p->prec != SC_FP64) {  // column-tiled storage: reordered into (row, column, component)
-            if ((int64_t)bytes > capacity)
-                return fail(SC_EINVAL, "destination holds %lld bytes, need %zu", (long long)capacity, bytes);
-            hipError_t e = sc_launch_maps_rowmajor(p, (float *)dst);
-            if (e != hipSuccess) return hip_fail(e, "stage copy");
-            return (int64_t)bytes;
-        }
+        // column-tiled storage: reordered into (row, column, component)
+        if ((int64_t)bytes > capacity)
+            return fail(SC_EINVAL, "destination holds %lld bytes, need %zu", (long long)capacity, bytes);
+        hipError_t e = sc_launch_maps_rowmajor(p, dst);
+        if (e != hipSuccess) return hip_fail(e, "stage copy");
+        return (int64_t)bytes;
     } else if (which == 2) {
         // the index field of each 32-byte sample record
         if (!p->bw.sorted.rec) return fail(SC_ESTATE, "no binning pass has run on this plan");

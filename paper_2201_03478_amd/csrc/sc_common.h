@@ -131,7 +131,7 @@ struct sc_plan {
     // device buffers
     double2 *F;        // [kmax+1][2 lmax+1][nring] ring sums (float2 with mid32)
     double2 *G;        // [kmax+1][rows][gst] theta-upsampled, deconvolved (float2 with mid32)
-    void *maps;        // FP64: [rows][cols][ncp]; FP32: column-tiled (sc_map_off)
+    void *maps;        // column-tiled, float or double (sc_map_off)
     double2 *rroot;    // [lmax+1][lmax+1] at [x][l]: (sqrt((l+1)^2 - x^2), its reciprocal), 0 if l < x
     double4 *ctab;     // recursion coefficients (a, b, bn, S_l) of every (m, k, l), l >= max(m, k) (or null)
     long long *ctab_off;  // [lmax+1][kmax+1] first entry of each column
@@ -189,34 +189,35 @@ struct TimedLaunch {
 
 static inline size_t sc_map_elem_bytes(const sc_plan *p) { return p->prec == SC_FP64 ? 8 : 4; }
 
-// Storage order of the component maps.  FP64 maps hold one record of ncp values
-// per (row, column).  FP32 maps are column-tiled: value (row r, column c,
-// component q) sits at ((r ntile + c / 8) (ncp / 4) + q / 4) 32 + (c mod 8) 4 +
-// q mod 4, ntile = ceil(cols / 8), so the four values of one k pair (components
-// 4g .. 4g + 3) at eight consecutive columns are 128 contiguous bytes: the phi
-// synthesis of a k pair writes whole lines, and the gather reads a pair's 8 x 8
-// block as eight 128-byte runs.  ncp is a multiple of 16 for FP32 maps.
+// Storage order of the component maps: column-tiled in groups of 16 bytes of
+// components (G = 4 floats or 2 doubles).  Value (row r, column c, component q)
+// sits at ((r ntile + c / 8) (ncp / G) + q / G) 8 G + (c mod 8) G + q mod G,
+// ntile = ceil(cols / 8): a group's values at eight consecutive columns are 128
+// contiguous bytes (for FP32 maps the four values of one k pair, components 4g ..
+// 4g + 3; for FP64 maps the cos/sin pair of one k), so the phi synthesis of a k
+// group writes whole lines, and the gather reads a group's 8 x 8 block as eight
+// 128-byte runs.  ncp is a multiple of 16 for FP32 maps and of 4 for FP64 maps.
 __host__ __device__ __forceinline__ int sc_map_ntile(int cols) { return (cols + 7) >> 3; }
+// FP32 maps, in floats: q4 = q / 4, ng = ncp / 4
 __device__ __forceinline__ size_t sc_tile_off(int r, int c, int q4, int ntile, int ng) {
     return ((((size_t)r * ntile + (c >> 3)) * ng + q4) << 5) + ((c & 7) << 2);
 }
 template <typename T>
 __device__ __forceinline__ size_t sc_map_off(int r, int c, int q, int cols, int ncp) {
-    if constexpr (sizeof(T) == 4)
-        return sc_tile_off(r, c, q >> 2, sc_map_ntile(cols), ncp >> 2) + (q & 3);
-    else
-        return ((size_t)r * cols + c) * ncp + q;
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "float or double maps");
+    constexpr int LG = sizeof(T) == 4 ? 2 : 1;  // log2 of the group size G
+    return ((((size_t)r * sc_map_ntile(cols) + (c >> 3)) * (size_t)(ncp >> LG) + (q >> LG)) << (LG + 3)) +
+           ((c & 7) << LG) + (q & ((1 << LG) - 1));
 }
 // bytes of the plan's map buffer (FP32: whole tiles of eight columns)
 static inline size_t sc_map_bytes(const sc_plan *p) {
-    const size_t c = p->prec == SC_FP64 ? (size_t)p->cols : 8 * (size_t)sc_map_ntile(p->cols);
-    return sc_map_elem_bytes(p) * (size_t)p->rows * c * p->ncp;
+    return sc_map_elem_bytes(p) * (size_t)p->rows * (8 * (size_t)sc_map_ntile(p->cols)) * p->ncp;
 }
 
 // ---------------------------------------------------------------- launchers
 hipError_t sc_launch_tables(sc_plan *p);
-// FP32 maps in (row, column, component) order into dst (rows x cols x ncp floats)
-hipError_t sc_launch_maps_rowmajor(sc_plan *p, float *dst);
+// the maps in (row, column, component) order into dst (rows x cols x ncp values)
+hipError_t sc_launch_maps_rowmajor(sc_plan *p, void *dst);
 hipError_t sc_launch_psi_tables(sc_plan *p);
 hipError_t sc_launch_psi_cube(sc_plan *p);
 hipError_t sc_launch_gather_psi(sc_plan *p, const double *ptg, int64_t n, void *tod);
